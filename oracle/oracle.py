@@ -1,0 +1,250 @@
+"""ctypes/numpy front end of the CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It loads ``oracle/liboracle.so`` (plain C,
+built by ``oracle/build.py``) and shares no code with the GPU library.
+
+Axis order is (x, y, z) in every per-axis argument; numpy arrays are C-ordered
+(N_z, N_y, N_x), x fastest.  Definitions follow arXiv:1910.08535: Section 2 for
+the basis and the row sums, Section 3 for the tensor product, Section 4.1 for the
+generation loops, Section 4.2 for the explicit step.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
+MAT_GAL_MASS, MAT_GAL_LAP, MAT_GAL_BYPARTS, MAT_PG_MASS, MAT_PG_LAP = 0, 1, 2, 3, 4
+
+_PL = C.POINTER(C.c_long)
+_PD = C.POINTER(C.c_double)
+
+
+class _Problem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("p", C.c_int), ("ne", C.c_long * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("nq", C.c_int * 3),
+                ("nspan", C.c_long * 3), ("span_first", _PL * 3), ("span_last", _PL * 3)]
+
+
+class _Source(C.Structure):
+    _fields_ = [("table", _PD), ("sin_amp", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b  # type: ignore
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        L.or_gauss_legendre.argtypes = [C.c_int, _PD, _PD]
+        L.or_basis_eval.argtypes = [C.c_int, C.c_long, C.c_double, C.c_double, C.c_double,
+                                    C.c_int, _PD]
+        L.or_matrix_1d.argtypes = [C.c_int, C.c_long, C.c_double, C.c_double, C.c_int, C.c_int,
+                                   C.c_long, _PL, _PL, _PD]
+        L.or_rhs.argtypes = [C.POINTER(_Problem), C.c_int, _PD, C.c_double, C.c_double,
+                             C.c_double, C.POINTER(_Source), C.c_long, C.c_long, _PD]
+        L.or_explicit_step.argtypes = [C.POINTER(_Problem), _PD, C.c_double,
+                                       C.POINTER(_Source), C.c_int]
+        L.or_num_threads.argtypes = []
+        for fn in (L.or_gauss_legendre, L.or_basis_eval, L.or_matrix_1d, L.or_rhs,
+                   L.or_explicit_step, L.or_num_threads):
+            fn.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_PD)
+
+
+def _lp(a: np.ndarray):
+    return a.ctypes.data_as(_PL)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def gauss_legendre(nq: int) -> Tuple[np.ndarray, np.ndarray]:
+    xi = np.zeros(nq)
+    w = np.zeros(nq)
+    if lib().or_gauss_legendre(nq, _dp(xi), _dp(w)):
+        raise ValueError("bad nq")
+    return xi, w
+
+
+def basis_eval(p: int, ne: int, x: float, lo: float = 0.0, hi: float = 1.0,
+               nder: int = 2) -> np.ndarray:
+    """All N = ne + p B-splines and their derivatives at x, shape (nder+1, N)."""
+    out = np.zeros((nder + 1) * (ne + p))
+    if lib().or_basis_eval(p, ne, lo, hi, float(x), nder, _dp(out)):
+        raise ValueError("bad basis arguments")
+    return out.reshape(nder + 1, ne + p)
+
+
+def spans(kind: str, p: int, ne: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Test spans along one axis (inclusive element ranges).
+
+    ``support``: row r in [0, ne+p) takes S_r = supp B_r = [max(0, r-p), min(ne-1, r)],
+    i.e. every element's integral is added to the p+1 rows of the B-splines
+    that live on it, as in the piece-wise-constant generation loop of Section 4.1.
+    ``element``: row e in [0, ne) takes S_e = {e}, the single-element integrals
+    (the example's rows where p+1 consecutive B-splines sum to one, Section 2).
+    """
+    if kind == "support":
+        r = np.arange(ne + p)
+        return (np.maximum(0, r - p).astype(np.int64), np.minimum(ne - 1, r).astype(np.int64))
+    if kind == "element":
+        r = np.arange(ne, dtype=np.int64)
+        return r.copy(), r.copy()
+    raise ValueError(kind)
+
+
+def matrix_1d(p: int, ne: int, nq: int, kind: int, lo: float = 0.0, hi: float = 1.0,
+              span: Optional[Tuple[np.ndarray, np.ndarray]] = None) -> np.ndarray:
+    N = ne + p
+    if kind in (MAT_PG_MASS, MAT_PG_LAP):
+        if span is None:
+            span = spans("support", p, ne)
+        first = np.ascontiguousarray(span[0], dtype=np.int64)
+        last = np.ascontiguousarray(span[1], dtype=np.int64)
+        nrows = len(first)
+    else:
+        first = last = np.zeros(1, dtype=np.int64)
+        nrows = N
+    out = np.zeros(nrows * N)
+    rc = lib().or_matrix_1d(p, ne, lo, hi, nq, kind, nrows, _lp(first), _lp(last), _dp(out))
+    if rc:
+        raise ValueError(f"or_matrix_1d failed ({rc})")
+    return out.reshape(nrows, N)
+
+
+@dataclass
+class Problem:
+    """A tensor-product B-spline space with its Gauss rule and test spans."""
+    dim: int
+    p: int
+    ne: Sequence[int]
+    nq: Sequence[int]
+    lo: Sequence[float] = (0.0, 0.0, 0.0)
+    hi: Sequence[float] = (1.0, 1.0, 1.0)
+    span_kind: str = "support"
+    custom_spans: Optional[Sequence[Tuple[np.ndarray, np.ndarray]]] = None
+    _spans: list = field(default_factory=list, repr=False)
+
+    def __post_init__(self):
+        self.ne = tuple(int(v) for v in self.ne)[: self.dim]
+        self.nq = tuple(int(v) for v in self.nq)[: self.dim]
+        if self.custom_spans is not None:
+            self._spans = [(np.ascontiguousarray(f, dtype=np.int64),
+                            np.ascontiguousarray(l, dtype=np.int64))
+                           for f, l in self.custom_spans]
+        else:
+            self._spans = [spans(self.span_kind, self.p, n) for n in self.ne]
+
+    @property
+    def nbasis(self) -> Tuple[int, ...]:
+        return tuple(n + self.p for n in self.ne)
+
+    @property
+    def nspan(self) -> Tuple[int, ...]:
+        return tuple(len(s[0]) for s in self._spans)
+
+    def shape(self, form: int) -> Tuple[int, ...]:
+        per_axis = self.nspan if form == PG else self.nbasis
+        return tuple(reversed(per_axis))
+
+    def coef_shape(self) -> Tuple[int, ...]:
+        return tuple(reversed(self.nbasis))
+
+    def gauss_shape(self) -> Tuple[int, ...]:
+        return tuple(reversed([n * q for n, q in zip(self.ne, self.nq)]))
+
+    def _struct(self) -> _Problem:
+        s = _Problem()
+        s.dim = self.dim
+        s.p = self.p
+        for a in range(3):
+            real = a < self.dim
+            s.ne[a] = self.ne[a] if real else 1
+            s.lo[a] = self.lo[a] if real else 0.0
+            s.hi[a] = self.hi[a] if real else 1.0
+            s.nq[a] = self.nq[a] if real else 1
+            if real:
+                f, l = self._spans[a]
+                s.nspan[a] = len(f)
+                s.span_first[a] = _lp(f)
+                s.span_last[a] = _lp(l)
+            else:
+                s.nspan[a] = 1
+        return s
+
+
+def _source(table: Optional[np.ndarray], sin_amp: float):
+    src = _Source()
+    src.table = _dp(table) if table is not None else None
+    src.sin_amp = float(sin_amp)
+    return src
+
+
+def rhs(pb: Problem, form: int, u: Optional[np.ndarray], alpha: float = 0.0, beta: float = 0.0,
+        gamma: float = 0.0, f_table: Optional[np.ndarray] = None, sin_amp: float = 0.0,
+        rows: Optional[Tuple[int, int]] = None) -> np.ndarray:
+    """b = int T_r (alpha u_h + beta Lap u_h + gamma f) for every row r.
+
+    T_r = B_r (Galerkin; the by-parts form integrates the Laplacian term by
+    parts) or the indicator of the span S_r (PG).  ``rows`` restricts the output
+    to a slab [r0, r1) of the outermost axis."""
+    shape = pb.shape(form)
+    if u is not None:
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.shape == pb.coef_shape(), (u.shape, pb.coef_shape())
+    if f_table is not None:
+        f_table = np.ascontiguousarray(f_table, dtype=np.float64)
+        assert f_table.shape == pb.gauss_shape()
+    r0, r1 = (0, shape[0]) if rows is None else rows
+    out = np.zeros((r1 - r0,) + shape[1:])
+    st = pb._struct()
+    src = _source(f_table, sin_amp)
+    rc = lib().or_rhs(C.byref(st), form, _dp(u), alpha, beta, gamma, C.byref(src), r0, r1,
+                      _dp(out))
+    if rc:
+        raise ValueError(f"or_rhs failed ({rc})")
+    return out
+
+
+def explicit_step(pb: Problem, u: np.ndarray, dt: float, f_table: Optional[np.ndarray] = None,
+                  sin_amp: float = 0.0, nsteps: int = 1) -> np.ndarray:
+    """nsteps forward-Euler steps, PG form, lumped left-hand side (returns a copy)."""
+    v = np.array(u, dtype=np.float64, copy=True, order="C")
+    assert v.shape == pb.coef_shape()
+    if f_table is not None:
+        f_table = np.ascontiguousarray(f_table, dtype=np.float64)
+    st = pb._struct()
+    src = _source(f_table, sin_amp)
+    rc = lib().or_explicit_step(C.byref(st), _dp(v), dt, C.byref(src), nsteps)
+    if rc:
+        raise ValueError(f"or_explicit_step failed ({rc})")
+    return v
+
+
+def span_lengths(pb: Problem) -> Tuple[np.ndarray, ...]:
+    """Per-axis knot lengths |S_r| of the test spans (uniform knots)."""
+    out = []
+    for a in range(pb.dim):
+        h = (pb.hi[a] - pb.lo[a]) / pb.ne[a]
+        f, l = pb._spans[a]
+        out.append((l - f + 1) * h)
+    return tuple(out)
