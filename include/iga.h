@@ -1,0 +1,201 @@
+/*
+ * iga.h -- C ABI of the MI355X (gfx950) library for quadrature-based generation of
+ * isogeometric systems and right-hand sides with C^{p-1} tensor-product B-splines
+ * (Paszynski, "Isogeometric analysis with piece-wise constant test functions",
+ * arXiv:1910.08535).
+ *
+ * Forms (Section 1, Section 2):
+ *   IGA_GALERKIN_BYPARTS    test with B_i, Laplacian integrated by parts:
+ *                           row i = int B_i (alpha u + gamma f) - beta int grad B_i . grad u
+ *   IGA_GALERKIN_LAPLACIAN  test with B_i, not integrated by parts:
+ *                           row i = int B_i (alpha u + beta Lap u + gamma f)
+ *   IGA_PG                  Petrov-Galerkin form: the test function of row r is the
+ *                           indicator of a span S_r of trial elements, obtained from
+ *                           the Galerkin rows by summing the rows of the B-splines that
+ *                           are nonzero on the span (partition of unity), so that the
+ *                           test function is never evaluated (Section 2, Section 3):
+ *                           row r = int_{S_r} (alpha u + beta Lap u + gamma f)
+ *   Operator IGA_OP_LAPLACE is +Lap in every form (the caller negates for -Lap u = f,
+ *   Section 4.3).
+ *
+ * Conventions.
+ *   - Axis a in [0, dim): a = 0 is x, a = 1 is y, a = 2 is z.  Axis a has ne[a]
+ *     uniform elements on [lo[a], hi[a]], an open knot vector, and N_a = ne[a] + p
+ *     B-splines (Section 2).  B_j is nonzero on elements max(0,j-p) .. min(ne-1,j).
+ *   - Coefficient arrays u and row arrays b are C-ordered (N_z, N_y, N_x) /
+ *     (R_z, R_y, R_x), x fastest, FP64, contiguous (Section 3 and 4.1 number the
+ *     unknowns with x fastest).  R_a = N_a for Galerkin forms and for PG spans
+ *     IGA_SPANS_SUPPORT; R_a = ne[a] for IGA_SPANS_ELEMENT; R_a = nspan[a] for
+ *     IGA_SPANS_CUSTOM.
+ *   - PG spans (inclusive element ranges [first, last] per row and axis; the tensor
+ *     span is the product of the axis spans):
+ *       IGA_SPANS_SUPPORT  S_r = supp B_r = [max(0,r-p), min(ne-1,r)] -- every element
+ *                          integral is added to the p+1 rows of the B-splines living on
+ *                          it, as in the piece-wise-constant generation loops of
+ *                          Section 4.1 and Section 4.3;
+ *       IGA_SPANS_ELEMENT  S_e = {e} -- the single-element integrals (the rows of the
+ *                          worked example of Section 2 where p+1 consecutive B-splines
+ *                          sum to one);
+ *       IGA_SPANS_CUSTOM   caller tables; each S_r must lie inside supp B_r.
+ *   - Gauss rule: nq[a] Gauss-Legendre points per element on axis a; weight times
+ *     Jacobian W = w h / 2 per axis (Section 2, Section 4.1).
+ *   - A source f is   sin_amp * prod_a sin(pi x_a)   plus an optional table with one
+ *     value per Gauss point on the global Gauss grid, shape
+ *     (ne_z nq_z, ne_y nq_y, ne_x nq_x), x fastest, point q of element e at e*nq + q
+ *     with q ascending in the abscissa.
+ *
+ * Memory and execution.
+ *   - Every array argument is a DEVICE pointer owned by the caller, except where
+ *     marked "host".  The library never frees caller memory.  A context owns its
+ *     tables and its scratch buffers only.
+ *   - Calls enqueue kernels on the context's HIP stream and return without waiting
+ *     (asynchronous); argument errors are detected and returned before anything is
+ *     enqueued.  One context per stream; calls on one context are not thread-safe.
+ *   - Return value: IGA_OK (0) or a negative IGA_E_* code; nothing throws.
+ *   - All arithmetic is FP64.
+ */
+#ifndef IGA_H
+#define IGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IGA_OK 0
+#define IGA_E_INVAL (-1)       /* bad argument (null pointer, size, range, span table) */
+#define IGA_E_UNSUPPORTED (-2) /* dim not in {1,2,3}, p not in {2,3}, nq not in [1,16] */
+#define IGA_E_NOMEM (-3)       /* device allocation failed / batch over its memory budget */
+#define IGA_E_DEVICE (-4)      /* a HIP call failed */
+#define IGA_E_AGAIN (-5)       /* batch queue full: poll and submit again */
+
+typedef enum { IGA_GALERKIN_BYPARTS = 0, IGA_GALERKIN_LAPLACIAN = 1, IGA_PG = 2 } iga_form;
+typedef enum { IGA_OP_MASS = 0, IGA_OP_LAPLACE = 1 } iga_op;
+typedef enum { IGA_SPANS_SUPPORT = 0, IGA_SPANS_ELEMENT = 1, IGA_SPANS_CUSTOM = 2 } iga_spans;
+
+typedef struct {
+    int32_t dim;        /* 1, 2 or 3                                                  */
+    int32_t p;          /* B-spline degree on every axis: 2 (C1) or 3 (C2)             */
+    int64_t ne[3];      /* elements per axis, >= 1 (entries beyond dim ignored)        */
+    double lo[3];       /* domain per axis, lo < hi                                    */
+    double hi[3];
+    int32_t nq[3];      /* Gauss points per element per axis, 1..16                    */
+    int32_t spans;      /* iga_spans                                                   */
+    /* IGA_SPANS_CUSTOM only (host, read during iga_create and not kept):             */
+    int64_t nspan[3];
+    const int64_t *span_first[3];
+    const int64_t *span_last[3];
+} iga_mesh_desc;
+
+typedef struct {
+    const double *table; /* device, nullable: one value per Gauss point (layout above) */
+    double sin_amp;      /* amplitude of prod_a sin(pi x_a); 0 for none                */
+} iga_source;
+
+typedef struct iga_ctx iga_ctx;
+
+/* Creates a context for one mesh: validates the descriptor and builds, with device
+   kernels, the per-axis Gauss rule, the basis tables and the banded 1D factors.
+   hip_stream: a hipStream_t (NULL = the default stream) on which every call of this
+   context is enqueued.  Waits for its own set-up kernels before returning.
+   Errors: IGA_E_INVAL (null out, bad sizes or spans), IGA_E_UNSUPPORTED,
+   IGA_E_NOMEM, IGA_E_DEVICE. */
+int iga_create(const iga_mesh_desc *desc, void *hip_stream, iga_ctx **out);
+
+/* Releases the context's tables, scratch and cached graphs (waits for its stream). */
+int iga_destroy(iga_ctx *ctx);
+
+/* Row counts R_a (rows, host, [3]) of `form` and basis counts N_a (cols, host, [3]);
+   entries beyond dim are 1. */
+int iga_shape(const iga_ctx *ctx, int32_t form, int64_t rows[3], int64_t cols[3]);
+
+/* System matrices as banded 1D factors (Section 4.1: the tensor-product matrices are
+   Kronecker products of 1D matrices, the structure used by the alternating-directions
+   solver).  Writes `bands` (device, caller-allocated, dim*2*Rmax*(2p+1) doubles,
+   Rmax = max_a R_a): bands[((a*2 + f)*Rmax + r)*(2p+1) + k] is the entry of factor f
+   on axis a in row r, column r + k - p (zero where that column does not exist and in
+   rows r >= R_a).  Factor 0 is the mass-type factor (Galerkin: int B_r B_j; PG:
+   int_{S_r} B_j); factor 1 is the operator factor (Galerkin Laplacian form:
+   int B_r B_j''; by parts: -int B_r' B_j'; PG: int_{S_r} B_j'').
+   The d-dimensional matrix is  MASS: prod_a F0_a  and  LAPLACE: sum_t prod_a
+   (a == t ? F1_a : F0_a)  (Kronecker products, x fastest).  `op` selects whether
+   factor 1 is written (IGA_OP_LAPLACE) or left untouched (IGA_OP_MASS).
+   Errors: IGA_E_INVAL. */
+int iga_assemble(iga_ctx *ctx, int32_t form, int32_t op, double *bands);
+
+/* Right-hand side / operator application (Section 2-4.1):
+     b_r = int T_r (alpha u_h + beta Lap u_h + gamma f)
+   with T_r = B_r (Galerkin forms) or the indicator of S_r (PG), u_h = sum_j u_j B_j.
+   u: device coefficients (N_z,N_y,N_x), may be NULL when alpha = beta = 0.
+   f: host struct (NULL = no source); its table is a device pointer.
+   b: device rows (R_z,R_y,R_x), must not alias u or f->table.
+   Errors: IGA_E_INVAL. */
+int iga_rhs(iga_ctx *ctx, int32_t form, const double *u, double alpha, double beta,
+            double gamma, const iga_source *f, double *b);
+
+/* Fused matrix-free application of both operators in one pass over u:
+     mass_out_r = int T_r u_h,   lap_out_r = int T_r Lap u_h   (by parts for
+   IGA_GALERKIN_BYPARTS).  Either output may be NULL (not both).
+   Errors: IGA_E_INVAL. */
+int iga_apply(iga_ctx *ctx, int32_t form, const double *u, double *mass_out, double *lap_out);
+
+/* nsteps forward-Euler steps of u_t = Lap u + f (Section 4.2) in the PG form with
+   support spans, the left-hand side lumped by its row sums (partition of unity:
+   sum_j int_{S_r} B_j = |S_r|):
+     u_r <- int_{S_r} (u_h + dt Lap u_h + dt f) / |S_r|.
+   u: device coefficients, updated in place.  Requires IGA_SPANS_SUPPORT (square
+   system).  For nsteps >= 2 the launches are captured once into a HIP graph that is
+   cached on the context and replayed while (u, dt, f, nsteps) stay the same.
+   Errors: IGA_E_INVAL (also for other span kinds), IGA_E_NOMEM. */
+int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, int32_t nsteps);
+
+/* Error string of an IGA_* code (static storage). */
+const char *iga_strerror(int code);
+
+/* ---------------------------------------------------------------------------------
+ * Batched execution: many independent problems of different sizes in ONE persistent
+ * kernel launch whose workgroups claim tiles from a device work counter.  Jobs are
+ * 2D PG fused applies (IGA_JOB_APPLY2D: mass_out and lap_out of iga_apply) or
+ * explicit steps (IGA_JOB_STEP, any dim, nsteps in-kernel steps on the job's
+ * (u, work) pair).  A batch owns a device queue; submitted jobs start when the next
+ * flush launches; results are identical to the per-problem calls with the same tile
+ * configuration.
+ * ------------------------------------------------------------------------------ */
+typedef enum { IGA_JOB_APPLY = 0, IGA_JOB_STEP = 1 } iga_job_kind;
+typedef enum { IGA_JOB_QUEUED = 0, IGA_JOB_RUNNING = 1, IGA_JOB_DONE = 2, IGA_JOB_FAILED = 3 } iga_job_state;
+
+typedef struct {
+    int32_t kind;       /* iga_job_kind                                                */
+    int32_t dim, p;     /* 1..3, 2..3                                                  */
+    int64_t ne[3];      /* elements per axis on [0,1]^dim, nq = p+1, support spans     */
+    const double *u;    /* device input coefficients (APPLY) / state (STEP, in place)   */
+    double *out0;       /* APPLY: mass_out (nullable)     STEP: device work buffer      */
+    double *out1;       /* APPLY: lap_out (nullable)      STEP: unused                  */
+    double dt;          /* STEP                                                        */
+    double sin_amp;     /* STEP: source amplitude of prod sin(pi x_a)                   */
+    int32_t nsteps;     /* STEP, >= 1                                                  */
+} iga_job;
+
+typedef struct iga_batch iga_batch;
+
+/* mem_budget_bytes: admission limit on the bytes the queued jobs touch (inputs and
+   outputs); 0 = unlimited.  max_jobs: queue capacity. */
+int iga_batch_create(void *hip_stream, size_t mem_budget_bytes, int32_t max_jobs,
+                     iga_batch **out);
+/* Validates and queues jobs (host array); tickets (host, [njobs]) receive ids.
+   IGA_E_AGAIN when the queue or the budget cannot take all of them (none queued). */
+int iga_batch_submit(iga_batch *b, const iga_job *jobs, int32_t njobs, uint64_t *tickets);
+/* Launches one persistent kernel over every queued job (asynchronous). */
+int iga_batch_flush(iga_batch *b);
+/* state (host): IGA_JOB_QUEUED / RUNNING / DONE / FAILED of a ticket. */
+int iga_batch_poll(iga_batch *b, uint64_t ticket, int32_t *state);
+/* Blocks until every flushed job is done. */
+int iga_batch_wait(iga_batch *b);
+int iga_batch_destroy(iga_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGA_H */

@@ -1,0 +1,54 @@
+// common.hpp -- types shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace iga {
+
+constexpr int kMaxP = 3;      // kernels are instantiated for p = 2, 3
+constexpr int kMaxNq = 16;    // Gauss points per element per axis
+constexpr int kBlock = 256;   // threads per workgroup of the tiled kernels (4 wave64)
+
+// One axis of a tensor-product operator given by banded 1D factors of width
+// W = 2p+1: entry k of row r multiplies coefficient r + k - p.
+struct AxisOp {
+    const double* M;   // [R][W] mass-type factor
+    const double* D;   // [R][W] operator factor
+    const double* S;   // [R] output scale (inverse span length of the lumped step) or null
+    const double* F;   // [R] separable source factor or null
+    int R;             // rows
+    int N;             // basis functions (columns)
+};
+
+// out_r  = S(r) * ( alpha (Mass u)_r + beta (Lap u)_r + gsep * prod_a F_a(r_a) + garr * farr_r )
+// omass_r = (Mass u)_r            (written when omass != null)
+// with Mass = prod_a M_a and Lap = sum_t prod_a (a == t ? D_a : M_a) (Kronecker, x fastest).
+struct ApplyArgs {
+    AxisOp ax[3];
+    const double* u;      // (N_z, N_y, N_x)
+    double* out;          // (R_z, R_y, R_x) or null
+    double* omass;        // (R_z, R_y, R_x) or null
+    const double* farr;   // (R_z, R_y, R_x) or null
+    double alpha, beta, gsep, garr;
+};
+
+// Launch geometry of the tiled kernels: output tiles of TX x TY (x TZ planes in 3D),
+// enumerated x fastest, then y, then z-chunk.
+struct TileGrid {
+    int tx, ty, tz;       // tiles along each axis
+    int TZ;               // planes per z-chunk (3D)
+    int nblk;             // tx * ty * tz
+};
+
+// XCD-aware block order: gfx950 dispatches consecutive workgroups round-robin over its
+// 8 XCDs, each with a private L2.  Give every XCD a contiguous run of logical tiles so
+// that neighbouring tiles (which share p-wide halos) mostly land in the same L2.
+__device__ __forceinline__ int xcd_logical_block(int bid, int nblk)
+{
+    const int q = nblk >> 3, r = nblk & 7;
+    const int x = bid & 7, k = bid >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+}  // namespace iga

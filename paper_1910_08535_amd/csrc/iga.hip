@@ -1,0 +1,560 @@
+// iga.hip -- C ABI of the library (declared in include/iga.h): context set-up,
+// argument validation and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "iga.h"
+
+#include "apply.hpp"
+#include "common.hpp"
+#include "source.hpp"
+#include "tables.hpp"
+
+using iga::ApplyArgs;
+using iga::AxisOp;
+using iga::AxisTables;
+using iga::kBlock;
+using iga::TileGrid;
+
+#define IGA_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) {                                         \
+            std::fprintf(stderr, "iga: %s failed: %s (%s:%d)\n", #call, \
+                         hipGetErrorString(e_), __FILE__, __LINE__);    \
+            return IGA_E_DEVICE;                                        \
+        }                                                               \
+    } while (0)
+
+#define IGA_TRY(expr)              \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != IGA_OK) return rc_; \
+    } while (0)
+
+struct iga_ctx {
+    int dim = 0, p = 0, W = 0, spans = 0;
+    int ne[3] = {1, 1, 1}, nq[3] = {1, 1, 1}, N[3] = {1, 1, 1}, R[3] = {1, 1, 1};
+    double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    AxisTables t[3] = {};
+    std::vector<void*> allocs;
+    double* unit = nullptr;   // device {1, 0, 0, ...}: tables of an axis beyond dim
+    int* zero = nullptr;      // device {0}
+    double* farr = nullptr;
+    size_t farr_n = 0;
+    double* elem = nullptr;
+    size_t elem_n = 0;
+    double* work = nullptr;
+    size_t work_n = 0;
+    // cached explicit-step graph
+    hipGraphExec_t gexec = nullptr;
+    const double* g_u = nullptr;
+    const double* g_tab = nullptr;
+    double g_dt = 0, g_amp = 0;
+    int g_n = 0;
+};
+
+namespace {
+
+int dalloc(iga_ctx* c, void** p, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return IGA_E_NOMEM;
+    }
+    c->allocs.push_back(*p);
+    return IGA_OK;
+}
+
+// Scratch of at least n doubles, grown on demand.  Growth waits for the stream so
+// that no queued kernel still uses the old buffer.
+int scratch(iga_ctx* c, double** buf, size_t* cap, size_t n)
+{
+    if (*cap >= n && *buf) return IGA_OK;
+    IGA_HIP(hipStreamSynchronize(c->stream));
+    if (*buf) {
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)*buf);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        IGA_HIP(hipFree(*buf));
+        *buf = nullptr;
+        *cap = 0;
+    }
+    void* p = nullptr;
+    IGA_TRY(dalloc(c, &p, n * sizeof(double)));
+    *buf = (double*)p;
+    *cap = n;
+    return IGA_OK;
+}
+
+size_t prod3(const int v[3]) { return (size_t)v[0] * v[1] * v[2]; }
+
+int rows_of(const iga_ctx* c, int form, int a) { return form == IGA_PG ? c->R[a] : c->N[a]; }
+
+size_t nrows(const iga_ctx* c, int form)
+{
+    size_t n = 1;
+    for (int a = 0; a < c->dim; ++a) n *= (size_t)rows_of(c, form, a);
+    return n;
+}
+
+bool valid_form(int form)
+{
+    return form == IGA_GALERKIN_BYPARTS || form == IGA_GALERKIN_LAPLACIAN || form == IGA_PG;
+}
+
+ApplyArgs make_args(const iga_ctx* c, int form, bool step, bool sep_source)
+{
+    ApplyArgs g;
+    std::memset(&g, 0, sizeof(g));
+    for (int a = 0; a < 3; ++a) {
+        AxisOp& o = g.ax[a];
+        if (a < c->dim) {
+            const AxisTables& t = c->t[a];
+            if (form == IGA_PG) {
+                o.M = t.pm;
+                o.D = t.pd;
+                o.F = sep_source ? t.fs_pg : nullptr;
+                o.S = step ? t.inv_len : nullptr;
+                o.R = t.R;
+            } else {
+                o.M = t.gm;
+                o.D = form == IGA_GALERKIN_LAPLACIAN ? t.gl : t.gb;
+                o.F = sep_source ? t.fs_g : nullptr;
+                o.S = nullptr;
+                o.R = t.N;
+            }
+            o.N = t.N;
+        } else {
+            o.M = o.D = c->unit;
+            o.F = o.S = nullptr;
+            o.R = o.N = 1;
+        }
+    }
+    return g;
+}
+
+int pick_tz(int tx, int ty, int R2)
+{
+    // enough z-chunks that the launch has several workgroups per CU
+    int TZ = 16;
+    while (TZ > 4 && (size_t)tx * ty * ((R2 + TZ - 1) / TZ) < 1024) TZ /= 2;
+    return TZ;
+}
+
+template <int P>
+int launch_apply_p(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
+{
+    if (c->dim == 1) {
+        const int grid = (g.ax[0].R + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(iga::apply1d_kernel<P>, dim3(grid), dim3(kBlock), 0, s, g);
+    } else if (c->dim == 2) {
+        constexpr int TY = 16;
+        TileGrid tg;
+        tg.tx = (g.ax[0].R + 63) / 64;
+        tg.ty = (g.ax[1].R + TY - 1) / TY;
+        tg.tz = 1;
+        tg.TZ = 1;
+        tg.nblk = tg.tx * tg.ty;
+        hipLaunchKernelGGL((iga::apply2d_kernel<P, TY>), dim3(tg.nblk), dim3(kBlock), 0, s, g, tg);
+    } else {
+        TileGrid tg;
+        tg.tx = (g.ax[0].R + 63) / 64;
+        tg.ty = (g.ax[1].R + 7) / 8;
+        tg.TZ = pick_tz(tg.tx, tg.ty, g.ax[2].R);
+        tg.tz = (g.ax[2].R + tg.TZ - 1) / tg.TZ;
+        tg.nblk = tg.tx * tg.ty * tg.tz;
+        hipLaunchKernelGGL(iga::apply3d_kernel<P>, dim3(tg.nblk), dim3(kBlock), 0, s, g, tg);
+    }
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
+int launch_apply(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
+{
+    return c->p == 2 ? launch_apply_p<2>(c, g, s) : launch_apply_p<3>(c, g, s);
+}
+
+int launch_rows_only(const iga_ctx* c, const ApplyArgs& g, size_t n, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(iga::rows_only_kernel, dim3(grid), dim3(kBlock), 0, s, g, c->dim, n);
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
+// Rows of a Gauss-table source into c->farr (unscaled F_r).
+int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
+{
+    iga::SrcArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    size_t nel = 1;
+    int np1 = 1;
+    for (int a = 0; a < 3; ++a) {
+        iga::SrcAxis& x = sa.ax[a];
+        if (a < c->dim) {
+            const AxisTables& t = c->t[a];
+            x.ne = t.ne;
+            x.nq = t.nq;
+            x.np1 = t.p + 1;
+            x.R = form == IGA_PG ? t.R : t.N;
+            x.wg = t.wg;
+            x.bq = t.bq;
+            x.first = t.first;
+            x.last = t.last;
+            nel *= (size_t)t.ne;
+            np1 *= t.p + 1;
+        } else {
+            x.ne = x.nq = x.np1 = x.R = 1;
+            x.wg = c->unit;
+            x.bq = c->unit;
+            x.first = x.last = c->zero;
+        }
+    }
+    const size_t nr = nrows(c, form);
+    const size_t nelem_vals = form == IGA_PG ? nel : nel * (size_t)np1;
+    IGA_TRY(scratch(c, &c->elem, &c->elem_n, nelem_vals));
+    IGA_TRY(scratch(c, &c->farr, &c->farr_n, nr));
+    sa.table = table;
+    sa.elem = c->elem;
+    sa.rows = c->farr;
+    const unsigned ge = (unsigned)((nel + kBlock - 1) / kBlock);
+    const unsigned gr = (unsigned)((nr + kBlock - 1) / kBlock);
+    if (form == IGA_PG) {
+        hipLaunchKernelGGL(iga::pg_src_elem_kernel, dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        hipLaunchKernelGGL(iga::pg_src_rows_kernel, dim3(gr), dim3(kBlock), 0, s, sa, nr);
+    } else {
+        hipLaunchKernelGGL(iga::gal_src_elem_kernel, dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        hipLaunchKernelGGL(iga::gal_src_rows_kernel, dim3(gr), dim3(kBlock), 0, s, sa, nr);
+    }
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
+void free_graph(iga_ctx* c)
+{
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+}
+
+int validate_desc(const iga_mesh_desc* d)
+{
+    if (!d) return IGA_E_INVAL;
+    if (d->dim < 1 || d->dim > 3) return IGA_E_UNSUPPORTED;
+    if (d->p < 2 || d->p > iga::kMaxP) return IGA_E_UNSUPPORTED;
+    size_t ncoef = 1, ngauss = 1;
+    for (int a = 0; a < d->dim; ++a) {
+        if (d->nq[a] < 1 || d->nq[a] > iga::kMaxNq) return IGA_E_UNSUPPORTED;
+        if (d->ne[a] < 1 || d->ne[a] > (1 << 28)) return IGA_E_INVAL;
+        if (!(d->lo[a] < d->hi[a]) || !std::isfinite(d->lo[a]) || !std::isfinite(d->hi[a]))
+            return IGA_E_INVAL;
+        ncoef *= (size_t)(d->ne[a] + d->p);
+        ngauss *= (size_t)d->ne[a] * d->nq[a];
+    }
+    if (ncoef >= (size_t)1 << 31 || ngauss >= (size_t)1 << 40) return IGA_E_INVAL;
+    if (d->spans != IGA_SPANS_SUPPORT && d->spans != IGA_SPANS_ELEMENT &&
+        d->spans != IGA_SPANS_CUSTOM)
+        return IGA_E_INVAL;
+    if (d->spans == IGA_SPANS_CUSTOM) {
+        for (int a = 0; a < d->dim; ++a) {
+            const int64_t N = d->ne[a] + d->p;
+            if (d->nspan[a] < 1 || d->nspan[a] > N || !d->span_first[a] || !d->span_last[a])
+                return IGA_E_INVAL;
+            for (int64_t r = 0; r < d->nspan[a]; ++r) {
+                const int64_t s = d->span_first[a][r], t = d->span_last[a][r];
+                // the span of row r must lie inside the support of B_r
+                if (s < std::max<int64_t>(0, r - d->p) || t < s || t > std::min<int64_t>(d->ne[a] - 1, r))
+                    return IGA_E_INVAL;
+            }
+        }
+    }
+    return IGA_OK;
+}
+
+int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
+{
+    AxisTables& t = c->t[a];
+    t.p = c->p;
+    t.ne = (int)d->ne[a];
+    t.nq = d->nq[a];
+    t.N = t.ne + t.p;
+    t.W = 2 * t.p + 1;
+    t.lo = d->lo[a];
+    t.hi = d->hi[a];
+    std::vector<int> first, last;
+    if (d->spans == IGA_SPANS_SUPPORT) {
+        for (int r = 0; r < t.N; ++r) {
+            first.push_back(std::max(0, r - t.p));
+            last.push_back(std::min(t.ne - 1, r));
+        }
+    } else if (d->spans == IGA_SPANS_ELEMENT) {
+        for (int e = 0; e < t.ne; ++e) {
+            first.push_back(e);
+            last.push_back(e);
+        }
+    } else {
+        for (int64_t r = 0; r < d->nspan[a]; ++r) {
+            first.push_back((int)d->span_first[a][r]);
+            last.push_back((int)d->span_last[a][r]);
+        }
+    }
+    t.R = (int)first.size();
+    const size_t ng = (size_t)t.ne * t.nq;
+    void* p;
+    IGA_TRY(dalloc(c, &p, ng * sizeof(double))); t.xg = (double*)p;
+    IGA_TRY(dalloc(c, &p, ng * sizeof(double))); t.wg = (double*)p;
+    IGA_TRY(dalloc(c, &p, ng * 3 * (t.p + 1) * sizeof(double))); t.bq = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.R * t.W * sizeof(double))); t.pm = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.R * t.W * sizeof(double))); t.pd = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(double))); t.inv_len = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(double))); t.fs_pg = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.N * t.W * sizeof(double))); t.gm = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.N * t.W * sizeof(double))); t.gl = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.N * t.W * sizeof(double))); t.gb = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.N * sizeof(double))); t.fs_g = (double*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(int))); t.first = (int*)p;
+    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(int))); t.last = (int*)p;
+    IGA_HIP(hipMemcpyAsync(t.first, first.data(), first.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+    IGA_HIP(hipMemcpyAsync(t.last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+    const unsigned g1 = (unsigned)((ng + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(iga::gauss_tables_kernel, dim3(g1), dim3(kBlock), 0, c->stream, t);
+    const int nr = std::max(t.R, t.N);
+    hipLaunchKernelGGL(iga::band_tables_kernel, dim3((nr + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       c->stream, t);
+    IGA_HIP(hipGetLastError());
+    // the host span vectors die at return: wait for the copies
+    IGA_HIP(hipStreamSynchronize(c->stream));
+    return IGA_OK;
+}
+
+__global__ void bands_out_kernel(double* dst, const double* f0, const double* f1, int R, int Rmax,
+                                 int W, int write1)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Rmax * W) return;
+    const int r = i / W;
+    dst[i] = r < R ? f0[i] : 0.0;
+    if (write1) dst[(size_t)Rmax * W + i] = r < R ? f1[i] : 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* iga_strerror(int code)
+{
+    switch (code) {
+    case IGA_OK: return "ok";
+    case IGA_E_INVAL: return "invalid argument";
+    case IGA_E_UNSUPPORTED: return "unsupported dimension, degree or quadrature";
+    case IGA_E_NOMEM: return "out of device memory or over the memory budget";
+    case IGA_E_DEVICE: return "HIP runtime error";
+    case IGA_E_AGAIN: return "queue full, try again";
+    default: return "unknown error";
+    }
+}
+
+int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
+{
+    if (!out) return IGA_E_INVAL;
+    *out = nullptr;
+    IGA_TRY(validate_desc(desc));
+    iga_ctx* c = new (std::nothrow) iga_ctx;
+    if (!c) return IGA_E_NOMEM;
+    c->dim = desc->dim;
+    c->p = desc->p;
+    c->W = 2 * desc->p + 1;
+    c->spans = desc->spans;
+    c->stream = (hipStream_t)hip_stream;
+    int rc = IGA_OK;
+    void* p = nullptr;
+    rc = dalloc(c, &p, 8 * sizeof(double));
+    if (rc == IGA_OK) {
+        c->unit = (double*)p;
+        const double u8[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+        if (hipMemcpy(c->unit, u8, sizeof(u8), hipMemcpyHostToDevice) != hipSuccess) rc = IGA_E_DEVICE;
+    }
+    if (rc == IGA_OK) rc = dalloc(c, &p, sizeof(int) * 2);
+    if (rc == IGA_OK) {
+        c->zero = (int*)p;
+        const int z2[2] = {0, 0};
+        if (hipMemcpy(c->zero, z2, sizeof(z2), hipMemcpyHostToDevice) != hipSuccess) rc = IGA_E_DEVICE;
+    }
+    for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
+        c->ne[a] = (int)desc->ne[a];
+        c->nq[a] = desc->nq[a];
+        c->lo[a] = desc->lo[a];
+        c->hi[a] = desc->hi[a];
+        rc = build_axis(c, a, desc);
+        c->N[a] = c->t[a].N;
+        c->R[a] = c->t[a].R;
+    }
+    if (rc != IGA_OK) {
+        iga_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return IGA_OK;
+}
+
+int iga_destroy(iga_ctx* c)
+{
+    if (!c) return IGA_E_INVAL;
+    (void)hipStreamSynchronize(c->stream);
+    free_graph(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    for (void* p : c->allocs) (void)hipFree(p);
+    delete c;
+    return IGA_OK;
+}
+
+int iga_shape(const iga_ctx* c, int32_t form, int64_t rows[3], int64_t cols[3])
+{
+    if (!c || !rows || !cols || !valid_form(form)) return IGA_E_INVAL;
+    for (int a = 0; a < 3; ++a) {
+        rows[a] = a < c->dim ? rows_of(c, form, a) : 1;
+        cols[a] = a < c->dim ? c->N[a] : 1;
+    }
+    return IGA_OK;
+}
+
+int iga_assemble(iga_ctx* c, int32_t form, int32_t op, double* bands)
+{
+    if (!c || !bands || !valid_form(form) || (op != IGA_OP_MASS && op != IGA_OP_LAPLACE))
+        return IGA_E_INVAL;
+    int Rmax = 1;
+    for (int a = 0; a < c->dim; ++a) Rmax = std::max(Rmax, rows_of(c, form, a));
+    const ApplyArgs g = make_args(c, form, false, false);
+    for (int a = 0; a < c->dim; ++a) {
+        double* dst = bands + (size_t)a * 2 * Rmax * c->W;
+        const int n = Rmax * c->W;
+        hipLaunchKernelGGL(bands_out_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                           c->stream, dst, g.ax[a].M, g.ax[a].D, g.ax[a].R, Rmax, c->W,
+                           op == IGA_OP_LAPLACE ? 1 : 0);
+    }
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
+int iga_rhs(iga_ctx* c, int32_t form, const double* u, double alpha, double beta, double gamma,
+            const iga_source* f, double* b)
+{
+    if (!c || !b || !valid_form(form)) return IGA_E_INVAL;
+    const bool uterm = alpha != 0.0 || beta != 0.0;
+    if (uterm && !u) return IGA_E_INVAL;
+    if (!std::isfinite(alpha) || !std::isfinite(beta) || !std::isfinite(gamma)) return IGA_E_INVAL;
+    const double amp = f ? f->sin_amp : 0.0;
+    const bool tab = f && f->table && gamma != 0.0;
+    const bool sep = amp != 0.0 && gamma != 0.0;
+    if (!std::isfinite(amp)) return IGA_E_INVAL;
+    if ((u && (const double*)b == u) || (tab && (const double*)b == f->table)) return IGA_E_INVAL;
+    ApplyArgs g = make_args(c, form, false, sep);
+    g.u = u;
+    g.out = b;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.gsep = sep ? gamma * amp : 0.0;
+    g.garr = gamma;
+    if (tab) {
+        IGA_TRY(source_rows(c, form, f->table, c->stream));
+        g.farr = c->farr;
+    }
+    if (uterm) return launch_apply(c, g, c->stream);
+    return launch_rows_only(c, g, nrows(c, form), c->stream);
+}
+
+int iga_apply(iga_ctx* c, int32_t form, const double* u, double* mass_out, double* lap_out)
+{
+    if (!c || !u || !valid_form(form) || (!mass_out && !lap_out)) return IGA_E_INVAL;
+    if ((const double*)mass_out == u || (const double*)lap_out == u || (mass_out && mass_out == lap_out))
+        return IGA_E_INVAL;
+    ApplyArgs g = make_args(c, form, false, false);
+    g.u = u;
+    g.out = lap_out;
+    g.omass = mass_out;
+    g.alpha = 0.0;
+    g.beta = 1.0;
+    return launch_apply(c, g, c->stream);
+}
+
+int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int32_t nsteps)
+{
+    if (!c || !u || nsteps < 0 || !std::isfinite(dt)) return IGA_E_INVAL;
+    if (c->spans != IGA_SPANS_SUPPORT) return IGA_E_INVAL;
+    if (nsteps == 0) return IGA_OK;
+    const double amp = f ? f->sin_amp : 0.0;
+    const double* table = f ? f->table : nullptr;
+    if (!std::isfinite(amp)) return IGA_E_INVAL;
+    const size_t n = prod3(c->N);
+    IGA_TRY(scratch(c, &c->work, &c->work_n, n));
+    if (table) {   // make sure the source scratch exists before any capture
+        size_t nel = 1;
+        for (int a = 0; a < c->dim; ++a) nel *= (size_t)c->ne[a];
+        IGA_TRY(scratch(c, &c->elem, &c->elem_n, nel));
+        IGA_TRY(scratch(c, &c->farr, &c->farr_n, n));
+    }
+    auto enqueue = [&](hipStream_t s) -> int {
+        ApplyArgs g = make_args(c, IGA_PG, true, amp != 0.0);
+        g.alpha = 1.0;
+        g.beta = dt;
+        g.gsep = dt * amp;
+        g.garr = dt;
+        if (table) {
+            IGA_TRY(source_rows(c, IGA_PG, table, s));
+            g.farr = c->farr;
+        }
+        for (int k = 0; k < nsteps; ++k) {
+            g.u = (k & 1) ? c->work : u;
+            g.out = (k & 1) ? u : c->work;
+            IGA_TRY(launch_apply(c, g, s));
+        }
+        if (nsteps & 1) {
+            hipLaunchKernelGGL(iga::copy_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, s, u, (const double*)c->work, n);
+            IGA_HIP(hipGetLastError());
+        }
+        return IGA_OK;
+    };
+    if (nsteps == 1) return enqueue(c->stream);
+    const bool hit = c->gexec && c->g_u == u && c->g_tab == table && c->g_dt == dt &&
+                     c->g_amp == amp && c->g_n == nsteps;
+    if (!hit) {
+        free_graph(c);
+        if (!c->cap) IGA_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        IGA_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue(c->cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+        if (rc != IGA_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        IGA_HIP(e);
+        const hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        IGA_HIP(ei);
+        c->g_u = u;
+        c->g_tab = table;
+        c->g_dt = dt;
+        c->g_amp = amp;
+        c->g_n = nsteps;
+    }
+    IGA_HIP(hipGraphLaunch(c->gexec, c->stream));
+    return IGA_OK;
+}
+
+}  // extern "C"

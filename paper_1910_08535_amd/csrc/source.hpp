@@ -1,0 +1,136 @@
+// source.hpp -- right-hand sides of a source given at the Gauss points (a table with
+// one value per Gauss point), Section 4.1: the paper's generation loops for the
+// L2-projection right-hand side.
+//
+//   Petrov-Galerkin:  F_r = sum_{e in S_r} sum_q W_q f_q        (test = 1, never evaluated)
+//   Galerkin:         F_i = sum_e sum_q W_q B_i(x_q) f_q         (test B_i at every point)
+//
+// Both run in two steps: a per-element reduction over the element's Gauss points
+// (PG: one number; Galerkin: one number per local test function), then a gather of
+// the element results into rows.  The gather reads each element result from the
+// rows it feeds, so no atomics are used and the result does not depend on timing.
+#pragma once
+
+#include "common.hpp"
+
+namespace iga {
+
+struct SrcAxis {
+    int ne, nq, np1;          // elements, Gauss points per element, local functions (p+1)
+    int R;                    // rows of this axis
+    const double* wg;         // [ne*nq] weight * Jacobian
+    const double* bq;         // [ne*nq*3*np1] basis values (Galerkin)
+    const int* first;         // [R] PG spans
+    const int* last;
+};
+
+struct SrcArgs {
+    SrcAxis ax[3];            // axes beyond dim: ne = nq = np1 = R = 1, unit tables
+    const double* table;      // (ne_z nq_z, ne_y nq_y, ne_x nq_x)
+    double* elem;             // PG: [n_el]; Galerkin: [n_el * np1^3]
+    double* rows;             // (R_z, R_y, R_x)
+};
+
+__device__ __forceinline__ void elem_index(const SrcArgs& s, size_t idx, int e[3])
+{
+    e[0] = (int)(idx % s.ax[0].ne);
+    e[1] = (int)((idx / s.ax[0].ne) % s.ax[1].ne);
+    e[2] = (int)(idx / ((size_t)s.ax[0].ne * s.ax[1].ne));
+}
+
+// PG step 1: E_e = sum_q W_q f_q over the element's Gauss points.
+__global__ void pg_src_elem_kernel(SrcArgs s, size_t nel)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nel) return;
+    int e[3];
+    elem_index(s, idx, e);
+    const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
+    const size_t gx0 = (size_t)e[0] * X.nq, gy0 = (size_t)e[1] * Y.nq, gz0 = (size_t)e[2] * Z.nq;
+    const size_t ngx = (size_t)X.ne * X.nq, ngy = (size_t)Y.ne * Y.nq;
+    double acc = 0.0;
+    for (int qz = 0; qz < Z.nq; ++qz)
+        for (int qy = 0; qy < Y.nq; ++qy) {
+            const double wyz = Z.wg[gz0 + qz] * Y.wg[gy0 + qy];
+            const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0;
+            double t = 0.0;
+            for (int qx = 0; qx < X.nq; ++qx) t = fma(X.wg[gx0 + qx], row[qx], t);
+            acc = fma(wyz, t, acc);
+        }
+    s.elem[idx] = acc;
+}
+
+// PG step 2: F_r = sum over the tensor span of the element integrals.
+__global__ void pg_src_rows_kernel(SrcArgs s, size_t nrows)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows) return;
+    const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
+    const int rx = (int)(idx % X.R);
+    const int ry = (int)((idx / X.R) % Y.R);
+    const int rz = (int)(idx / ((size_t)X.R * Y.R));
+    double acc = 0.0;
+    for (int ez = Z.first[rz]; ez <= Z.last[rz]; ++ez)
+        for (int ey = Y.first[ry]; ey <= Y.last[ry]; ++ey)
+            for (int ex = X.first[rx]; ex <= X.last[rx]; ++ex)
+                acc += s.elem[((size_t)ez * Y.ne + ey) * X.ne + ex];
+    s.rows[idx] = acc;
+}
+
+// Galerkin step 1: E_{e,a} = sum_q W_q B_{e+a}(x_q) f_q for the np1^dim local tests a.
+__global__ void gal_src_elem_kernel(SrcArgs s, size_t nel)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nel) return;
+    int e[3];
+    elem_index(s, idx, e);
+    const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
+    const size_t gx0 = (size_t)e[0] * X.nq, gy0 = (size_t)e[1] * Y.nq, gz0 = (size_t)e[2] * Z.nq;
+    const size_t ngx = (size_t)X.ne * X.nq, ngy = (size_t)Y.ne * Y.nq;
+    const int nloc = X.np1 * Y.np1 * Z.np1;
+    for (int a = 0; a < nloc; ++a) {
+        const int ax = a % X.np1, ay = (a / X.np1) % Y.np1, az = a / (X.np1 * Y.np1);
+        double acc = 0.0;
+        for (int qz = 0; qz < Z.nq; ++qz)
+            for (int qy = 0; qy < Y.nq; ++qy) {
+                const double tz = Z.wg[gz0 + qz] * Z.bq[((gz0 + qz) * 3) * Z.np1 + az];
+                const double ty = Y.wg[gy0 + qy] * Y.bq[((gy0 + qy) * 3) * Y.np1 + ay];
+                const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0;
+                double t = 0.0;
+                for (int qx = 0; qx < X.nq; ++qx)
+                    t = fma(X.wg[gx0 + qx] * X.bq[((gx0 + qx) * 3) * X.np1 + ax], row[qx], t);
+                acc = fma(tz * ty, t, acc);
+            }
+        s.elem[idx * nloc + a] = acc;
+    }
+}
+
+// Galerkin step 2: F_i = sum over the elements e = i - a (a local index per axis).
+__global__ void gal_src_rows_kernel(SrcArgs s, size_t nrows)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows) return;
+    const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
+    const int ix = (int)(idx % X.R);
+    const int iy = (int)((idx / X.R) % Y.R);
+    const int iz = (int)(idx / ((size_t)X.R * Y.R));
+    const int nloc = X.np1 * Y.np1 * Z.np1;
+    double acc = 0.0;
+    for (int az = 0; az < Z.np1; ++az) {
+        const int ez = iz - az;
+        if (ez < 0 || ez >= Z.ne) continue;
+        for (int ay = 0; ay < Y.np1; ++ay) {
+            const int ey = iy - ay;
+            if (ey < 0 || ey >= Y.ne) continue;
+            for (int ax = 0; ax < X.np1; ++ax) {
+                const int ex = ix - ax;
+                if (ex < 0 || ex >= X.ne) continue;
+                const size_t el = ((size_t)ez * Y.ne + ey) * X.ne + ex;
+                acc += s.elem[el * nloc + (az * Y.np1 + ay) * X.np1 + ax];
+            }
+        }
+    }
+    s.rows[idx] = acc;
+}
+
+}  // namespace iga

@@ -1,0 +1,218 @@
+// tables.hpp -- set-up kernels: per-axis Gauss rule, B-spline values at the Gauss
+// points, and the banded 1D factors of the Galerkin and Petrov-Galerkin matrices.
+//
+// Everything here runs once per context, so the kernels favour clarity over speed.
+// The hot kernels (apply.hpp) only read the tables built here.
+#pragma once
+
+#include "common.hpp"
+
+namespace iga {
+
+// Knot t_k of the open uniform knot vector of degree p with ne elements on [lo, hi]
+// (Section 2: the first and the last knot repeated p+1 times).
+__device__ __forceinline__ double open_knot(int k, int p, int ne, double lo, double hi)
+{
+    if (k <= p) return lo;
+    if (k >= ne + p) return hi;
+    return lo + (hi - lo) * (double)(k - p) / (double)ne;
+}
+
+// Legendre polynomial P_n(z) and its derivative, by the three-term recurrence.
+__device__ __forceinline__ void legendre(int n, double z, double* pn, double* dpn)
+{
+    double pm1 = 1.0, p0 = z;
+    if (n == 0) { *pn = 1.0; *dpn = 0.0; return; }
+    for (int k = 2; k <= n; ++k) {
+        const double p1 = ((2.0 * k - 1.0) * z * p0 - (k - 1.0) * pm1) / (double)k;
+        pm1 = p0;
+        p0 = p1;
+    }
+    *pn = p0;
+    *dpn = (double)n * (z * p0 - pm1) / (z * z - 1.0);
+}
+
+// Node i (ascending) and weight of the n-point Gauss-Legendre rule on [-1, 1]:
+// Newton's method from Tricomi's asymptotic estimate of the (n-i)-th largest root.
+__device__ void gauss_node(int n, int i, double* x, double* w)
+{
+    const int k = n - i;
+    const double nn = (double)n;
+    double z = (1.0 - 1.0 / (8.0 * nn * nn) + 1.0 / (8.0 * nn * nn * nn)) *
+               cos(M_PI * (4.0 * k - 1.0) / (4.0 * nn + 2.0));
+    double pn, dp;
+    for (int it = 0; it < 60; ++it) {
+        legendre(n, z, &pn, &dp);
+        const double dz = pn / dp;
+        z -= dz;
+        if (fabs(dz) <= 1e-17) break;
+    }
+    legendre(n, z, &pn, &dp);
+    *x = z;
+    *w = 2.0 / ((1.0 - z * z) * dp * dp);
+}
+
+// Values, first and second derivatives of the p+1 B-splines e..e+p that can be nonzero
+// on element e, at the point x of that element: bottom-up triangle of the Cox-de Boor
+// recurrence for degrees 0..p, then the derivative relation
+//   d/dx B_{j,k} = k ( B_{j,k-1}/(t_{j+k}-t_j) - B_{j+1,k-1}/(t_{j+k+1}-t_{j+1}) )
+// applied once (first derivatives of degrees p-1 and p) and twice (second, degree p).
+// out[m][a] = m-th derivative of B_{e+a}.
+__device__ void basis_ders(int p, int ne, double lo, double hi, int e, double x,
+                           double out[3][kMaxP + 1])
+{
+    const int mu = e + p;   // knot interval [t_mu, t_{mu+1})
+    // V[k][i] = B_{mu-k+i, k}(x), i = 0..k
+    double V[kMaxP + 1][kMaxP + 1];
+    V[0][0] = 1.0;
+    for (int k = 1; k <= p; ++k) {
+        for (int i = 0; i <= k; ++i) {
+            const int j = mu - k + i;
+            const double tj = open_knot(j, p, ne, lo, hi);
+            const double tjk = open_knot(j + k, p, ne, lo, hi);
+            const double tj1 = open_knot(j + 1, p, ne, lo, hi);
+            const double tjk1 = open_knot(j + k + 1, p, ne, lo, hi);
+            const double lft = (i > 0) ? V[k - 1][i - 1] : 0.0;   // B_{j,k-1}
+            const double rgt = (i < k) ? V[k - 1][i] : 0.0;       // B_{j+1,k-1}
+            double v = 0.0;
+            if (tjk > tj) v += (x - tj) / (tjk - tj) * lft;
+            if (tjk1 > tj1) v += (tjk1 - x) / (tjk1 - tj1) * rgt;
+            V[k][i] = v;
+        }
+    }
+    // first derivatives of degree k in {p-1, p}: D1[k][i] for B_{mu-k+i, k}
+    double D1[kMaxP + 1][kMaxP + 1];
+    for (int k = (p >= 2 ? p - 1 : 1); k <= p; ++k) {
+        for (int i = 0; i <= k; ++i) {
+            const int j = mu - k + i;
+            const double tj = open_knot(j, p, ne, lo, hi);
+            const double tjk = open_knot(j + k, p, ne, lo, hi);
+            const double tj1 = open_knot(j + 1, p, ne, lo, hi);
+            const double tjk1 = open_knot(j + k + 1, p, ne, lo, hi);
+            const double lft = (i > 0) ? V[k - 1][i - 1] : 0.0;
+            const double rgt = (i < k) ? V[k - 1][i] : 0.0;
+            double d = 0.0;
+            if (tjk > tj) d += (double)k / (tjk - tj) * lft;
+            if (tjk1 > tj1) d -= (double)k / (tjk1 - tj1) * rgt;
+            D1[k][i] = d;
+        }
+    }
+    for (int i = 0; i <= p; ++i) {
+        out[0][i] = V[p][i];
+        out[1][i] = D1[p][i];
+        double d2 = 0.0;
+        if (p >= 2) {
+            const int j = mu - p + i;
+            const double tj = open_knot(j, p, ne, lo, hi);
+            const double tjk = open_knot(j + p, p, ne, lo, hi);
+            const double tj1 = open_knot(j + 1, p, ne, lo, hi);
+            const double tjk1 = open_knot(j + p + 1, p, ne, lo, hi);
+            const double lft = (i > 0) ? D1[p - 1][i - 1] : 0.0;
+            const double rgt = (i < p) ? D1[p - 1][i] : 0.0;
+            if (tjk > tj) d2 += (double)p / (tjk - tj) * lft;
+            if (tjk1 > tj1) d2 -= (double)p / (tjk1 - tj1) * rgt;
+        }
+        out[2][i] = d2;
+    }
+}
+
+// Per-axis device tables.  Layout of one axis (all doubles unless noted):
+//   xg[ne*nq], wg[ne*nq]      Gauss points and weight*Jacobian, point q of element e at e*nq+q
+//   bq[ne*nq*3*(p+1)]         bq[((e*nq+q)*3 + m)*(p+1) + a] = B^{(m)}_{e+a}(x_{e,q})
+//   pm[R*W], pd[R*W]          PG factors  int_{S_r} B_j,  int_{S_r} B_j''   (column r+k-p)
+//   inv_len[R], fs_pg[R]      1/|S_r|,  int_{S_r} sin(pi x)  (Gauss rule)
+//   gm[N*W], gl[N*W], gb[N*W] Galerkin int B_i B_j, int B_i B_j'', -int B_i' B_j'
+//   fs_g[N]                   int B_i sin(pi x)  (Gauss rule)
+//   first[R], last[R] (int)   PG spans
+struct AxisTables {
+    int p, ne, nq, N, R, W;
+    double lo, hi;
+    double *xg, *wg, *bq;
+    double *pm, *pd, *inv_len, *fs_pg;
+    double *gm, *gl, *gb, *fs_g;
+    int *first, *last;
+};
+
+__global__ void gauss_tables_kernel(AxisTables t)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= t.ne * t.nq) return;
+    const int e = idx / t.nq, q = idx % t.nq;
+    double xi, w;
+    gauss_node(t.nq, q, &xi, &w);
+    const double a0 = open_knot(e + t.p, t.p, t.ne, t.lo, t.hi);
+    const double a1 = open_knot(e + t.p + 1, t.p, t.ne, t.lo, t.hi);
+    const double x = a0 + 0.5 * (xi + 1.0) * (a1 - a0);
+    t.xg[idx] = x;
+    t.wg[idx] = 0.5 * w * (a1 - a0);
+    double B[3][kMaxP + 1];
+    basis_ders(t.p, t.ne, t.lo, t.hi, e, x, B);
+    for (int m = 0; m < 3; ++m)
+        for (int a = 0; a <= t.p; ++a) t.bq[((size_t)idx * 3 + m) * (t.p + 1) + a] = B[m][a];
+}
+
+// One thread per row: the Gauss sums of the banded factors.  PG rows never multiply by
+// a test function -- the integrand is summed with weight 1 over the span's elements.
+__global__ void band_tables_kernel(AxisTables t)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = t.p, np1 = t.p + 1, nq = t.nq, W = t.W;
+    if (r < t.R) {
+        const int s = t.first[r], l = t.last[r];
+        double fs = 0.0;
+        for (int k = 0; k < W; ++k) {
+            const int j = r + k - p;
+            double m0 = 0.0, d0 = 0.0;
+            for (int e = s; e <= l; ++e) {
+                const int a = j - e;
+                if (a < 0 || a > p) continue;
+                for (int q = 0; q < nq; ++q) {
+                    const size_t eq = (size_t)e * nq + q;
+                    m0 += t.wg[eq] * t.bq[(eq * 3 + 0) * np1 + a];
+                    d0 += t.wg[eq] * t.bq[(eq * 3 + 2) * np1 + a];
+                }
+            }
+            t.pm[(size_t)r * W + k] = m0;
+            t.pd[(size_t)r * W + k] = d0;
+        }
+        for (int e = s; e <= l; ++e)
+            for (int q = 0; q < nq; ++q) {
+                const size_t eq = (size_t)e * nq + q;
+                fs += t.wg[eq] * sin(M_PI * t.xg[eq]);
+            }
+        t.fs_pg[r] = fs;
+        t.inv_len[r] = 1.0 / (open_knot(l + p + 1, p, t.ne, t.lo, t.hi) -
+                              open_knot(s + p, p, t.ne, t.lo, t.hi));
+    }
+    if (r < t.N) {
+        const int e0 = r - p < 0 ? 0 : r - p;
+        const int e1 = r < t.ne - 1 ? r : t.ne - 1;
+        double fs = 0.0;
+        for (int k = 0; k < W; ++k) {
+            const int j = r + k - p;
+            double gm = 0.0, gl = 0.0, gb = 0.0;
+            for (int e = e0; e <= e1; ++e) {
+                const int c = r - e, a = j - e;
+                if (a < 0 || a > p) continue;
+                for (int q = 0; q < nq; ++q) {
+                    const size_t eq = (size_t)e * nq + q;
+                    const double* B = &t.bq[eq * 3 * np1];
+                    gm += t.wg[eq] * B[c] * B[a];
+                    gl += t.wg[eq] * B[c] * B[2 * np1 + a];
+                    gb -= t.wg[eq] * B[np1 + c] * B[np1 + a];
+                }
+            }
+            t.gm[(size_t)r * W + k] = gm;
+            t.gl[(size_t)r * W + k] = gl;
+            t.gb[(size_t)r * W + k] = gb;
+        }
+        for (int e = e0; e <= e1; ++e)
+            for (int q = 0; q < nq; ++q) {
+                const size_t eq = (size_t)e * nq + q;
+                fs += t.wg[eq] * t.bq[(eq * 3) * np1 + (r - e)] * sin(M_PI * t.xg[eq]);
+            }
+        t.fs_g[r] = fs;
+    }
+}
+
+}  // namespace iga

@@ -1,0 +1,277 @@
+"""Thin ctypes binding of the C ABI in include/iga.h (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libiga.so``; torch is used only for
+device memory and streams.  The binding refuses to run when the library is not
+built -- there is no fallback path.
+
+The raw functions carry the C names (``iga_create``, ``iga_rhs``, ...).  ``Mesh``
+is a convenience wrapper that takes torch tensors (float64, CUDA, contiguous,
+C-ordered (N_z, N_y, N_x), x fastest) and returns new tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiga.so")
+
+IGA_OK, IGA_E_INVAL, IGA_E_UNSUPPORTED, IGA_E_NOMEM, IGA_E_DEVICE, IGA_E_AGAIN = 0, -1, -2, -3, -4, -5
+GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
+OP_MASS, OP_LAPLACE = 0, 1
+SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM = 0, 1, 2
+JOB_APPLY, JOB_STEP = 0, 1
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
+_P64 = C.POINTER(C.c_int64)
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("p", C.c_int32), ("ne", C.c_int64 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("nq", C.c_int32 * 3),
+                ("spans", C.c_int32), ("nspan", C.c_int64 * 3),
+                ("span_first", _P64 * 3), ("span_last", _P64 * 3)]
+
+
+class Source(C.Structure):
+    _fields_ = [("table", C.c_void_p), ("sin_amp", C.c_double)]
+
+
+class Job(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("p", C.c_int32),
+                ("ne", C.c_int64 * 3), ("u", C.c_void_p), ("out0", C.c_void_p),
+                ("out1", C.c_void_p), ("dt", C.c_double), ("sin_amp", C.c_double),
+                ("nsteps", C.c_int32)]
+
+
+class IGAError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+# (name, argtypes)
+_SIGS = {
+    "iga_create": [C.POINTER(MeshDesc), C.c_void_p, C.POINTER(C.c_void_p)],
+    "iga_destroy": [C.c_void_p],
+    "iga_shape": [C.c_void_p, C.c_int32, C.c_int64 * 3, C.c_int64 * 3],
+    "iga_assemble": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
+    "iga_rhs": [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                C.POINTER(Source), C.c_void_p],
+    "iga_apply": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+    "iga_explicit_step": [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Source), C.c_int32],
+    "iga_strerror": [C.c_int],
+    "iga_batch_create": [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
+    "iga_batch_submit": [C.c_void_p, C.POINTER(Job), C.c_int32, C.POINTER(C.c_uint64)],
+    "iga_batch_flush": [C.c_void_p],
+    "iga_batch_poll": [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)],
+    "iga_batch_wait": [C.c_void_p],
+    "iga_batch_destroy": [C.c_void_p],
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.argtypes = args
+            fn.restype = C.c_char_p if name == "iga_strerror" else C.c_int
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list:
+    L = lib()
+    return [n for n in _SIGS if hasattr(L, n)]
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().iga_strerror(code).decode()
+    except Exception:  # library missing: still report the number
+        return f"error {code}"
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != IGA_OK:
+        raise IGAError(rc, where)
+
+
+# ---- raw C calls (same names as the C ABI) -------------------------------------
+
+def iga_create(desc: MeshDesc, stream: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().iga_create(C.byref(desc), C.c_void_p(stream), C.byref(h)), "iga_create")
+    return h
+
+
+def iga_destroy(h) -> None:
+    _check(lib().iga_destroy(h), "iga_destroy")
+
+
+def iga_shape(h, form: int) -> Tuple[Tuple[int, ...], Tuple[int, ...]]:
+    rows, cols = (C.c_int64 * 3)(), (C.c_int64 * 3)()
+    _check(lib().iga_shape(h, form, rows, cols), "iga_shape")
+    return tuple(rows), tuple(cols)
+
+
+def iga_assemble(h, form: int, op: int, bands_ptr: int) -> None:
+    _check(lib().iga_assemble(h, form, op, C.c_void_p(bands_ptr)), "iga_assemble")
+
+
+def iga_rhs(h, form: int, u_ptr: Optional[int], alpha: float, beta: float, gamma: float,
+            src: Optional[Source], b_ptr: int) -> None:
+    _check(lib().iga_rhs(h, form, C.c_void_p(u_ptr) if u_ptr else None, alpha, beta, gamma,
+                         C.byref(src) if src is not None else None, C.c_void_p(b_ptr)),
+           "iga_rhs")
+
+
+def iga_apply(h, form: int, u_ptr: int, mass_ptr: Optional[int], lap_ptr: Optional[int]) -> None:
+    _check(lib().iga_apply(h, form, C.c_void_p(u_ptr), C.c_void_p(mass_ptr) if mass_ptr else None,
+                           C.c_void_p(lap_ptr) if lap_ptr else None), "iga_apply")
+
+
+def iga_explicit_step(h, u_ptr: int, dt: float, src: Optional[Source], nsteps: int) -> None:
+    _check(lib().iga_explicit_step(h, C.c_void_p(u_ptr), dt,
+                                   C.byref(src) if src is not None else None, nsteps),
+           "iga_explicit_step")
+
+
+# ---- torch convenience layer ----------------------------------------------------
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    import torch
+    if t is None:
+        return 0
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return int(t.data_ptr())
+
+
+class Mesh:
+    """One context: a tensor-product B-spline space with its Gauss rule and spans.
+
+    ne, nq, lo, hi are per axis in (x, y, z) order.  ``spans`` is "support",
+    "element" or a list of per-axis (first, last) integer arrays (custom)."""
+
+    def __init__(self, dim: int, p: int, ne: Sequence[int], nq: Sequence[int],
+                 lo: Optional[Sequence[float]] = None, hi: Optional[Sequence[float]] = None,
+                 spans="support", stream=None):
+        import numpy as np
+        self.stream = stream
+        d = MeshDesc()
+        d.dim, d.p = dim, p
+        lo = list(lo) if lo is not None else [0.0] * dim
+        hi = list(hi) if hi is not None else [1.0] * dim
+        self._keep = []
+        for a in range(3):
+            real = a < dim
+            d.ne[a] = int(ne[a]) if real else 1
+            d.nq[a] = int(nq[a]) if real else 1
+            d.lo[a] = float(lo[a]) if real else 0.0
+            d.hi[a] = float(hi[a]) if real else 1.0
+        if isinstance(spans, str):
+            d.spans = {"support": SPANS_SUPPORT, "element": SPANS_ELEMENT}[spans]
+        else:
+            d.spans = SPANS_CUSTOM
+            for a in range(dim):
+                f = np.ascontiguousarray(spans[a][0], dtype=np.int64)
+                l = np.ascontiguousarray(spans[a][1], dtype=np.int64)
+                self._keep += [f, l]
+                d.nspan[a] = len(f)
+                d.span_first[a] = f.ctypes.data_as(_P64)
+                d.span_last[a] = l.ctypes.data_as(_P64)
+        self.dim, self.p = dim, p
+        self.ne = tuple(int(v) for v in ne[:dim])
+        self.nq = tuple(int(v) for v in nq[:dim])
+        self.h = iga_create(d, _stream_handle(stream))
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            iga_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, form: int) -> Tuple[int, ...]:
+        rows, _ = iga_shape(self.h, form)
+        return tuple(reversed(rows[: self.dim]))
+
+    def coef_shape(self) -> Tuple[int, ...]:
+        _, cols = iga_shape(self.h, PG)
+        return tuple(reversed(cols[: self.dim]))
+
+    def _new(self, shape):
+        import torch
+        return torch.empty(shape, dtype=torch.float64, device="cuda")
+
+    def _src(self, f_table, sin_amp) -> Optional[Source]:
+        if f_table is None and sin_amp == 0.0:
+            return None
+        s = Source()
+        s.table = C.c_void_p(_ptr(f_table)) if f_table is not None else None
+        s.sin_amp = float(sin_amp)
+        return s
+
+    def rhs(self, form: int, u=None, alpha: float = 0.0, beta: float = 0.0, gamma: float = 0.0,
+            f_table=None, sin_amp: float = 0.0, out=None):
+        b = out if out is not None else self._new(self.shape(form))
+        iga_rhs(self.h, form, _ptr(u) if u is not None else 0, alpha, beta, gamma,
+                self._src(f_table, sin_amp), _ptr(b))
+        return b
+
+    def apply(self, form: int, u, mass: bool = True, lap: bool = True, out_mass=None, out_lap=None):
+        m = out_mass if out_mass is not None else (self._new(self.shape(form)) if mass else None)
+        l = out_lap if out_lap is not None else (self._new(self.shape(form)) if lap else None)
+        iga_apply(self.h, form, _ptr(u), _ptr(m) if m is not None else 0,
+                  _ptr(l) if l is not None else 0)
+        return m, l
+
+    def explicit_step(self, u, dt: float, f_table=None, sin_amp: float = 0.0, nsteps: int = 1):
+        """In place on u (returned)."""
+        iga_explicit_step(self.h, _ptr(u), dt, self._src(f_table, sin_amp), nsteps)
+        return u
+
+    def assemble(self, form: int, op: int = OP_LAPLACE):
+        """Banded factors, tensor of shape (dim, 2, Rmax, 2p+1)."""
+        import torch
+        rows, _ = iga_shape(self.h, form)
+        rmax = max(rows[: self.dim])
+        bands = torch.zeros((self.dim, 2, rmax, 2 * self.p + 1), dtype=torch.float64, device="cuda")
+        iga_assemble(self.h, form, op, _ptr(bands))
+        return bands
+
+
+def bands_to_dense(band, nrows: int, ncols: int, p: int):
+    """Host helper: one banded factor (Rmax, 2p+1) -> dense (nrows, ncols) numpy array."""
+    import numpy as np
+    band = np.asarray(band)
+    out = np.zeros((nrows, ncols))
+    for r in range(nrows):
+        for k in range(2 * p + 1):
+            c = r + k - p
+            if 0 <= c < ncols:
+                out[r, c] = band[r, k]
+    return out
