@@ -1,0 +1,180 @@
+"""Benchmark: Gauss-points/s of the Petrov-Galerkin generation on one MI355X.
+
+Workload (default): 2D Laplace, quadratic C1 tensor B-splines, 1024 x 1024 elements on
+the unit square, 3 x 3 Gauss points per element, FP64, seeded N(0,1) coefficients.
+One step = one fused matrix-free apply with support spans:
+    mass_r = int_{S_r} u_h,   lap_r = int_{S_r} Lap u_h     (both written)
+which touches every one of the 9,437,184 Gauss points' contributions once
+(sum-factorized).  Algorithmic HBM bytes per step: read u (1026^2 doubles) and write
+two row arrays = 24 B per coefficient = 25.26 MB.
+
+The K timed steps run as one replay of a HIP graph holding K launches, cycling
+through enough distinct (u, mass, lap) buffer sets (>= 512 MB) that the 256 MB
+Infinity Cache cannot hold the working set: inputs are resident in HBM when the
+timed region starts.
+
+Prints one JSON line (rank 0).  --gpus above 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
+GP_C2 = 1024 * 1024 * 9
+BYTES_C2 = 1026 * 1026 * 24
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1910_08535_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(args) -> dict:
+    """The oracle (test infrastructure) on the host cores: the full 1024^2 workload,
+    mass rows and Laplacian rows (two oracle passes over every Gauss point), best of 3."""
+    from oracle import oracle as orc
+    from paper_1910_08535_amd import inputs
+    c = inputs.Apply2D()
+    u = c.coefs()
+    pb = orc.Problem(dim=2, p=c.p, ne=c.ne, nq=c.nq)
+    best = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        orc.rhs(pb, orc.PG, u, alpha=1.0)
+        orc.rhs(pb, orc.PG, u, beta=1.0)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return {"value": GP_C2 / best, "unit": "GP/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": "full 1024x1024 p=2 workload (mass and Laplacian PG rows), best of 3 runs, "
+                      f"{best:.3f} s each"}
+
+
+def run_c2(args):
+    import torch
+    from paper_1910_08535_amd import iga, inputs
+
+    c = inputs.Apply2D()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    mesh = iga.Mesh(2, c.p, c.ne, c.nq, stream=stream)
+    u0 = torch.from_numpy(c.coefs()).to("cuda")
+    set_bytes = BYTES_C2
+    nsets = max(1, -(-args.rotate_mb * 2**20 // set_bytes))
+    sets = []
+    for _ in range(nsets):
+        sets.append((u0.clone(), torch.empty_like(u0), torch.empty_like(u0)))
+    torch.cuda.synchronize()
+
+    def step(k):
+        u, m, l = sets[k % nsets]
+        mesh.apply(iga.PG, u, out_mass=m, out_lap=l)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for k in range(args.steps):
+            step(k)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    graph.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    per_launch_s = gpu_ms * 1e-3 / args.steps
+
+    # results of the timed launches against a fresh single launch (same kernel)
+    u, m, l = sets[(args.steps - 1) % nsets]
+    m2, l2 = mesh.apply(iga.PG, u)
+    torch.cuda.synchronize()
+    assert torch.equal(m, m2) and torch.equal(l, l2)
+
+    achieved = BYTES_C2 / per_launch_s / 1e9
+    traffic = measured_traffic("apply2d_p2_1024")
+    out = {
+        "metric": "RHS Gauss-points/s (PG fused mass+Laplacian apply)",
+        "value": GP_C2 * args.steps / wall,
+        "unit": "GP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded N(0,1) coefficients)",
+        "config": {"workload": "2D Laplace, quadratic C1 B-splines, 1024x1024 elements, "
+                               "3x3 Gauss, FP64, PG fused apply (mass + Laplacian rows), "
+                               "support spans",
+                   "elements": [1024, 1024], "p": 2, "nq": [3, 3],
+                   "gauss_points_per_step": GP_C2, "buffer_sets": nsets,
+                   "rotated_bytes": nsets * set_bytes},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "iga::apply2d_kernel<2, 8, 3, true>",
+                     "algorithmic_bytes_per_launch": BYTES_C2,
+                     "avg_launch_us": per_launch_s * 1e6},
+    }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--rotate-mb", type=int, default=600,
+                    help="distinct buffer bytes cycled through (defeats the Infinity Cache)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+    out = run_c2(args)
+    if rank == 0 and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

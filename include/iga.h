@@ -151,6 +151,23 @@ int iga_apply(iga_ctx *ctx, int32_t form, const double *u, double *mass_out, dou
    Errors: IGA_E_INVAL (also for other span kinds), IGA_E_NOMEM. */
 int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, int32_t nsteps);
 
+/* Tile configuration of the context's kernels (what the autotuner varies).  A setting
+   fixes the order of every sum, so results are reproducible for a given setting; other
+   settings differ from it by round-off only.  Keys:
+     IGA_TILE_2D_ROWS    output rows per 2D wave chunk of 128 columns: 2, 4, 8 (default) or 16
+     IGA_TILE_2D_ORDER   2D chunk order: 0 = XCD-aware, row bands first (default);
+                         1 = XCD-aware, strips first; 2 = plain dispatch order
+     IGA_TILE_3D_PLANES  output planes per 3D z-chunk: 1..32, 0 = automatic (default)
+     IGA_TILE_3D_SHAPE   3D in-plane tile: 0 = 32 x 16 (default), 1 = 64 x 8
+   Changing a setting drops the context's cached graph.
+   Errors: IGA_E_INVAL (unknown key or value). */
+#define IGA_TILE_2D_ROWS 1
+#define IGA_TILE_3D_PLANES 2
+#define IGA_TILE_3D_SHAPE 4
+#define IGA_TILE_2D_ORDER 5
+int iga_set_tile(iga_ctx *ctx, int32_t key, int32_t value);
+int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);
+
 /* Error string of an IGA_* code (static storage). */
 const char *iga_strerror(int code);
 

@@ -24,32 +24,34 @@
 
 namespace iga {
 
+// Output modes (template parameter of the kernels): which arrays a launch writes.
+enum : int {
+    kOut = 1,       // out_r = alpha mass + beta lap  [with the terms below]
+    kMass = 2,      // omass_r = mass
+    kFarr = 4,      // add garr * farr_r
+    kScaleSrc = 8   // out_r = S(r) ( ... + gsep prod_a F_a(r_a) ): scaled rows / separable source
+};
+
+// S and F always point at real tables (a table of ones where the launch has none), so
+// the only branches left are the compile-time output modes.
+template <int MODE>
 __device__ __forceinline__ void finish_row(const ApplyArgs& g, size_t idx, double mass, double lap,
                                            double scale, double fsep)
 {
-    if (g.omass) g.omass[idx] = mass;
-    if (g.out) {
-        double v = g.alpha * mass + g.beta * lap;
-        if (g.gsep != 0.0) v += g.gsep * fsep;
-        if (g.farr) v += g.garr * g.farr[idx];
-        g.out[idx] = scale * v;
+    if constexpr ((MODE & kMass) != 0) g.omass[idx] = mass;
+    if constexpr ((MODE & kOut) != 0) {
+        double v = fma(g.alpha, mass, g.beta * lap);
+        if constexpr ((MODE & kScaleSrc) != 0) v = fma(g.gsep, fsep, v);
+        if constexpr ((MODE & kFarr) != 0) v = fma(g.garr, g.farr[idx], v);
+        if constexpr ((MODE & kScaleSrc) != 0) v *= scale;
+        g.out[idx] = v;
     }
-}
-
-__device__ __forceinline__ double axis_scale(const AxisOp& a, int r)
-{
-    return a.S ? a.S[r] : 1.0;
-}
-
-__device__ __forceinline__ double axis_src(const AxisOp& a, int r)
-{
-    return a.F ? a.F[r] : 1.0;
 }
 
 // ---------------------------------------------------------------------------------
 // 1D: one thread per row, coefficients through the L1/L2 caches.
 // ---------------------------------------------------------------------------------
-template <int P>
+template <int P, int MODE>
 __global__ __launch_bounds__(kBlock) void apply1d_kernel(ApplyArgs g)
 {
     constexpr int W = 2 * P + 1;
@@ -64,130 +66,473 @@ __global__ __launch_bounds__(kBlock) void apply1d_kernel(ApplyArgs g)
         m = fma(X.M[(size_t)r * W + k], uj, m);
         d = fma(X.D[(size_t)r * W + k], uj, d);
     }
-    finish_row(g, r, m, d, axis_scale(X, r), axis_src(X, r));
+    finish_row<MODE>(g, r, m, d, X.S[r], X.F[r]);
 }
 
 // ---------------------------------------------------------------------------------
-// Shared pieces of the 2D / 3D tiles: a plane tile of (TY+2P) x (TX+2P) coefficients
-// in LDS, the x pass into LDS, and the y pass of one output row.
+// Shared pieces of the 2D / 3D kernels.
+//
+// A TX x TY output tile of one plane is processed by kBlock threads: thread t owns
+// column t % TX and rows t / TX + m * (kBlock / TX).  Its input is the coefficient tile
+// of (TY+2P) x (TX+2P) values, staged in LDS.
 // ---------------------------------------------------------------------------------
 template <int P, int TX, int TY>
-struct PlaneTile {
+struct Tile {
     static constexpr int W = 2 * P + 1;
     static constexpr int HX = TX + 2 * P;
     static constexpr int HY = TY + 2 * P;
+    static constexpr int RPP = kBlock / TX;                  // rows per pass
+    static constexpr int NXR = (HY + RPP - 1) / RPP;         // x-pass rows per thread
+    static constexpr int Q = TY / RPP;                       // output rows per thread
+    static constexpr int NL = (HY * HX + kBlock - 1) / kBlock;   // tile values per thread
+    static constexpr int NC = (TY * (2 * W + 2) + kBlock - 1) / kBlock;   // band values per thread
+    static_assert(kBlock % TX == 0 && TY % RPP == 0, "tile shape");
 };
 
-// Loads the coefficient plane rows y0-P .. y0+TY+P-1, columns x0-P .. x0+TX+P-1 of
-// `plane` (Ny x Nx, x fastest) into su; zero outside the array.
+// The coefficient tile of one plane through registers.  issue() puts every global load
+// of the tile in flight; store() (which waits for them) moves the values to LDS.
+// Interior tiles use per-thread offsets computed once; tiles that touch the array's
+// edge clamp every index into the array (the clamped values only ever meet band
+// entries that are exactly zero, so they contribute nothing).
 template <int P, int TX, int TY>
-__device__ __forceinline__ void load_plane(double* __restrict__ su, const double* __restrict__ plane,
-                                           int x0, int y0, int Nx, int Ny)
+struct TileRegs {
+    using T = Tile<P, TX, TY>;
+    double v[T::NL];
+
+    __device__ __forceinline__ void issue(const double* __restrict__ plane, const int (&rel)[T::NL],
+                                          int x0, int y0, int Nx, int Ny)
+    {
+        const bool inner = x0 >= P && y0 >= P && x0 + TX + P <= Nx && y0 + TY + P <= Ny;
+        if (inner) {
+            const double* __restrict__ base = plane + ((size_t)(y0 - P) * Nx + (x0 - P));
+#pragma unroll
+            for (int j = 0; j < T::NL; ++j) v[j] = base[rel[j]];
+        } else {
+#pragma unroll
+            for (int j = 0; j < T::NL; ++j) {
+                const int i = min((int)threadIdx.x + j * kBlock, T::HY * T::HX - 1);
+                const int iy = i / T::HX, ix = i - iy * T::HX;
+                const int gy = min(max(y0 - P + iy, 0), Ny - 1);
+                const int gx = min(max(x0 - P + ix, 0), Nx - 1);
+                v[j] = plane[(size_t)gy * Nx + gx];
+            }
+        }
+    }
+
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int j = 0; j < T::NL; ++j) v[j] = 0.0;
+    }
+
+    __device__ __forceinline__ void store(double* __restrict__ su) const
+    {
+#pragma unroll
+        for (int j = 0; j < T::NL; ++j) {
+            const int i = (int)threadIdx.x + j * kBlock;
+            if (j < T::NL - 1 || i < T::HY * T::HX) su[i] = v[j];
+        }
+    }
+};
+
+// rel[j] = iy * Nx + ix of this thread's j-th tile value (index clamped into the tile)
+template <int P, int TX, int TY, int NL>
+__device__ __forceinline__ void tile_offsets(int (&rel)[NL], int Nx)
 {
-    using T = PlaneTile<P, TX, TY>;
-    for (int i = threadIdx.x; i < T::HY * T::HX; i += kBlock) {
-        const int iy = i / T::HX, ix = i - iy * T::HX;
-        const int gy = y0 - P + iy, gx = x0 - P + ix;
-        double v = 0.0;
-        if (gy >= 0 && gy < Ny && gx >= 0 && gx < Nx) v = plane[(size_t)gy * Nx + gx];
-        su[i] = v;
+    using T = Tile<P, TX, TY>;
+    static_assert(NL == T::NL, "offset count");
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const int i = min((int)threadIdx.x + j * kBlock, T::HY * T::HX - 1);
+        const int iy = i / T::HX;
+        rel[j] = iy * Nx + (i - iy * T::HX);
     }
 }
 
-// x pass over all HY rows of the tile: A = Mx u, B = Dx u for this lane's column.
+// Per-column x factors of one tile column (registers) and the per-row band rows of the
+// tile's TY output rows (loaded into registers, one or two values per thread, then
+// published through LDS).
+template <int P, int TX, int TY>
+struct TileCoefs {
+    using T = Tile<P, TX, TY>;
+    static constexpr int W = T::W;
+    double mx[W], dx[W], sx, fx;
+    double cv[T::NC];
+
+    __device__ __forceinline__ void issue(const AxisOp& X, const AxisOp& Y, int x0, int y0)
+    {
+        const int gx = x0 + (int)threadIdx.x % TX;
+        const bool ok = gx < X.R;
+        const int r = ok ? gx : 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            mx[k] = X.M[(size_t)r * W + k];
+            dx[k] = X.D[(size_t)r * W + k];
+        }
+        sx = X.S[r];
+        fx = X.F[r];
+        if (!ok) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) mx[k] = dx[k] = 0.0;
+            sx = fx = 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < T::NC; ++c) {
+            const int i = (int)threadIdx.x + c * kBlock;
+            const int row = i / (2 * W + 2), k = i - row * (2 * W + 2);
+            const int yr = min(y0 + row, Y.R - 1);
+            double v = 0.0;
+            if (k < W)
+                v = Y.M[(size_t)yr * W + k];
+            else if (k < 2 * W)
+                v = Y.D[(size_t)yr * W + (k - W)];
+            else if (k == 2 * W)
+                v = Y.S[yr];
+            else
+                v = Y.F[yr];
+            cv[c] = (y0 + row < Y.R && i < TY * (2 * W + 2)) ? v : 0.0;
+        }
+    }
+
+    // rows of the tile: cM[row*W+k], cD[row*W+k], cS[row], cF[row]
+    __device__ __forceinline__ void publish(double* cM, double* cD, double* cS, double* cF) const
+    {
+#pragma unroll
+        for (int c = 0; c < T::NC; ++c) {
+            const int i = (int)threadIdx.x + c * kBlock;
+            if (i >= TY * (2 * W + 2)) continue;
+            const int row = i / (2 * W + 2), k = i - row * (2 * W + 2);
+            if (k < W)
+                cM[row * W + k] = cv[c];
+            else if (k < 2 * W)
+                cD[row * W + (k - W)] = cv[c];
+            else if (k == 2 * W)
+                cS[row] = cv[c];
+            else
+                cF[row] = cv[c];
+        }
+    }
+};
+
+// x pass: A = Mx u, B = Dx u on all HY rows of the tile, this thread's column.
 template <int P, int TX, int TY>
 __device__ __forceinline__ void x_pass(const double* __restrict__ su, double* __restrict__ sA,
                                        double* __restrict__ sB, const double (&mx)[2 * P + 1],
-                                       const double (&dx)[2 * P + 1], int lane, int wave)
+                                       const double (&dx)[2 * P + 1])
 {
-    using T = PlaneTile<P, TX, TY>;
-    for (int iy = wave; iy < T::HY; iy += kBlock / 64) {
-        double a = 0.0, b = 0.0;
+    using T = Tile<P, TX, TY>;
+    const int c = (int)threadIdx.x % TX, r0 = (int)threadIdx.x / TX;
 #pragma unroll
-        for (int k = 0; k < T::W; ++k) {
-            const double v = su[iy * T::HX + lane + k];
-            a = fma(mx[k], v, a);
-            b = fma(dx[k], v, b);
+    for (int m = 0; m < T::NXR; ++m) {
+        const int r = r0 + m * T::RPP;
+        if (r < T::HY) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int k = 0; k < T::W; ++k) {
+                const double v = su[r * T::HX + c + k];
+                a = fma(mx[k], v, a);
+                b = fma(dx[k], v, b);
+            }
+            sA[r * TX + c] = a;
+            sB[r * TX + c] = b;
         }
-        sA[iy * TX + lane] = a;
-        sB[iy * TX + lane] = b;
+    }
+}
+
+// Band rows r0 .. r0+n-1 of one axis staged in LDS (used for the z rows of a 3D chunk).
+template <int W>
+__device__ __forceinline__ void stage_band_rows(double* __restrict__ cM, double* __restrict__ cD,
+                                                double* __restrict__ cS, double* __restrict__ cF,
+                                                const AxisOp& A, int r0, int n)
+{
+    for (int i = threadIdx.x; i < n * (2 * W + 2); i += kBlock) {
+        const int row = i / (2 * W + 2), k = i - row * (2 * W + 2);
+        const int r = r0 + row;
+        const bool ok = r < A.R;
+        double v;
+        if (k < W)
+            v = ok ? A.M[(size_t)r * W + k] : 0.0;
+        else if (k < 2 * W)
+            v = ok ? A.D[(size_t)r * W + (k - W)] : 0.0;
+        else if (k == 2 * W)
+            v = ok ? A.S[r] : 0.0;
+        else
+            v = ok ? A.F[r] : 0.0;
+        if (k < W)
+            cM[row * W + k] = v;
+        else if (k < 2 * W)
+            cD[row * W + (k - W)] = v;
+        else if (k == 2 * W)
+            cS[row] = v;
+        else
+            cF[row] = v;
     }
 }
 
 // ---------------------------------------------------------------------------------
-// 2D: output tile of 64 x TY rows; one lane per output column.
+// Buffer addressing.  A buffer resource carries the array's size; the hardware returns
+// 0 for loads outside it and drops stores outside it, so edge tiles need no branches:
+// an index outside the array is given the offset kOOB.
 // ---------------------------------------------------------------------------------
-template <int P, int TY>
-__global__ __launch_bounds__(kBlock) void apply2d_kernel(ApplyArgs g, TileGrid tg)
+typedef int iv2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kOOB = 0xffffffffu;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* p, size_t n_doubles)
 {
-    constexpr int TX = 64;
-    using T = PlaneTile<P, TX, TY>;
-    constexpr int W = T::W;
-    __shared__ double su[T::HY * T::HX];
-    __shared__ double sA[T::HY * TX];
-    __shared__ double sB[T::HY * TX];
+    const size_t bytes = n_doubles * sizeof(double);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                             (int)(bytes > 0xffffffffull ? 0xffffffffull : bytes),
+                                             0x00020000);
+}
 
-    const AxisOp X = g.ax[0], Y = g.ax[1];
-    const int L = xcd_logical_block(blockIdx.x, tg.nblk);
-    const int bx = L % tg.tx, by = L / tg.tx;
-    const int x0 = bx * TX, y0 = by * TY;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned byte_off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
 
-    load_plane<P, TX, TY>(su, g.u, x0, y0, X.N, Y.N);
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2, v), r, (int)byte_off, 0, 0);
+}
 
-    const int gx = x0 + lane;
-    const bool colok = gx < X.R;
-    double mx[W], dx[W];
+typedef int iv4 __attribute__((ext_vector_type(4)));
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ dv2 bload2(__amdgpu_buffer_rsrc_t r, unsigned byte_off)
+{
+    return __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+}
+
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double a, double b)
+{
+    dv2 v;
+    v.x = a;
+    v.y = b;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4, v), r, (int)byte_off, 0, 0);
+}
+
+// byte offset of element (row, col) of a rows x cols array, kOOB outside it
+__device__ __forceinline__ unsigned boff(int row, int col, int rows, int cols)
+{
+    return (row >= 0 && row < rows && col >= 0 && col < cols)
+               ? (unsigned)(((unsigned)row * (unsigned)cols + (unsigned)col) * 8u)
+               : kOOB;
+}
+
+// ---------------------------------------------------------------------------------
+// 2D: one wave per workgroup handles a strip of 128 output columns (two adjacent
+// columns per lane) over a chunk of TY output rows.
+//   1. all TY+2P input rows of the chunk are requested at once (128 values plus a halo
+//      of P on each side per row; buffer bounds zero whatever lies outside u);
+//   2. each row lands in an LDS row buffer as soon as its loads are in;
+//   3. per row, the x pass (A = Mx u, B = Dx u) reads the lane's 2P+2 neighbours with
+//      128-bit LDS reads; the last 2P+1 rows of (A, B) stay in a register ring and the
+//      y pass (mass = My A, lap = Dy A + My B) forms one output row per input row.
+// The row loop is unrolled at compile time (ring slots are registers, memory counters
+// exact) and the code is branch-free: halo lanes, array edges and the band rows of
+// the chunk are all handled by buffer bounds and spare LDS slots.
+// ---------------------------------------------------------------------------------
+template <int P, int TY, int MODE, bool VEC>
+__global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
+{
+    constexpr int W = 2 * P + 1;
+    constexpr int NR = TY + 2 * P;          // input rows of a chunk
+    constexpr int SW = 128;                 // strip width
+    constexpr int RBW = SW + 2 * P + 2;     // columns x0-P .. x0+SW+P-1 and 2 spare slots
+    constexpr int CW = 2 * W + 2;           // band values per row: M[W], D[W], S, F
+    constexpr int NCV = (TY * CW + 63) / 64;
+    static_assert(RBW % 2 == 0 && CW % 2 == 0, "16-byte LDS rows");
+    __shared__ __attribute__((aligned(16))) double rb[NR][RBW];
+    __shared__ __attribute__((aligned(16))) double cy[NCV * 64];
+
+    const AxisOp &X = g.ax[0], &Y = g.ax[1];
+    // tg.TZ selects the block order (tuning): 0 = XCD-aware, row bands consecutive;
+    // 1 = XCD-aware, strips consecutive; 2 = dispatch order, row bands consecutive
+    const int L = tg.TZ == 2 ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, tg.nblk);
+    const int bx = tg.TZ == 1 ? L / tg.ty : L % tg.tx;
+    const int by = tg.TZ == 1 ? L % tg.ty : L / tg.tx;
+    const int x0 = bx * SW, y0 = by * TY;
+    const int lane = threadIdx.x;
+    const int Nx = X.N, Ny = Y.N;
+
+    // x factors of the lane's two output columns
+    const int c0 = x0 + 2 * lane;   // the lane's first column
+    const int xr0 = c0, xr1 = c0 + 1;
+    const auto rxm = buf(X.M, (size_t)X.R * W), rxd = buf(X.D, (size_t)X.R * W);
+    double m0[W], d0[W], m1[W], d1[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        mx[k] = colok ? X.M[(size_t)gx * W + k] : 0.0;
-        dx[k] = colok ? X.D[(size_t)gx * W + k] : 0.0;
+        m0[k] = bload(rxm, xr0 < X.R ? (unsigned)(xr0 * W + k) * 8u : kOOB);
+        d0[k] = bload(rxd, xr0 < X.R ? (unsigned)(xr0 * W + k) * 8u : kOOB);
+        m1[k] = bload(rxm, xr1 < X.R ? (unsigned)(xr1 * W + k) * 8u : kOOB);
+        d1[k] = bload(rxd, xr1 < X.R ? (unsigned)(xr1 * W + k) * 8u : kOOB);
     }
-    const double sx = colok ? axis_scale(X, gx) : 0.0;
-    const double fx = colok ? axis_src(X, gx) : 0.0;
-    __syncthreads();
-    x_pass<P, TX, TY>(su, sA, sB, mx, dx, lane, wave);
-    __syncthreads();
+    double sx0 = 1.0, sx1 = 1.0, fx0 = 1.0, fx1 = 1.0;
+    if constexpr ((MODE & kScaleSrc) != 0) {
+        const auto rxs = buf(X.S, X.R), rxf = buf(X.F, X.R);
+        sx0 = bload(rxs, xr0 < X.R ? (unsigned)xr0 * 8u : kOOB);
+        sx1 = bload(rxs, xr1 < X.R ? (unsigned)xr1 * 8u : kOOB);
+        fx0 = bload(rxf, xr0 < X.R ? (unsigned)xr0 * 8u : kOOB);
+        fx1 = bload(rxf, xr1 < X.R ? (unsigned)xr1 * 8u : kOOB);
+    }
+    // band rows of the chunk: cy[j*CW + k]; every lane loads from each table with the
+    // offset of the table that holds value k (the others read 0 out of bounds)
+    {
+        const auto rym = buf(Y.M, (size_t)Y.R * W), ryd = buf(Y.D, (size_t)Y.R * W);
+        const auto rys = buf(Y.S, Y.R), ryf = buf(Y.F, Y.R);
+        double cv[NCV];
+#pragma unroll
+        for (int c = 0; c < NCV; ++c) {
+            const int i = lane + 64 * c;
+            const int j = i / CW, k = i - j * CW;
+            const int yr = y0 + j;
+            const bool ok = i < TY * CW && yr < Y.R;
+            const unsigned om = ok && k < W ? (unsigned)(yr * W + k) * 8u : kOOB;
+            const unsigned od = ok && k >= W && k < 2 * W ? (unsigned)(yr * W + k - W) * 8u : kOOB;
+            const unsigned os = ok && k == 2 * W ? (unsigned)yr * 8u : kOOB;
+            const unsigned of = ok && k == 2 * W + 1 ? (unsigned)yr * 8u : kOOB;
+            cv[c] = bload(rym, om) + bload(ryd, od) + bload(rys, os) + bload(ryf, of);
+        }
+#pragma unroll
+        for (int c = 0; c < NCV; ++c) cy[lane + 64 * c] = cv[c];
+    }
 
-    for (int oy = wave; oy < TY; oy += kBlock / 64) {
-        const int gy = y0 + oy;
-        if (gy >= Y.R) break;
-        double mass = 0.0, lapy = 0.0, lapx = 0.0;
+    // 1. input rows (issued after the band loads: the memory counter retires in
+    //    order, so the first FMA then waits for its factors, not for every row): the lane's two columns and one halo column (lanes < 2P)
+    const auto ru = buf(g.u, (size_t)Nx * Ny);
+    const int ch = lane < P ? x0 - P + lane : x0 + SW + lane - P;
+    const bool ok0 = c0 < Nx, ok1 = c0 + 1 < Nx, okh = lane < 2 * P && ch >= 0 && ch < Nx;
+    double v0[NR], v1[NR], vh[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int yi = y0 - P + i;
+        const bool rowok = yi >= 0 && yi < Ny;
+        const unsigned rowoff = (unsigned)yi * (unsigned)Nx;
+        if constexpr (VEC) {   // rows of even length: the lane's pair is 16-byte aligned
+            const dv2 v = bload2(ru, rowok && ok0 ? (rowoff + c0) * 8u : kOOB);
+            v0[i] = v.x;
+            v1[i] = v.y;
+        } else {
+            v0[i] = bload(ru, rowok && ok0 ? (rowoff + c0) * 8u : kOOB);
+            v1[i] = bload(ru, rowok && ok1 ? (rowoff + c0 + 1) * 8u : kOOB);
+        }
+        vh[i] = bload(ru, rowok && okh ? (rowoff + ch) * 8u : kOOB);
+    }
+
+    // spare LDS slots take the halo value of lanes without a halo column
+    const int hidx = lane < P ? lane : (lane < 2 * P ? SW + lane : SW + 2 * P + (lane & 1));
+
+    // 3. x pass, ring, y pass, stores
+    const auto ro = buf(g.out, (size_t)X.R * Y.R);
+    const auto rm = buf(g.omass, (MODE & kMass) ? (size_t)X.R * Y.R : 0);
+    const auto rf = buf(g.farr, (MODE & kFarr) ? (size_t)X.R * Y.R : 0);
+    const bool okc0 = xr0 < X.R, okc1 = xr1 < X.R;
+    double ra0[W], rb0[W], ra1[W], rb1[W];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        // 2. row i into LDS as soon as its loads are in (later rows keep loading while
+        //    this one is computed and stored); LDS operations of one wave execute in
+        //    order, the fence only keeps the compiler from reordering them
+        rb[i][P + 2 * lane] = v0[i];
+        rb[i][P + 2 * lane + 1] = v1[i];
+        rb[i][hidx] = vh[i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double t[2 * P + 2];
+#pragma unroll
+        for (int q = 0; q < 2 * P + 2; ++q) t[q] = rb[i][2 * lane + q];
+        double a0 = 0.0, b0 = 0.0, a1 = 0.0, b1 = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            const double my = Y.M[(size_t)gy * W + k];
-            const double dy = Y.D[(size_t)gy * W + k];
-            const double a = sA[(oy + k) * TX + lane];
-            const double b = sB[(oy + k) * TX + lane];
-            mass = fma(my, a, mass);
-            lapy = fma(dy, a, lapy);
-            lapx = fma(my, b, lapx);
+            a0 = fma(m0[k], t[k], a0);
+            b0 = fma(d0[k], t[k], b0);
+            a1 = fma(m1[k], t[k + 1], a1);
+            b1 = fma(d1[k], t[k + 1], b1);
         }
-        if (colok)
-            finish_row(g, (size_t)gy * X.R + gx, mass, lapx + lapy, sx * axis_scale(Y, gy),
-                       fx * axis_src(Y, gy));
+        ra0[i % W] = a0;
+        rb0[i % W] = b0;
+        ra1[i % W] = a1;
+        rb1[i % W] = b1;
+        if (i >= 2 * P) {
+            const int j = i - 2 * P;   // output row y0 + j uses input rows j .. j + 2P
+            const double* cr = &cy[j * CW];
+            double ms0 = 0.0, ly0 = 0.0, lx0 = 0.0, ms1 = 0.0, ly1 = 0.0, lx1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const double my = cr[k], dy = cr[W + k];
+                const int sl = (j + k) % W;
+                ms0 = fma(my, ra0[sl], ms0);
+                ly0 = fma(dy, ra0[sl], ly0);
+                lx0 = fma(my, rb0[sl], lx0);
+                ms1 = fma(my, ra1[sl], ms1);
+                ly1 = fma(dy, ra1[sl], ly1);
+                lx1 = fma(my, rb1[sl], lx1);
+            }
+            const bool rowok = y0 + j < Y.R;
+            const unsigned ob = (unsigned)((y0 + j) * X.R + xr0) * 8u;
+            const unsigned o0 = rowok && okc0 ? ob : kOOB;
+            const unsigned o1 = rowok && okc1 ? ob + 8u : kOOB;
+            if constexpr ((MODE & kMass) != 0) {
+                if constexpr (VEC) {
+                    bstore2(rm, o0, ms0, ms1);
+                } else {
+                    bstore(rm, o0, ms0);
+                    bstore(rm, o1, ms1);
+                }
+            }
+            double w0 = fma(g.alpha, ms0, g.beta * (lx0 + ly0));
+            double w1 = fma(g.alpha, ms1, g.beta * (lx1 + ly1));
+            if constexpr ((MODE & kScaleSrc) != 0) {
+                w0 = fma(g.gsep, fx0 * cr[2 * W + 1], w0);
+                w1 = fma(g.gsep, fx1 * cr[2 * W + 1], w1);
+            }
+            if constexpr ((MODE & kFarr) != 0) {
+                if constexpr (VEC) {
+                    const dv2 f = bload2(rf, o0);
+                    w0 = fma(g.garr, f.x, w0);
+                    w1 = fma(g.garr, f.y, w1);
+                } else {
+                    w0 = fma(g.garr, bload(rf, o0), w0);
+                    w1 = fma(g.garr, bload(rf, o1), w1);
+                }
+            }
+            if constexpr ((MODE & kScaleSrc) != 0) {
+                w0 *= sx0 * cr[2 * W];
+                w1 *= sx1 * cr[2 * W];
+            }
+            if constexpr (VEC) {
+                bstore2(ro, o0, w0, w1);
+            } else {
+                bstore(ro, o0, w0);
+                bstore(ro, o1, w1);
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------------
-// 3D: in-plane output tile of 64 x 8, streamed along z over a chunk of TZ output
+// 3D: in-plane output tile of TX x TY, streamed along z over a chunk of TZ output
 // planes.  Each input plane goes through the x pass (LDS) and the y pass; the y-pass
 // results of the last 2P+1 planes stay in a register ring from which the z pass forms
-// one output plane per input plane.
+// one output plane per input plane.  The coefficient planes flow through a second
+// register ring of 2P+1 slots: the loads of plane z+2P+1 are issued as soon as plane z
+// has been moved to LDS, so 2P+1 planes are in flight while one is computed.
 // ---------------------------------------------------------------------------------
-template <int P>
+template <int P, int TX, int TY, int MODE>
 __global__ __launch_bounds__(kBlock) void apply3d_kernel(ApplyArgs g, TileGrid tg)
 {
-    constexpr int TX = 64, TY = 8;
-    using T = PlaneTile<P, TX, TY>;
+    constexpr int MAXTZ = 32;
+    using T = Tile<P, TX, TY>;
     constexpr int W = T::W;
-    constexpr int Q = TY / (kBlock / 64);   // output rows per wave
+    constexpr int Q = T::Q;
     __shared__ double su[T::HY * T::HX];
     __shared__ double sA[T::HY * TX];
     __shared__ double sB[T::HY * TX];
+    __shared__ double yM[TY * W], yD[TY * W], yS[TY], yF[TY];
+    __shared__ double zM[MAXTZ * W], zD[MAXTZ * W], zS[MAXTZ], zF[MAXTZ];
 
-    const AxisOp X = g.ax[0], Y = g.ax[1], Z = g.ax[2];
+    const AxisOp &X = g.ax[0], &Y = g.ax[1], &Z = g.ax[2];
     const int L = xcd_logical_block(blockIdx.x, tg.nblk);
     const int bx = L % tg.tx;
     const int by = (L / tg.tx) % tg.ty;
@@ -195,20 +540,27 @@ __global__ __launch_bounds__(kBlock) void apply3d_kernel(ApplyArgs g, TileGrid t
     const int x0 = bx * TX, y0 = by * TY;
     const int z0 = bz * tg.TZ;
     const int z1 = min(z0 + tg.TZ, Z.R);
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const size_t plane_in = (size_t)X.N * Y.N;
+    const int zlo = max(z0 - P, 0);       // input planes that exist: [zlo, zhi)
+    const int zhi = min(z1 + P, Z.N);
+    const int c = (int)threadIdx.x % TX, r0 = (int)threadIdx.x / TX;
 
-    const int gx = x0 + lane;
-    const bool colok = gx < X.R;
-    double mx[W], dx[W];
+    int rel[T::NL];
+    tile_offsets<P, TX, TY, T::NL>(rel, X.N);
+    // plane z0 - P + s sits in ring slot s (mod W)
+    TileRegs<P, TX, TY> pre[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        mx[k] = colok ? X.M[(size_t)gx * W + k] : 0.0;
-        dx[k] = colok ? X.D[(size_t)gx * W + k] : 0.0;
+    for (int s = 0; s < W; ++s) {
+        const int zi = z0 - P + s;
+        if (zi >= zlo && zi < zhi)
+            pre[s].issue(g.u + (size_t)zi * plane_in, rel, x0, y0, X.N, Y.N);
+        else
+            pre[s].zero();
     }
-    const double sx = colok ? axis_scale(X, gx) : 0.0;
-    const double fx = colok ? axis_src(X, gx) : 0.0;
+    TileCoefs<P, TX, TY> co;
+    co.issue(X, Y, x0, y0);
+    co.publish(yM, yD, yS, yF);
+    stage_band_rows<W>(zM, zD, zS, zF, Z, z0, z1 - z0);
 
     double rc[W][Q], re[W][Q];
 #pragma unroll
@@ -221,29 +573,35 @@ __global__ __launch_bounds__(kBlock) void apply3d_kernel(ApplyArgs g, TileGrid t
         for (int ph = 0; ph < W; ++ph) {
             const int zi = zb + ph;
             if (zi >= z1 + P) break;
-            if (zi >= 0 && zi < Z.N) {
+            const bool have = zi >= zlo && zi < zhi;
+            if (have) {
                 // su was last read by the previous x pass, which every thread finished
-                // before the barrier that preceded the previous y pass.
-                load_plane<P, TX, TY>(su, g.u + (size_t)zi * plane_in, x0, y0, X.N, Y.N);
+                // before the barrier that precedes the previous y pass.
+                pre[ph].store(su);
                 __syncthreads();
-                x_pass<P, TX, TY>(su, sA, sB, mx, dx, lane, wave);
+            }
+            // refill this slot with plane zi + W (registers are private: no hazard even
+            // when plane zi itself lies outside the array)
+            if (zi + W >= zlo && zi + W < zhi)
+                pre[ph].issue(g.u + (size_t)(zi + W) * plane_in, rel, x0, y0, X.N, Y.N);
+            if (have) {
+                x_pass<P, TX, TY>(su, sA, sB, co.mx, co.dx);
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < Q; ++j) {
-                    const int oy = wave + j * (kBlock / 64);
-                    const int gy = min(y0 + oy, Y.R - 1);
-                    double c = 0.0, e = 0.0;
+                    const int oy = r0 + j * T::RPP;
+                    double cc = 0.0, e = 0.0;
 #pragma unroll
                     for (int k = 0; k < W; ++k) {
-                        const double my = Y.M[(size_t)gy * W + k];
-                        const double dy = Y.D[(size_t)gy * W + k];
-                        const double a = sA[(oy + k) * TX + lane];
-                        const double b = sB[(oy + k) * TX + lane];
-                        c = fma(my, a, c);
+                        const double my = yM[oy * W + k];
+                        const double dy = yD[oy * W + k];
+                        const double a = sA[(oy + k) * TX + c];
+                        const double b = sB[(oy + k) * TX + c];
+                        cc = fma(my, a, cc);
                         e = fma(dy, a, e);
                         e = fma(my, b, e);
                     }
-                    rc[ph][j] = c;
+                    rc[ph][j] = cc;
                     re[ph][j] = e;
                 }
             } else {
@@ -252,23 +610,25 @@ __global__ __launch_bounds__(kBlock) void apply3d_kernel(ApplyArgs g, TileGrid t
             }
             const int zo = zi - P;
             if (zo >= z0) {
-                const double sz = axis_scale(Z, zo), fz = axis_src(Z, zo);
+                const int iz = zo - z0;
+                const int gx = x0 + c;
 #pragma unroll
                 for (int j = 0; j < Q; ++j) {
                     double mass = 0.0, lap = 0.0;
 #pragma unroll
                     for (int k = 0; k < W; ++k) {
-                        const int s = (ph + 1 + k) % W;   // plane zo - P + k
-                        const double mz = Z.M[(size_t)zo * W + k];
-                        const double dz = Z.D[(size_t)zo * W + k];
+                        const int s = (ph + 1 + k) % W;   // ring slot of plane zo - P + k
+                        const double mz = zM[iz * W + k];
+                        const double dz = zD[iz * W + k];
                         mass = fma(mz, rc[s][j], mass);
                         lap = fma(dz, rc[s][j], lap);
                         lap = fma(mz, re[s][j], lap);
                     }
-                    const int gy = y0 + wave + j * (kBlock / 64);
-                    if (colok && gy < Y.R)
-                        finish_row(g, ((size_t)zo * Y.R + gy) * X.R + gx, mass, lap,
-                                   sx * axis_scale(Y, gy) * sz, fx * axis_src(Y, gy) * fz);
+                    const int oy = r0 + j * T::RPP;
+                    const int gy = y0 + oy;
+                    if (gx < X.R && gy < Y.R)
+                        finish_row<MODE>(g, ((size_t)zo * Y.R + gy) * X.R + gx, mass, lap,
+                                   co.sx * yS[oy] * zS[iz], co.fx * yF[oy] * zF[iz]);
                 }
             }
         }
@@ -276,6 +636,7 @@ __global__ __launch_bounds__(kBlock) void apply3d_kernel(ApplyArgs g, TileGrid t
 }
 
 // Rows without a u-term: out_r = S(r) ( gsep prod_a F_a(r_a) + garr farr_r ).
+template <int MODE>
 __global__ void rows_only_kernel(ApplyArgs g, int dim, size_t nrows)
 {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,10 +644,10 @@ __global__ void rows_only_kernel(ApplyArgs g, int dim, size_t nrows)
     const int rx = (int)(idx % g.ax[0].R);
     const int ry = dim > 1 ? (int)((idx / g.ax[0].R) % g.ax[1].R) : 0;
     const int rz = dim > 2 ? (int)(idx / ((size_t)g.ax[0].R * g.ax[1].R)) : 0;
-    double s = axis_scale(g.ax[0], rx), f = axis_src(g.ax[0], rx);
-    if (dim > 1) { s *= axis_scale(g.ax[1], ry); f *= axis_src(g.ax[1], ry); }
-    if (dim > 2) { s *= axis_scale(g.ax[2], rz); f *= axis_src(g.ax[2], rz); }
-    finish_row(g, idx, 0.0, 0.0, s, f);
+    double s = g.ax[0].S[rx], f = g.ax[0].F[rx];
+    if (dim > 1) { s *= g.ax[1].S[ry]; f *= g.ax[1].F[ry]; }
+    if (dim > 2) { s *= g.ax[2].S[rz]; f *= g.ax[2].F[rz]; }
+    finish_row<MODE>(g, idx, 0.0, 0.0, s, f);
 }
 
 __global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__ src, size_t n)

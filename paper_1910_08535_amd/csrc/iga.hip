@@ -48,6 +48,7 @@ struct iga_ctx {
     AxisTables t[3] = {};
     std::vector<void*> allocs;
     double* unit = nullptr;   // device {1, 0, 0, ...}: tables of an axis beyond dim
+    double* ones = nullptr;   // device, all 1: scale / source factors of launches without them
     int* zero = nullptr;      // device {0}
     double* farr = nullptr;
     size_t farr_n = 0;
@@ -61,6 +62,11 @@ struct iga_ctx {
     const double* g_tab = nullptr;
     double g_dt = 0, g_amp = 0;
     int g_n = 0;
+    // tile configuration
+    int ty2d = 8;
+    int order2d = 0;
+    int tz3d = 0;
+    int shape3d = 0;
 };
 
 namespace {
@@ -124,20 +130,20 @@ ApplyArgs make_args(const iga_ctx* c, int form, bool step, bool sep_source)
             if (form == IGA_PG) {
                 o.M = t.pm;
                 o.D = t.pd;
-                o.F = sep_source ? t.fs_pg : nullptr;
-                o.S = step ? t.inv_len : nullptr;
+                o.F = sep_source ? t.fs_pg : c->ones;
+                o.S = step ? t.inv_len : c->ones;
                 o.R = t.R;
             } else {
                 o.M = t.gm;
                 o.D = form == IGA_GALERKIN_LAPLACIAN ? t.gl : t.gb;
-                o.F = sep_source ? t.fs_g : nullptr;
-                o.S = nullptr;
+                o.F = sep_source ? t.fs_g : c->ones;
+                o.S = c->ones;
                 o.R = t.N;
             }
             o.N = t.N;
         } else {
             o.M = o.D = c->unit;
-            o.F = o.S = nullptr;
+            o.F = o.S = c->ones;
             o.R = o.N = 1;
         }
     }
@@ -152,43 +158,97 @@ int pick_tz(int tx, int ty, int R2)
     return TZ;
 }
 
-template <int P>
-int launch_apply_p(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
+template <int P, int TY, int MODE>
+void launch_2d(const ApplyArgs& g, hipStream_t s, int order)
+{
+    TileGrid tg;
+    tg.tx = (g.ax[0].R + 127) / 128;
+    tg.ty = (g.ax[1].R + TY - 1) / TY;
+    tg.tz = 1;
+    tg.TZ = order;
+    tg.nblk = tg.tx * tg.ty;
+    // 128-bit row accesses when every row of u and of the rows starts 16-byte aligned
+    if (g.ax[0].N % 2 == 0 && g.ax[0].R % 2 == 0)
+        hipLaunchKernelGGL((iga::apply2d_kernel<P, TY, MODE, true>), dim3(tg.nblk), dim3(64), 0, s, g,
+                           tg);
+    else
+        hipLaunchKernelGGL((iga::apply2d_kernel<P, TY, MODE, false>), dim3(tg.nblk), dim3(64), 0, s, g,
+                           tg);
+}
+
+template <int P, int TX, int TY, int MODE>
+void launch_3d(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
+{
+    TileGrid tg;
+    tg.tx = (g.ax[0].R + TX - 1) / TX;
+    tg.ty = (g.ax[1].R + TY - 1) / TY;
+    tg.TZ = c->tz3d > 0 ? c->tz3d : pick_tz(tg.tx, tg.ty, g.ax[2].R);
+    tg.tz = (g.ax[2].R + tg.TZ - 1) / tg.TZ;
+    tg.nblk = tg.tx * tg.ty * tg.tz;
+    hipLaunchKernelGGL((iga::apply3d_kernel<P, TX, TY, MODE>), dim3(tg.nblk), dim3(kBlock), 0, s,
+                       g, tg);
+}
+
+template <int P, int MODE>
+void launch_apply_pm(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
 {
     if (c->dim == 1) {
         const int grid = (g.ax[0].R + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(iga::apply1d_kernel<P>, dim3(grid), dim3(kBlock), 0, s, g);
+        hipLaunchKernelGGL((iga::apply1d_kernel<P, MODE>), dim3(grid), dim3(kBlock), 0, s, g);
     } else if (c->dim == 2) {
-        constexpr int TY = 16;
-        TileGrid tg;
-        tg.tx = (g.ax[0].R + 63) / 64;
-        tg.ty = (g.ax[1].R + TY - 1) / TY;
-        tg.tz = 1;
-        tg.TZ = 1;
-        tg.nblk = tg.tx * tg.ty;
-        hipLaunchKernelGGL((iga::apply2d_kernel<P, TY>), dim3(tg.nblk), dim3(kBlock), 0, s, g, tg);
+        if (c->ty2d == 2)
+            launch_2d<P, 2, MODE>(g, s, c->order2d);
+        else if (c->ty2d == 8)
+            launch_2d<P, 8, MODE>(g, s, c->order2d);
+        else if (c->ty2d == 16)
+            launch_2d<P, 16, MODE>(g, s, c->order2d);
+        else
+            launch_2d<P, 4, MODE>(g, s, c->order2d);
     } else {
-        TileGrid tg;
-        tg.tx = (g.ax[0].R + 63) / 64;
-        tg.ty = (g.ax[1].R + 7) / 8;
-        tg.TZ = pick_tz(tg.tx, tg.ty, g.ax[2].R);
-        tg.tz = (g.ax[2].R + tg.TZ - 1) / tg.TZ;
-        tg.nblk = tg.tx * tg.ty * tg.tz;
-        hipLaunchKernelGGL(iga::apply3d_kernel<P>, dim3(tg.nblk), dim3(kBlock), 0, s, g, tg);
+        if (c->shape3d == 1)
+            launch_3d<P, 64, 8, MODE>(c, g, s);
+        else
+            launch_3d<P, 32, 16, MODE>(c, g, s);
     }
-    IGA_HIP(hipGetLastError());
-    return IGA_OK;
 }
 
-int launch_apply(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
+// Output mode of a launch: always `out`; plus the mass rows or a table source, and
+// the scale / separable-source epilogue when a launch has scales or a sine source.
+template <int P>
+void launch_apply_p(const iga_ctx* c, const ApplyArgs& g, hipStream_t s, int mode)
 {
-    return c->p == 2 ? launch_apply_p<2>(c, g, s) : launch_apply_p<3>(c, g, s);
+    using namespace iga;
+    switch (mode) {
+    case kOut | kMass: launch_apply_pm<P, kOut | kMass>(c, g, s); break;
+    case kOut | kFarr: launch_apply_pm<P, kOut | kFarr>(c, g, s); break;
+    case kOut | kScaleSrc: launch_apply_pm<P, kOut | kScaleSrc>(c, g, s); break;
+    case kOut | kFarr | kScaleSrc: launch_apply_pm<P, kOut | kFarr | kScaleSrc>(c, g, s); break;
+    default: launch_apply_pm<P, kOut>(c, g, s); break;
+    }
+}
+
+int launch_apply(const iga_ctx* c, const ApplyArgs& g, hipStream_t s, bool scale_src)
+{
+    using namespace iga;
+    if (!g.out || (g.omass && (g.farr || scale_src))) return IGA_E_INVAL;
+    const int mode = kOut | (g.omass ? kMass : 0) | (g.farr ? kFarr : 0) | (scale_src ? kScaleSrc : 0);
+    if (c->p == 2)
+        launch_apply_p<2>(c, g, s, mode);
+    else
+        launch_apply_p<3>(c, g, s, mode);
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
 }
 
 int launch_rows_only(const iga_ctx* c, const ApplyArgs& g, size_t n, hipStream_t s)
 {
     const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(iga::rows_only_kernel, dim3(grid), dim3(kBlock), 0, s, g, c->dim, n);
+    if (g.farr)
+        hipLaunchKernelGGL(iga::rows_only_kernel<iga::kOut | iga::kFarr | iga::kScaleSrc>, dim3(grid), dim3(kBlock), 0,
+                           s, g, c->dim, n);
+    else
+        hipLaunchKernelGGL(iga::rows_only_kernel<iga::kOut | iga::kScaleSrc>, dim3(grid), dim3(kBlock), 0, s, g,
+                           c->dim, n);
     IGA_HIP(hipGetLastError());
     return IGA_OK;
 }
@@ -341,6 +401,12 @@ int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
     return IGA_OK;
 }
 
+__global__ void fill_kernel(double* dst, double v, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
 __global__ void bands_out_kernel(double* dst, const double* f0, const double* f1, int R, int Rmax,
                                  int W, int write1)
 {
@@ -394,6 +460,17 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
         const int z2[2] = {0, 0};
         if (hipMemcpy(c->zero, z2, sizeof(z2), hipMemcpyHostToDevice) != hipSuccess) rc = IGA_E_DEVICE;
     }
+    if (rc == IGA_OK) {
+        int64_t nmax = 1;
+        for (int a = 0; a < c->dim; ++a) nmax = std::max<int64_t>(nmax, desc->ne[a] + desc->p);
+        rc = dalloc(c, &p, (size_t)nmax * sizeof(double));
+        if (rc == IGA_OK) {
+            c->ones = (double*)p;
+            hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock),
+                               0, c->stream, c->ones, 1.0, (size_t)nmax);
+            if (hipGetLastError() != hipSuccess) rc = IGA_E_DEVICE;
+        }
+    }
     for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
         c->ne[a] = (int)desc->ne[a];
         c->nq[a] = desc->nq[a];
@@ -428,6 +505,46 @@ int iga_shape(const iga_ctx* c, int32_t form, int64_t rows[3], int64_t cols[3])
     for (int a = 0; a < 3; ++a) {
         rows[a] = a < c->dim ? rows_of(c, form, a) : 1;
         cols[a] = a < c->dim ? c->N[a] : 1;
+    }
+    return IGA_OK;
+}
+
+int iga_set_tile(iga_ctx* c, int32_t key, int32_t value)
+{
+    if (!c) return IGA_E_INVAL;
+    switch (key) {
+    case IGA_TILE_2D_ROWS:
+        if (value != 2 && value != 4 && value != 8 && value != 16) return IGA_E_INVAL;
+        c->ty2d = value;
+        break;
+    case IGA_TILE_2D_ORDER:
+        if (value < 0 || value > 2) return IGA_E_INVAL;
+        c->order2d = value;
+        break;
+    case IGA_TILE_3D_PLANES:
+        if (value < 0 || value > 32) return IGA_E_INVAL;
+        c->tz3d = value;
+        break;
+    case IGA_TILE_3D_SHAPE:
+        if (value != 0 && value != 1) return IGA_E_INVAL;
+        c->shape3d = value;
+        break;
+    default:
+        return IGA_E_INVAL;
+    }
+    free_graph(c);   // a cached graph holds the old launch geometry
+    return IGA_OK;
+}
+
+int iga_get_tile(const iga_ctx* c, int32_t key, int32_t* value)
+{
+    if (!c || !value) return IGA_E_INVAL;
+    switch (key) {
+    case IGA_TILE_2D_ROWS: *value = c->ty2d; break;
+    case IGA_TILE_2D_ORDER: *value = c->order2d; break;
+    case IGA_TILE_3D_PLANES: *value = c->tz3d; break;
+    case IGA_TILE_3D_SHAPE: *value = c->shape3d; break;
+    default: return IGA_E_INVAL;
     }
     return IGA_OK;
 }
@@ -473,7 +590,7 @@ int iga_rhs(iga_ctx* c, int32_t form, const double* u, double alpha, double beta
         IGA_TRY(source_rows(c, form, f->table, c->stream));
         g.farr = c->farr;
     }
-    if (uterm) return launch_apply(c, g, c->stream);
+    if (uterm) return launch_apply(c, g, c->stream, sep);
     return launch_rows_only(c, g, nrows(c, form), c->stream);
 }
 
@@ -484,11 +601,17 @@ int iga_apply(iga_ctx* c, int32_t form, const double* u, double* mass_out, doubl
         return IGA_E_INVAL;
     ApplyArgs g = make_args(c, form, false, false);
     g.u = u;
-    g.out = lap_out;
-    g.omass = mass_out;
-    g.alpha = 0.0;
-    g.beta = 1.0;
-    return launch_apply(c, g, c->stream);
+    if (lap_out) {   // out = lap (alpha 0, beta 1), mass rows on the side if requested
+        g.out = lap_out;
+        g.omass = mass_out;
+        g.alpha = 0.0;
+        g.beta = 1.0;
+    } else {         // mass rows only
+        g.out = mass_out;
+        g.alpha = 1.0;
+        g.beta = 0.0;
+    }
+    return launch_apply(c, g, c->stream, false);
 }
 
 int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int32_t nsteps)
@@ -520,7 +643,7 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
         for (int k = 0; k < nsteps; ++k) {
             g.u = (k & 1) ? c->work : u;
             g.out = (k & 1) ? u : c->work;
-            IGA_TRY(launch_apply(c, g, s));
+            IGA_TRY(launch_apply(c, g, s, true));
         }
         if (nsteps & 1) {
             hipLaunchKernelGGL(iga::copy_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)),

@@ -22,6 +22,7 @@ GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM = 0, 1, 2
 JOB_APPLY, JOB_STEP = 0, 1
+TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_SHAPE, TILE_2D_ORDER = 1, 2, 4, 5
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 _P64 = C.POINTER(C.c_int64)
@@ -64,6 +65,8 @@ _SIGS = {
     "iga_apply": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "iga_explicit_step": [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Source), C.c_int32],
     "iga_strerror": [C.c_int],
+    "iga_set_tile": [C.c_void_p, C.c_int32, C.c_int32],
+    "iga_get_tile": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
     "iga_batch_create": [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
     "iga_batch_submit": [C.c_void_p, C.POINTER(Job), C.c_int32, C.POINTER(C.c_uint64)],
     "iga_batch_flush": [C.c_void_p],
@@ -148,6 +151,16 @@ def iga_explicit_step(h, u_ptr: int, dt: float, src: Optional[Source], nsteps: i
            "iga_explicit_step")
 
 
+def iga_set_tile(h, key: int, value: int) -> None:
+    _check(lib().iga_set_tile(h, key, value), "iga_set_tile")
+
+
+def iga_get_tile(h, key: int) -> int:
+    v = C.c_int32()
+    _check(lib().iga_get_tile(h, key, C.byref(v)), "iga_get_tile")
+    return v.value
+
+
 # ---- torch convenience layer ----------------------------------------------------
 
 def _stream_handle(stream) -> int:
@@ -214,6 +227,12 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+    def set_tile(self, key: int, value: int) -> None:
+        iga_set_tile(self.h, key, value)
+
+    def get_tile(self, key: int) -> int:
+        return iga_get_tile(self.h, key)
 
     def shape(self, form: int) -> Tuple[int, ...]:
         rows, _ = iga_shape(self.h, form)
