@@ -172,44 +172,50 @@ int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);
 const char *iga_strerror(int code);
 
 /* ---------------------------------------------------------------------------------
- * Batched execution: many independent problems of different sizes in ONE persistent
- * kernel launch whose workgroups claim tiles from a device work counter.  Jobs are
- * 2D PG fused applies (IGA_JOB_APPLY2D: mass_out and lap_out of iga_apply) or
- * explicit steps (IGA_JOB_STEP, any dim, nsteps in-kernel steps on the job's
- * (u, work) pair).  A batch owns a device queue; submitted jobs start when the next
- * flush launches; results are identical to the per-problem calls with the same tile
- * configuration.
+ * Batched execution: many independent 2D problems of different sizes and degrees in
+ * ONE persistent kernel launch (captured once into a HIP graph and replayed), whose
+ * waves claim chunks of rows from a device work counter.  Every job is the fused
+ * Petrov-Galerkin apply of iga_apply (mass rows and Laplacian rows, support spans) on
+ * its own space: p in {2,3}, ne[0] x ne[1] elements on [0,1]^2, p+1 Gauss points per
+ * axis.  Per-mesh tables are built once and cached in the batch.  Results are identical,
+ * bit for bit, to iga_apply on a context with the same tile setting.
  * ------------------------------------------------------------------------------ */
-typedef enum { IGA_JOB_APPLY = 0, IGA_JOB_STEP = 1 } iga_job_kind;
 typedef enum { IGA_JOB_QUEUED = 0, IGA_JOB_RUNNING = 1, IGA_JOB_DONE = 2, IGA_JOB_FAILED = 3 } iga_job_state;
 
 typedef struct {
-    int32_t kind;       /* iga_job_kind                                                */
-    int32_t dim, p;     /* 1..3, 2..3                                                  */
-    int64_t ne[3];      /* elements per axis on [0,1]^dim, nq = p+1, support spans     */
-    const double *u;    /* device input coefficients (APPLY) / state (STEP, in place)   */
-    double *out0;       /* APPLY: mass_out (nullable)     STEP: device work buffer      */
-    double *out1;       /* APPLY: lap_out (nullable)      STEP: unused                  */
-    double dt;          /* STEP                                                        */
-    double sin_amp;     /* STEP: source amplitude of prod sin(pi x_a)                   */
-    int32_t nsteps;     /* STEP, >= 1                                                  */
+    int32_t p;          /* 2 or 3                                                       */
+    int64_t ne[2];      /* elements along x and y, >= 1                                  */
+    const double *u;    /* device coefficients, shape (ne[1]+p, ne[0]+p), x fastest      */
+    double *mass_out;   /* device rows int_{S_r} u_h, same shape                         */
+    double *lap_out;    /* device rows int_{S_r} Lap u_h, same shape                     */
 } iga_job;
 
 typedef struct iga_batch iga_batch;
 
-/* mem_budget_bytes: admission limit on the bytes the queued jobs touch (inputs and
-   outputs); 0 = unlimited.  max_jobs: queue capacity. */
+/* hip_stream: stream of every batch launch (NULL = default stream).
+   mem_budget_bytes: admission limit on the bytes the queued and running jobs touch
+   (u and both outputs); 0 = unlimited.  max_jobs: jobs per launch (queue capacity).
+   Errors: IGA_E_INVAL, IGA_E_NOMEM, IGA_E_DEVICE. */
 int iga_batch_create(void *hip_stream, size_t mem_budget_bytes, int32_t max_jobs,
                      iga_batch **out);
-/* Validates and queues jobs (host array); tickets (host, [njobs]) receive ids.
-   IGA_E_AGAIN when the queue or the budget cannot take all of them (none queued). */
+/* Validates and queues njobs jobs (host array); tickets (host, [njobs]) receive their
+   ids.  All or nothing: IGA_E_INVAL for a bad job, IGA_E_UNSUPPORTED for p outside
+   {2,3}, IGA_E_AGAIN when the queue or the memory budget cannot take all of them now
+   (poll or wait, then submit again). */
 int iga_batch_submit(iga_batch *b, const iga_job *jobs, int32_t njobs, uint64_t *tickets);
-/* Launches one persistent kernel over every queued job (asynchronous). */
+/* Launches one persistent kernel over the queued jobs (asynchronous).  A launch still
+   running is waited for first, so jobs that arrive while one launch runs ride the
+   next.  No-op when nothing is queued. */
 int iga_batch_flush(iga_batch *b);
-/* state (host): IGA_JOB_QUEUED / RUNNING / DONE / FAILED of a ticket. */
+/* state (host): IGA_JOB_QUEUED / RUNNING / DONE / FAILED of a ticket.  Reads the
+   completion flag the kernel publishes; never blocks.  IGA_E_INVAL: unknown ticket. */
 int iga_batch_poll(iga_batch *b, uint64_t ticket, int32_t *state);
-/* Blocks until every flushed job is done. */
+/* Blocks until the running launch, if any, is done. */
 int iga_batch_wait(iga_batch *b);
+/* Autotuner: times the queued jobs (which stay queued; applies are idempotent) with
+   every chunk height of the 2D kernel, `reps` launches each, keeps the fastest for
+   later launches and writes it to best_rows (host, nullable). */
+int iga_batch_autotune(iga_batch *b, int32_t reps, int32_t *best_rows);
 int iga_batch_destroy(iga_batch *b);
 
 #ifdef __cplusplus

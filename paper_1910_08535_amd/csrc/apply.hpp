@@ -332,25 +332,29 @@ __device__ __forceinline__ unsigned boff(int row, int col, int rows, int cols)
 // exact) and the code is branch-free: halo lanes, array edges and the band rows of
 // the chunk are all handled by buffer bounds and spare LDS slots.
 // ---------------------------------------------------------------------------------
-template <int P, int TY, int MODE, bool VEC>
-__global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
-{
-    constexpr int W = 2 * P + 1;
-    constexpr int NR = TY + 2 * P;          // input rows of a chunk
-    constexpr int SW = 128;                 // strip width
-    constexpr int RBW = SW + 2 * P + 2;     // columns x0-P .. x0+SW+P-1 and 2 spare slots
-    constexpr int CW = 2 * W + 2;           // band values per row: M[W], D[W], S, F
-    constexpr int NCV = (TY * CW + 63) / 64;
+// LDS doubles one 2D chunk needs
+template <int P, int TY>
+struct Chunk2D {
+    static constexpr int W = 2 * P + 1;
+    static constexpr int NR = TY + 2 * P;          // input rows of a chunk
+    static constexpr int SW = 128;                 // strip width
+    static constexpr int RBW = SW + 2 * P + 2;     // columns x0-P .. x0+SW+P-1, 2 spare slots
+    static constexpr int CW = 2 * W + 2;           // band values per row: M[W], D[W], S, F
+    static constexpr int NCV = (TY * CW + 63) / 64;
+    static constexpr int LDS = NR * RBW + NCV * 64;
     static_assert(RBW % 2 == 0 && CW % 2 == 0, "16-byte LDS rows");
-    __shared__ __attribute__((aligned(16))) double rb[NR][RBW];
-    __shared__ __attribute__((aligned(16))) double cy[NCV * 64];
+};
 
+// One chunk: strip bx (output columns 128 bx ..) and rows TY by .. of one problem.
+// lds: Chunk2D<P, TY>::LDS doubles, 16-byte aligned, private to the calling wave.
+template <int P, int TY, int MODE, bool VEC>
+__device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by, double* lds)
+{
+    using C = Chunk2D<P, TY>;
+    constexpr int W = C::W, NR = C::NR, SW = C::SW, RBW = C::RBW, CW = C::CW, NCV = C::NCV;
+    double (*rb)[RBW] = reinterpret_cast<double (*)[RBW]>(lds);
+    double* cy = lds + NR * RBW;
     const AxisOp &X = g.ax[0], &Y = g.ax[1];
-    // tg.TZ selects the block order (tuning): 0 = XCD-aware, row bands consecutive;
-    // 1 = XCD-aware, strips consecutive; 2 = dispatch order, row bands consecutive
-    const int L = tg.TZ == 2 ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, tg.nblk);
-    const int bx = tg.TZ == 1 ? L / tg.ty : L % tg.tx;
-    const int by = tg.TZ == 1 ? L % tg.ty : L / tg.tx;
     const int x0 = bx * SW, y0 = by * TY;
     const int lane = threadIdx.x;
     const int Nx = X.N, Ny = Y.N;
@@ -509,6 +513,18 @@ __global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
             }
         }
     }
+}
+
+template <int P, int TY, int MODE, bool VEC>
+__global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
+{
+    __shared__ __attribute__((aligned(16))) double lds[Chunk2D<P, TY>::LDS];
+    // tg.TZ selects the block order (tuning): 0 = XCD-aware, row bands consecutive;
+    // 1 = XCD-aware, strips consecutive; 2 = dispatch order, row bands consecutive
+    const int L = tg.TZ == 2 ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, tg.nblk);
+    const int bx = tg.TZ == 1 ? L / tg.ty : L % tg.tx;
+    const int by = tg.TZ == 1 ? L % tg.ty : L / tg.tx;
+    apply2d_chunk<P, TY, MODE, VEC>(g, bx, by, lds);
 }
 
 // ---------------------------------------------------------------------------------

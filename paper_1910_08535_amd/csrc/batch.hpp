@@ -1,0 +1,93 @@
+// batch.hpp -- many independent 2D problems in one persistent launch.
+//
+// Every job is a fused Petrov-Galerkin apply (mass and Laplacian rows) of its own
+// tensor-product space (its own p, element counts and band tables).  Its rows are cut
+// into the chunks of the 2D kernel (128 columns x TY rows); the chunks of all jobs are
+// numbered consecutively, and each wave of the persistent grid claims the next chunk
+// number from a device counter until none is left.  A wave that finishes the last
+// chunk of a job publishes the job as done in host-visible memory.
+#pragma once
+
+#include "apply.hpp"
+#include "common.hpp"
+
+namespace iga {
+
+struct BatchJobDev {
+    ApplyArgs g;   // band tables, u, out (Laplacian rows), omass (mass rows)
+    int p;         // 2 or 3
+    int vec;       // rows of even length: 128-bit row accesses
+    int tx, ty;    // strips and row chunks of the job
+    int chunk0;    // first chunk number of the job in this launch
+    int slot;      // index of the job's completion flag
+};
+
+struct BatchCtl {
+    unsigned counter;   // next chunk number to claim
+    int njobs;
+    int total;          // chunks over all jobs
+    int pad;
+};
+
+// Resets the claim counter and the per-job chunk counters of a launch.
+__global__ void batch_reset_kernel(BatchCtl* ctl, unsigned* done, int max_jobs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < max_jobs) done[i] = 0u;
+    if (i == 0) ctl->counter = 0u;
+}
+
+template <int TY>
+__global__ __launch_bounds__(64) void batch2d_kernel(BatchCtl* ctl, const BatchJobDev* __restrict__ jobs,
+                                                     unsigned* done, int* flags)
+{
+    constexpr int LDS = Chunk2D<3, TY>::LDS > Chunk2D<2, TY>::LDS ? Chunk2D<3, TY>::LDS
+                                                                 : Chunk2D<2, TY>::LDS;
+    __shared__ __attribute__((aligned(16))) double lds[LDS];
+    const int njobs = ctl->njobs, total = ctl->total;
+    for (;;) {
+        unsigned c = 0;
+        if (threadIdx.x == 0) c = atomicAdd(&ctl->counter, 1u);
+        c = __builtin_amdgcn_readfirstlane(c);
+        if ((int)c >= total) break;
+        // the job whose chunk range holds c (jobs are sorted by chunk0)
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].chunk0 <= (int)c)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchJobDev& J = jobs[lo];
+        const int local = (int)c - J.chunk0;
+        const int bx = local % J.tx, by = local / J.tx;
+        if (J.p == 2) {
+            if (J.vec)
+                apply2d_chunk<2, TY, kOut | kMass, true>(J.g, bx, by, lds);
+            else
+                apply2d_chunk<2, TY, kOut | kMass, false>(J.g, bx, by, lds);
+        } else {
+            if (J.vec)
+                apply2d_chunk<3, TY, kOut | kMass, true>(J.g, bx, by, lds);
+            else
+                apply2d_chunk<3, TY, kOut | kMass, false>(J.g, bx, by, lds);
+        }
+        // this chunk's rows are visible device-wide before it is counted; the wave that
+        // counts the job's last chunk publishes the job to the host
+        __threadfence();
+        if (threadIdx.x == 0) {
+            const unsigned d = atomicAdd(&done[lo], 1u) + 1u;
+            if (d == (unsigned)(J.tx * J.ty)) {
+                __threadfence_system();
+                __hip_atomic_store(&flags[J.slot], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        // the chunk's LDS is reused by the next claim of this wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+}  // namespace iga

@@ -681,3 +681,6 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
 }
 
 }  // extern "C"
+
+// batch API (uses the context machinery above)
+#include "batch_host.hpp"

@@ -21,7 +21,6 @@ IGA_OK, IGA_E_INVAL, IGA_E_UNSUPPORTED, IGA_E_NOMEM, IGA_E_DEVICE, IGA_E_AGAIN =
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM = 0, 1, 2
-JOB_APPLY, JOB_STEP = 0, 1
 TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_SHAPE, TILE_2D_ORDER = 1, 2, 4, 5
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
@@ -40,10 +39,8 @@ class Source(C.Structure):
 
 
 class Job(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("p", C.c_int32),
-                ("ne", C.c_int64 * 3), ("u", C.c_void_p), ("out0", C.c_void_p),
-                ("out1", C.c_void_p), ("dt", C.c_double), ("sin_amp", C.c_double),
-                ("nsteps", C.c_int32)]
+    _fields_ = [("p", C.c_int32), ("ne", C.c_int64 * 2), ("u", C.c_void_p),
+                ("mass_out", C.c_void_p), ("lap_out", C.c_void_p)]
 
 
 class IGAError(RuntimeError):
@@ -72,6 +69,7 @@ _SIGS = {
     "iga_batch_flush": [C.c_void_p],
     "iga_batch_poll": [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)],
     "iga_batch_wait": [C.c_void_p],
+    "iga_batch_autotune": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
     "iga_batch_destroy": [C.c_void_p],
 }
 
@@ -294,3 +292,64 @@ def bands_to_dense(band, nrows: int, ncols: int, p: int):
             if 0 <= c < ncols:
                 out[r, c] = band[r, k]
     return out
+
+
+# ---- batches ----------------------------------------------------------------------
+
+class Batch:
+    """Many independent 2D fused PG applies in one persistent launch (iga_batch_*).
+
+    Tensors passed to submit() must stay alive until their job is done."""
+
+    def __init__(self, mem_budget_bytes: int = 0, max_jobs: int = 1024, stream=None):
+        self.stream = stream
+        self.h = C.c_void_p()
+        _check(lib().iga_batch_create(C.c_void_p(_stream_handle(stream)), mem_budget_bytes,
+                                      max_jobs, C.byref(self.h)), "iga_batch_create")
+
+    def submit(self, jobs: Sequence[Tuple[int, Tuple[int, int], object, object, object]]) -> list:
+        """jobs: (p, (nx, ny), u, mass_out, lap_out) with torch tensors; returns tickets."""
+        arr = (Job * len(jobs))()
+        for k, (p, ne, u, m, l) in enumerate(jobs):
+            arr[k].p = p
+            arr[k].ne[0], arr[k].ne[1] = ne
+            arr[k].u, arr[k].mass_out, arr[k].lap_out = _ptr(u), _ptr(m), _ptr(l)
+        tickets = (C.c_uint64 * max(1, len(jobs)))()
+        _check(lib().iga_batch_submit(self.h, arr, len(jobs), tickets), "iga_batch_submit")
+        return list(tickets)[: len(jobs)]
+
+    def try_submit(self, jobs) -> Optional[list]:
+        """Like submit(), but returns None when the batch answers IGA_E_AGAIN."""
+        try:
+            return self.submit(jobs)
+        except IGAError as e:
+            if e.code == IGA_E_AGAIN:
+                return None
+            raise
+
+    def flush(self) -> None:
+        _check(lib().iga_batch_flush(self.h), "iga_batch_flush")
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int32()
+        _check(lib().iga_batch_poll(self.h, ticket, C.byref(st)), "iga_batch_poll")
+        return st.value
+
+    def wait(self) -> None:
+        _check(lib().iga_batch_wait(self.h), "iga_batch_wait")
+
+    def autotune(self, reps: int = 3) -> int:
+        best = C.c_int32()
+        _check(lib().iga_batch_autotune(self.h, reps, C.byref(best)), "iga_batch_autotune")
+        return best.value
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _check(lib().iga_batch_destroy(self.h), "iga_batch_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

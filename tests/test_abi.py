@@ -53,7 +53,7 @@ def _desc(iga, **kw):
     (dict(dim=0), -2), (dict(dim=4), -2), (dict(p=1), -2), (dict(p=4), -2),
     (dict(nq=(0, 3, 3)), -2), (dict(nq=(3, 17, 3)), -2),
     (dict(ne=(0, 8, 8)), -1), (dict(hi=0.0), -1), (dict(spans=7), -1),
-    (dict(ne=(40000, 40000, 8)), -1),
+    (dict(ne=(50000, 50000, 8)), -1),
 ])
 def test_create_rejects_bad_descriptors(iga, kw, code):
     h = C.c_void_p()
