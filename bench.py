@@ -155,6 +155,73 @@ def run_c2(args):
     return out
 
 
+def run_c4(args) -> dict:
+    """256 independent 2D problems (p in {2,3}, n, m uniform in [32, 1024], seed 4), each a
+    fused PG apply.  Plain: one kernel launch per problem (the 256 launches replayed as one
+    HIP graph, so launch overhead is minimal); batched: one persistent launch over all
+    problems (iga_batch, autotuned chunk height).  Inputs resident in HBM (~1.8 GB).
+    Device times come from HIP events on the launching stream."""
+    import torch
+    from paper_1910_08535_amd import iga, inputs
+
+    jobs, coefs = inputs.batch_jobs()
+    stream = torch.cuda.Stream()   # graph capture needs a non-default stream
+    torch.cuda.set_stream(stream)
+    dev = []
+    gp = 0
+    nbytes = 0
+    for j, u in zip(jobs, coefs):
+        ud = torch.from_numpy(u).cuda()
+        dev.append((j.p, j.ne, ud, torch.empty_like(ud), torch.empty_like(ud)))
+        gp += j.ne[0] * j.ne[1] * (j.p + 1) ** 2
+        nbytes += 24 * ud.numel()
+    torch.cuda.synchronize()
+    # batched: the autotuner times `reps` persistent launches per chunk height
+    b = iga.Batch(max_jobs=len(dev), stream=stream)
+    b.submit(dev)
+    best_rows, batch_ms = b.autotune(reps=args.batch_reps)
+    b.flush()
+    b.wait()
+    # host-inclusive rounds: submit + flush of all 256 jobs each round
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_reps):
+        b.submit(dev)
+        b.flush()
+    b.wait()
+    round_s = (time.perf_counter() - t0) / args.batch_reps
+    b.close()
+    # plain: one launch per problem, same chunk height, 256 launches in one graph
+    meshes = [iga.Mesh(2, p, ne, (p + 1, p + 1), stream=stream) for p, ne, *_ in dev]
+    for m in meshes:
+        m.set_tile(iga.TILE_2D_ROWS, best_rows)
+    for m, (p, ne, u, mo, lo) in zip(meshes, dev):
+        m.apply(iga.PG, u, out_mass=mo, out_lap=lo)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        for m, (p, ne, u, mo, lo) in zip(meshes, dev):
+            m.apply(iga.PG, u, out_mass=mo, out_lap=lo)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.batch_reps):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / args.batch_reps
+    batch_s, plain_s = batch_ms * 1e-3, plain_ms * 1e-3
+    return {"workload": "256 independent 2D problems, p in {2,3}, n,m ~ U[32,1024] (seed 4), "
+                        "fused PG apply each",
+            "gauss_points": gp, "algorithmic_bytes": nbytes, "chunk_rows": best_rows,
+            "batched_GPs": gp / batch_s, "plain_GPs": gp / plain_s,
+            "batched_ms": batch_ms, "plain_ms": plain_ms, "speedup": plain_s / batch_s,
+            "batched_hbm_frac": nbytes / batch_s / (HBM_PEAK_GBS * 1e9),
+            "plain_hbm_frac": nbytes / plain_s / (HBM_PEAK_GBS * 1e9),
+            "batched_round_ms_host_inclusive": round_s * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +230,8 @@ def main():
     ap.add_argument("--rotate-mb", type=int, default=600,
                     help="distinct buffer bytes cycled through (defeats the Infinity Cache)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched leg")
+    ap.add_argument("--batch-reps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -170,6 +239,8 @@ def main():
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     out = run_c2(args)
+    if not args.no_batched:
+        out["batched"] = run_c4(args)
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     if rank == 0:

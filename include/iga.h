@@ -207,15 +207,17 @@ int iga_batch_submit(iga_batch *b, const iga_job *jobs, int32_t njobs, uint64_t 
    running is waited for first, so jobs that arrive while one launch runs ride the
    next.  No-op when nothing is queued. */
 int iga_batch_flush(iga_batch *b);
-/* state (host): IGA_JOB_QUEUED / RUNNING / DONE / FAILED of a ticket.  Reads the
-   completion flag the kernel publishes; never blocks.  IGA_E_INVAL: unknown ticket. */
+/* state (host): IGA_JOB_QUEUED / RUNNING / DONE / FAILED of a ticket.  The jobs of one
+   launch complete together (the launch's HIP event); never blocks.  IGA_E_INVAL:
+   unknown ticket. */
 int iga_batch_poll(iga_batch *b, uint64_t ticket, int32_t *state);
 /* Blocks until the running launch, if any, is done. */
 int iga_batch_wait(iga_batch *b);
 /* Autotuner: times the queued jobs (which stay queued; applies are idempotent) with
-   every chunk height of the 2D kernel, `reps` launches each, keeps the fastest for
-   later launches and writes it to best_rows (host, nullable). */
-int iga_batch_autotune(iga_batch *b, int32_t reps, int32_t *best_rows);
+   every chunk height of the 2D kernel, `reps` launches each (HIP events on the batch
+   stream), keeps the fastest for later launches and writes it to best_rows and its
+   time per launch in milliseconds to best_ms (host, both nullable). */
+int iga_batch_autotune(iga_batch *b, int32_t reps, int32_t *best_rows, float *best_ms);
 int iga_batch_destroy(iga_batch *b);
 
 #ifdef __cplusplus

@@ -4,8 +4,9 @@
 // tensor-product space (its own p, element counts and band tables).  Its rows are cut
 // into the chunks of the 2D kernel (128 columns x TY rows); the chunks of all jobs are
 // numbered consecutively, and each wave of the persistent grid claims the next chunk
-// number from a device counter until none is left.  A wave that finishes the last
-// chunk of a job publishes the job as done in host-visible memory.
+// number from a device counter until none is left.  The jobs of a launch complete
+// together with the launch: on this GPU a device-wide release (to publish one job early)
+// writes back a whole L2 of an XCD, far too dear to pay per chunk.
 #pragma once
 
 #include "apply.hpp"
@@ -19,7 +20,7 @@ struct BatchJobDev {
     int vec;       // rows of even length: 128-bit row accesses
     int tx, ty;    // strips and row chunks of the job
     int chunk0;    // first chunk number of the job in this launch
-    int slot;      // index of the job's completion flag
+    int pad;
 };
 
 struct BatchCtl {
@@ -29,17 +30,14 @@ struct BatchCtl {
     int pad;
 };
 
-// Resets the claim counter and the per-job chunk counters of a launch.
-__global__ void batch_reset_kernel(BatchCtl* ctl, unsigned* done, int max_jobs)
+// Resets the claim counter of a launch.
+__global__ void batch_reset_kernel(BatchCtl* ctl)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < max_jobs) done[i] = 0u;
-    if (i == 0) ctl->counter = 0u;
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->counter = 0u;
 }
 
 template <int TY>
-__global__ __launch_bounds__(64) void batch2d_kernel(BatchCtl* ctl, const BatchJobDev* __restrict__ jobs,
-                                                     unsigned* done, int* flags)
+__global__ __launch_bounds__(64) void batch2d_kernel(BatchCtl* ctl, const BatchJobDev* __restrict__ jobs)
 {
     constexpr int LDS = Chunk2D<3, TY>::LDS > Chunk2D<2, TY>::LDS ? Chunk2D<3, TY>::LDS
                                                                  : Chunk2D<2, TY>::LDS;
@@ -59,7 +57,9 @@ __global__ __launch_bounds__(64) void batch2d_kernel(BatchCtl* ctl, const BatchJ
             else
                 hi = mid - 1;
         }
-        const BatchJobDev& J = jobs[lo];
+        // a private copy: the kernel stores to global memory, so fields read through a
+        // pointer would be re-read after every store
+        const BatchJobDev J = jobs[lo];
         const int local = (int)c - J.chunk0;
         const int bx = local % J.tx, by = local / J.tx;
         if (J.p == 2) {
@@ -72,16 +72,6 @@ __global__ __launch_bounds__(64) void batch2d_kernel(BatchCtl* ctl, const BatchJ
                 apply2d_chunk<3, TY, kOut | kMass, true>(J.g, bx, by, lds);
             else
                 apply2d_chunk<3, TY, kOut | kMass, false>(J.g, bx, by, lds);
-        }
-        // this chunk's rows are visible device-wide before it is counted; the wave that
-        // counts the job's last chunk publishes the job to the host
-        __threadfence();
-        if (threadIdx.x == 0) {
-            const unsigned d = atomicAdd(&done[lo], 1u) + 1u;
-            if (d == (unsigned)(J.tx * J.ty)) {
-                __threadfence_system();
-                __hip_atomic_store(&flags[J.slot], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
         }
         // the chunk's LDS is reused by the next claim of this wave
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

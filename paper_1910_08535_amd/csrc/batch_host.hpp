@@ -31,9 +31,6 @@ struct iga_batch {
     iga::BatchJobDev* jobs_dev = nullptr;
     iga::BatchCtl* ctl_host = nullptr;       // pinned staging
     iga::BatchCtl* ctl_dev = nullptr;
-    unsigned* done_dev = nullptr;
-    int* flags_host = nullptr;               // host-coherent, written by the kernel
-    int* flags_dev = nullptr;
     hipEvent_t ev = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_ty = 0;
@@ -97,10 +94,9 @@ int batch_grid()
 template <int TY>
 void batch_enqueue(iga_batch* b, hipStream_t s)
 {
-    hipLaunchKernelGGL(iga::batch_reset_kernel, dim3((b->max_jobs + 255) / 256), dim3(256), 0, s,
-                       b->ctl_dev, b->done_dev, b->max_jobs);
+    hipLaunchKernelGGL(iga::batch_reset_kernel, dim3(1), dim3(64), 0, s, b->ctl_dev);
     hipLaunchKernelGGL(iga::batch2d_kernel<TY>, dim3(batch_grid<TY>()), dim3(64), 0, s, b->ctl_dev,
-                       (const iga::BatchJobDev*)b->jobs_dev, b->done_dev, b->flags_dev);
+                       (const iga::BatchJobDev*)b->jobs_dev);
 }
 
 // The graph of one launch: counter reset + persistent kernel.  Its arguments are fixed
@@ -158,7 +154,6 @@ int batch_fill(iga_batch* b, size_t n, int* total)
         d.tx = (d.g.ax[0].R + 127) / 128;
         d.ty = (d.g.ax[1].R + b->ty - 1) / b->ty;
         d.chunk0 = chunk;
-        d.slot = (int)k;
         chunk += d.tx * d.ty;
     }
     *total = chunk;
@@ -210,19 +205,14 @@ int iga_batch_create(void* hip_stream, size_t mem_budget_bytes, int32_t max_jobs
     b->max_jobs = max_jobs;
     bool ok = hipHostMalloc((void**)&b->jobs_host, sizeof(iga::BatchJobDev) * max_jobs, 0) == hipSuccess &&
               hipHostMalloc((void**)&b->ctl_host, sizeof(iga::BatchCtl), 0) == hipSuccess &&
-              hipHostMalloc((void**)&b->flags_host, sizeof(int) * max_jobs,
-                            hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
               hipMalloc((void**)&b->jobs_dev, sizeof(iga::BatchJobDev) * max_jobs) == hipSuccess &&
               hipMalloc((void**)&b->ctl_dev, sizeof(iga::BatchCtl)) == hipSuccess &&
-              hipMalloc((void**)&b->done_dev, sizeof(unsigned) * max_jobs) == hipSuccess &&
-              hipHostGetDevicePointer((void**)&b->flags_dev, b->flags_host, 0) == hipSuccess &&
               hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         iga_batch_destroy(b);
         return IGA_E_NOMEM;
     }
-    for (int i = 0; i < max_jobs; ++i) b->flags_host[i] = IGA_JOB_QUEUED;
     *out = b;
     return IGA_OK;
 }
@@ -265,7 +255,6 @@ int iga_batch_flush(iga_batch* b)
         b->queued.erase(b->queued.begin(), b->queued.begin() + n);
         return rc;
     }
-    for (size_t k = 0; k < n; ++k) b->flags_host[k] = IGA_JOB_RUNNING;
     IGA_TRY(batch_launch_prepared(b, n, total));
     for (size_t k = 0; k < n; ++k) {
         b->running.push_back(b->queued[k].ticket);
@@ -291,8 +280,15 @@ int iga_batch_poll(iga_batch* b, uint64_t ticket, int32_t* state)
         }
     for (size_t k = 0; k < b->running.size(); ++k)
         if (b->running[k] == ticket) {
-            const int f = __atomic_load_n(&b->flags_host[k], __ATOMIC_ACQUIRE);
-            *state = f == IGA_JOB_DONE ? IGA_JOB_DONE : IGA_JOB_RUNNING;
+            const hipError_t q = hipEventQuery(b->ev);
+            if (q == hipSuccess) {
+                batch_retire(b);
+                *state = IGA_JOB_DONE;
+            } else if (q == hipErrorNotReady) {
+                *state = IGA_JOB_RUNNING;
+            } else {
+                return IGA_E_DEVICE;
+            }
             return IGA_OK;
         }
     *state = IGA_JOB_DONE;   // an earlier launch, already retired
@@ -305,7 +301,7 @@ int iga_batch_wait(iga_batch* b)
     return batch_sync(b);
 }
 
-int iga_batch_autotune(iga_batch* b, int32_t reps, int32_t* best_rows)
+int iga_batch_autotune(iga_batch* b, int32_t reps, int32_t* best_rows, float* best_ms)
 {
     if (!b || reps < 1) return IGA_E_INVAL;
     IGA_TRY(batch_sync(b));
@@ -339,8 +335,8 @@ int iga_batch_autotune(iga_batch* b, int32_t reps, int32_t* best_rows)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->ty = best_ty;
-    for (size_t k = 0; k < n; ++k) b->flags_host[k] = IGA_JOB_QUEUED;
     if (best_rows) *best_rows = best_ty;
+    if (best_ms) *best_ms = best / (float)reps;
     return rc;
 }
 
@@ -353,10 +349,8 @@ int iga_batch_destroy(iga_batch* b)
     if (b->ev) (void)hipEventDestroy(b->ev);
     if (b->jobs_dev) (void)hipFree(b->jobs_dev);
     if (b->ctl_dev) (void)hipFree(b->ctl_dev);
-    if (b->done_dev) (void)hipFree(b->done_dev);
     if (b->jobs_host) (void)hipHostFree(b->jobs_host);
     if (b->ctl_host) (void)hipHostFree(b->ctl_host);
-    if (b->flags_host) (void)hipHostFree(b->flags_host);
     delete b;
     return IGA_OK;
 }

@@ -69,7 +69,7 @@ _SIGS = {
     "iga_batch_flush": [C.c_void_p],
     "iga_batch_poll": [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)],
     "iga_batch_wait": [C.c_void_p],
-    "iga_batch_autotune": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
+    "iga_batch_autotune": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)],
     "iga_batch_destroy": [C.c_void_p],
 }
 
@@ -338,10 +338,13 @@ class Batch:
     def wait(self) -> None:
         _check(lib().iga_batch_wait(self.h), "iga_batch_wait")
 
-    def autotune(self, reps: int = 3) -> int:
+    def autotune(self, reps: int = 3) -> Tuple[int, float]:
+        """(best chunk rows, milliseconds per launch of the queued jobs with it)."""
         best = C.c_int32()
-        _check(lib().iga_batch_autotune(self.h, reps, C.byref(best)), "iga_batch_autotune")
-        return best.value
+        ms = C.c_float()
+        _check(lib().iga_batch_autotune(self.h, reps, C.byref(best), C.byref(ms)),
+               "iga_batch_autotune")
+        return best.value, ms.value
 
     def close(self) -> None:
         if getattr(self, "h", None):
