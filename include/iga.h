@@ -99,7 +99,9 @@ typedef struct iga_ctx iga_ctx;
 /* Creates a context for one mesh: validates the descriptor and builds, with device
    kernels, the per-axis Gauss rule, the basis tables and the banded 1D factors.
    hip_stream: a hipStream_t (NULL = the default stream) on which every call of this
-   context is enqueued.  Waits for its own set-up kernels before returning.
+   context is enqueued.  The set-up kernels are enqueued on that stream too (every later
+   call of the context is ordered after them); only caller span tables (CUSTOM) are
+   copied synchronously.
    Errors: IGA_E_INVAL (null out, bad sizes or spans), IGA_E_UNSUPPORTED,
    IGA_E_NOMEM, IGA_E_DEVICE. */
 int iga_create(const iga_mesh_desc *desc, void *hip_stream, iga_ctx **out);

@@ -343,6 +343,22 @@ int validate_desc(const iga_mesh_desc* d)
     return IGA_OK;
 }
 
+// Spans of the built-in kinds, generated on the device (kind 0 support, 1 element).
+__global__ void spans_kernel(int* first, int* last, int R, int p, int ne, int kind)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    if (kind == IGA_SPANS_SUPPORT) {
+        first[r] = r - p > 0 ? r - p : 0;
+        last[r] = r < ne - 1 ? r : ne - 1;
+    } else {
+        first[r] = r;
+        last[r] = r;
+    }
+}
+
+// Tables of one axis, carved out of one device allocation and filled by kernels on the
+// context's stream (no host synchronisation except for caller span tables).
 int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
 {
     AxisTables& t = c->t[a];
@@ -353,58 +369,55 @@ int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
     t.W = 2 * t.p + 1;
     t.lo = d->lo[a];
     t.hi = d->hi[a];
-    std::vector<int> first, last;
-    if (d->spans == IGA_SPANS_SUPPORT) {
-        for (int r = 0; r < t.N; ++r) {
-            first.push_back(std::max(0, r - t.p));
-            last.push_back(std::min(t.ne - 1, r));
-        }
-    } else if (d->spans == IGA_SPANS_ELEMENT) {
-        for (int e = 0; e < t.ne; ++e) {
-            first.push_back(e);
-            last.push_back(e);
-        }
-    } else {
-        for (int64_t r = 0; r < d->nspan[a]; ++r) {
-            first.push_back((int)d->span_first[a][r]);
-            last.push_back((int)d->span_last[a][r]);
-        }
-    }
-    t.R = (int)first.size();
+    t.R = d->spans == IGA_SPANS_SUPPORT ? t.N : (d->spans == IGA_SPANS_ELEMENT ? t.ne : (int)d->nspan[a]);
     const size_t ng = (size_t)t.ne * t.nq;
-    void* p;
-    IGA_TRY(dalloc(c, &p, ng * sizeof(double))); t.xg = (double*)p;
-    IGA_TRY(dalloc(c, &p, ng * sizeof(double))); t.wg = (double*)p;
-    IGA_TRY(dalloc(c, &p, ng * 3 * (t.p + 1) * sizeof(double))); t.bq = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.R * t.W * sizeof(double))); t.pm = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.R * t.W * sizeof(double))); t.pd = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(double))); t.inv_len = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(double))); t.fs_pg = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.N * t.W * sizeof(double))); t.gm = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.N * t.W * sizeof(double))); t.gl = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.N * t.W * sizeof(double))); t.gb = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.N * sizeof(double))); t.fs_g = (double*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(int))); t.first = (int*)p;
-    IGA_TRY(dalloc(c, &p, (size_t)t.R * sizeof(int))); t.last = (int*)p;
-    IGA_HIP(hipMemcpyAsync(t.first, first.data(), first.size() * sizeof(int),
-                           hipMemcpyHostToDevice, c->stream));
-    IGA_HIP(hipMemcpyAsync(t.last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice,
-                           c->stream));
+    const size_t nd[11] = {ng, ng, ng * 3 * (t.p + 1), (size_t)t.R * t.W, (size_t)t.R * t.W,
+                           (size_t)t.R, (size_t)t.R, (size_t)t.N * t.W, (size_t)t.N * t.W,
+                           (size_t)t.N * t.W, (size_t)t.N};
+    double** dst[11] = {&t.xg, &t.wg, &t.bq, &t.pm, &t.pd, &t.inv_len, &t.fs_pg,
+                        &t.gm, &t.gl, &t.gb, &t.fs_g};
+    auto up = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+    size_t total = 0;
+    for (int i = 0; i < 11; ++i) total += up(nd[i] * sizeof(double));
+    total += 2 * up((size_t)t.R * sizeof(int));
+    void* base = nullptr;
+    IGA_TRY(dalloc(c, &base, total));
+    char* cur = (char*)base;
+    for (int i = 0; i < 11; ++i) {
+        *dst[i] = (double*)cur;
+        cur += up(nd[i] * sizeof(double));
+    }
+    t.first = (int*)cur;
+    cur += up((size_t)t.R * sizeof(int));
+    t.last = (int*)cur;
+    if (d->spans == IGA_SPANS_CUSTOM) {
+        std::vector<int> first(t.R), last(t.R);
+        for (int r = 0; r < t.R; ++r) {
+            first[r] = (int)d->span_first[a][r];
+            last[r] = (int)d->span_last[a][r];
+        }
+        IGA_HIP(hipMemcpy(t.first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice));
+        IGA_HIP(hipMemcpy(t.last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
+    } else {
+        hipLaunchKernelGGL(spans_kernel, dim3((t.R + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
+                           t.first, t.last, t.R, t.p, t.ne, d->spans);
+    }
     const unsigned g1 = (unsigned)((ng + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(iga::gauss_tables_kernel, dim3(g1), dim3(kBlock), 0, c->stream, t);
     const int nr = std::max(t.R, t.N);
     hipLaunchKernelGGL(iga::band_tables_kernel, dim3((nr + kBlock - 1) / kBlock), dim3(kBlock), 0,
                        c->stream, t);
     IGA_HIP(hipGetLastError());
-    // the host span vectors die at return: wait for the copies
-    IGA_HIP(hipStreamSynchronize(c->stream));
     return IGA_OK;
 }
 
-__global__ void fill_kernel(double* dst, double v, size_t n)
+// unit = {1, 0, ..., 0} (8 doubles), zero = two ints 0, ones = n doubles 1
+__global__ void consts_kernel(double* base, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = v;
+    if (i < 8) base[i] = i == 0 ? 1.0 : 0.0;
+    else if (i == 8) ((int*)(base + 8))[0] = ((int*)(base + 8))[1] = 0;
+    else if (i < 9 + n) base[i] = 1.0;
 }
 
 __global__ void bands_out_kernel(double* dst, const double* f0, const double* f1, int R, int Rmax,
@@ -448,28 +461,17 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
     c->stream = (hipStream_t)hip_stream;
     int rc = IGA_OK;
     void* p = nullptr;
-    rc = dalloc(c, &p, 8 * sizeof(double));
+    // unit {1, 0 x 7} | zero (two ints) | ones[nmax]
+    int64_t nmax = 1;
+    for (int a = 0; a < c->dim; ++a) nmax = std::max<int64_t>(nmax, desc->ne[a] + desc->p);
+    rc = dalloc(c, &p, (size_t)(8 + 1 + nmax) * sizeof(double));
     if (rc == IGA_OK) {
         c->unit = (double*)p;
-        const double u8[8] = {1, 0, 0, 0, 0, 0, 0, 0};
-        if (hipMemcpy(c->unit, u8, sizeof(u8), hipMemcpyHostToDevice) != hipSuccess) rc = IGA_E_DEVICE;
-    }
-    if (rc == IGA_OK) rc = dalloc(c, &p, sizeof(int) * 2);
-    if (rc == IGA_OK) {
-        c->zero = (int*)p;
-        const int z2[2] = {0, 0};
-        if (hipMemcpy(c->zero, z2, sizeof(z2), hipMemcpyHostToDevice) != hipSuccess) rc = IGA_E_DEVICE;
-    }
-    if (rc == IGA_OK) {
-        int64_t nmax = 1;
-        for (int a = 0; a < c->dim; ++a) nmax = std::max<int64_t>(nmax, desc->ne[a] + desc->p);
-        rc = dalloc(c, &p, (size_t)nmax * sizeof(double));
-        if (rc == IGA_OK) {
-            c->ones = (double*)p;
-            hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nmax + kBlock - 1) / kBlock)), dim3(kBlock),
-                               0, c->stream, c->ones, 1.0, (size_t)nmax);
-            if (hipGetLastError() != hipSuccess) rc = IGA_E_DEVICE;
-        }
+        c->zero = (int*)(c->unit + 8);
+        c->ones = c->unit + 9;
+        hipLaunchKernelGGL(consts_kernel, dim3((unsigned)((nmax + 9 + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, c->stream, c->unit, (size_t)nmax);
+        if (hipGetLastError() != hipSuccess) rc = IGA_E_DEVICE;
     }
     for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
         c->ne[a] = (int)desc->ne[a];
