@@ -222,6 +222,54 @@ def run_c4(args) -> dict:
             "batched_round_ms_host_inclusive": round_s * 1e3}
 
 
+def run_c5(args) -> dict:
+    """Serving: a seeded Poisson stream (2000 req/s) of RHS / explicit-step requests, 1D (up
+    to 1e6 elements), 2D (up to 2048^2), 3D (up to 192^3), p in {2,3}, 200 GB admission
+    budget.  (a) arrivals in real time: p50/p99 latency; (b) every request present at
+    t = 0: served throughput; (c) the same requests one at a time (plain)."""
+    import torch
+    from paper_1910_08535_amd import iga, inputs, serve
+
+    reqs = inputs.request_stream(rate=2000.0, seconds=args.serve_seconds, seed=5)
+    srv = serve.Server(budget_bytes=200 * 10**9)
+    realtime = srv.run(reqs)
+    srv.close()
+    srv = serve.Server(budget_bytes=200 * 10**9)
+    saturated = srv.run(reqs, time_scale=0.0)
+    srv.close()
+    # plain: one request at a time, each waited for before the next (meshes cached)
+    meshes = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gp = 0
+    for r in reqs:
+        key = (r.dim, r.p, r.ne)
+        if key not in meshes:
+            meshes[key] = iga.Mesh(r.dim, r.p, r.ne, (r.p + 1,) * r.dim)
+        mesh = meshes[key]
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(r.seed)
+        u = torch.randn(tuple(n + r.p for n in reversed(r.ne)), dtype=torch.float64,
+                        device="cuda", generator=gen)
+        if r.kind == "rhs":
+            mesh.apply(iga.PG, u)
+        else:
+            h = min(1.0 / n for n in r.ne)
+            for _ in range(r.nsteps):
+                mesh.explicit_step(u, h * h / 64.0, sin_amp=1.0, nsteps=1)
+        torch.cuda.synchronize()
+        gp += serve.request_work(r)[0]
+    plain_s = time.perf_counter() - t0
+    for m in meshes.values():
+        m.close()
+    return {"workload": f"Poisson 2000 req/s for {args.serve_seconds} s (seed 5): RHS / explicit "
+                        "step, 1D <= 1e6, 2D <= 2048^2, 3D <= 192^3 elements, p in {2,3}, "
+                        "200 GB budget",
+            "requests": len(reqs), "realtime": realtime, "saturated": saturated,
+            "plain_GPs": gp / plain_s, "plain_s": plain_s,
+            "served_vs_plain": saturated["GPs"] / (gp / plain_s)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +280,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched leg")
     ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -241,6 +291,8 @@ def main():
     out = run_c2(args)
     if not args.no_batched:
         out["batched"] = run_c4(args)
+    if not args.no_serving:
+        out["serving"] = run_c5(args)
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     if rank == 0:

@@ -106,7 +106,9 @@ typedef struct iga_ctx iga_ctx;
    IGA_E_NOMEM, IGA_E_DEVICE. */
 int iga_create(const iga_mesh_desc *desc, void *hip_stream, iga_ctx **out);
 
-/* Releases the context's tables, scratch and cached graphs (waits for its stream). */
+/* Releases the context's tables, scratch and cached graph.  Device memory is freed in
+   stream order (after the work already queued on the context's stream), so this does
+   not wait, except for a cached explicit-step graph, which is waited for first. */
 int iga_destroy(iga_ctx *ctx);
 
 /* Row counts R_a (rows, host, [3]) of `form` and basis counts N_a (cols, host, [3]);

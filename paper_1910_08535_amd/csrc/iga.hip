@@ -71,10 +71,12 @@ struct iga_ctx {
 
 namespace {
 
+// Device memory of a context comes from the stream-ordered pool of its stream
+// (hipMallocAsync): setting up a context costs no device-wide synchronisation.
 int dalloc(iga_ctx* c, void** p, size_t bytes)
 {
     if (bytes == 0) bytes = 8;
-    if (hipMalloc(p, bytes) != hipSuccess) {
+    if (hipMallocAsync(p, bytes, c->stream) != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
         return IGA_E_NOMEM;
@@ -83,16 +85,15 @@ int dalloc(iga_ctx* c, void** p, size_t bytes)
     return IGA_OK;
 }
 
-// Scratch of at least n doubles, grown on demand.  Growth waits for the stream so
-// that no queued kernel still uses the old buffer.
+// Scratch of at least n doubles, grown on demand.  The old buffer is released in
+// stream order, after every kernel queued before the growth.
 int scratch(iga_ctx* c, double** buf, size_t* cap, size_t n)
 {
     if (*cap >= n && *buf) return IGA_OK;
-    IGA_HIP(hipStreamSynchronize(c->stream));
     if (*buf) {
         auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)*buf);
         if (it != c->allocs.end()) c->allocs.erase(it);
-        IGA_HIP(hipFree(*buf));
+        IGA_HIP(hipFreeAsync(*buf, c->stream));
         *buf = nullptr;
         *cap = 0;
     }
@@ -493,10 +494,13 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
 int iga_destroy(iga_ctx* c)
 {
     if (!c) return IGA_E_INVAL;
-    (void)hipStreamSynchronize(c->stream);
-    free_graph(c);
+    if (c->gexec) {   // a cached graph may still be running
+        (void)hipStreamSynchronize(c->stream);
+        free_graph(c);
+    }
     if (c->cap) (void)hipStreamDestroy(c->cap);
-    for (void* p : c->allocs) (void)hipFree(p);
+    // released in stream order: after every kernel already queued on the stream
+    for (void* p : c->allocs) (void)hipFreeAsync(p, c->stream);
     delete c;
     return IGA_OK;
 }
