@@ -18,7 +18,6 @@ Prints one JSON line (rank 0).  --gpus above 1 exits: this build runs on one GPU
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,13 +33,21 @@ BYTES_C2 = 1026 * 1026 * 24
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1910_08535_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1910_08535_amd.profiling import kernel_source_hash as h
+    return h()
+
+
+def copy_probe(mib: int) -> None:
+    """A plain device copy of known size (for scaling the HBM byte counters of a
+    profiling run of this script)."""
+    import torch
+    n = mib * 2**20 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def measured_traffic(workload: str):
@@ -282,12 +289,16 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run a plain copy of this many MiB first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.copy_probe_mb > 0:
+        copy_probe(args.copy_probe_mb)
     out = run_c2(args)
     if not args.no_batched:
         out["batched"] = run_c4(args)

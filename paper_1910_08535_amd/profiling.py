@@ -1,0 +1,102 @@
+"""Summaries of rocprofv3 output (kernel-trace statistics and HBM counters).
+
+Used by hand after a profiling run:
+
+    python -m paper_1910_08535_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_1910_08535_amd.profiling traffic <fetch_counter_collection.csv>
+        <write_counter_collection.csv> <kernel substring> <copy MiB> <workload> "<commands>"
+
+`traffic` scales each counter by what it reads for a plain copy of known size (the
+torch copy kernel the benchmark runs with --copy-probe-mb), giving HBM bytes per launch
+of the kernel, and writes profiles/traffic_<workload>.json stamped with the hash of the
+kernel sources (bench.py reports the figure only while the sources are unchanged).
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1910_08535_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats_markdown(stats_csv: str, out_md: str, command: str) -> None:
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["# rocprofv3 kernel statistics", "", "Command (from the repository root, after "
+             "`cd /tmp && export TMPDIR=/tmp` as the profiler needs):", "", "```", command, "```",
+             "", "| kernel | calls | average (us) | min (us) | max (us) | share |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
+                     f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
+                     f"{float(r['Percentage']):.1f}% |")
+    lines.append("")
+    lines.append(f"Kernel sources hash: `{kernel_source_hash()}`")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(csv_path: str, counter: str):
+    vals = {}
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] != counter:
+            continue
+        vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, workload: str,
+            commands: str) -> dict:
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+
+    def pick(vals, needle):
+        keys = [k for k in vals if needle in k]
+        if not keys:
+            raise SystemExit(f"no kernel matching {needle!r} in {list(vals)[:5]}")
+        return keys[0], vals[keys[0]]
+
+    copy_bytes = copy_mib * 2**20
+    # the copy kernel is the largest-traffic elementwise kernel of the probe
+    cf = max(v for k, vs in fetch.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
+    cw = max(v for k, vs in write.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    kf, fv = pick(fetch, kernel)
+    kw, wv = pick(write, kernel)
+    fb = statistics.median(fv) * 1024.0 * f_scale
+    wb = statistics.median(wv) * 1024.0 * w_scale
+    rec = {"workload": workload, "kernel": kf, "dispatches": [len(fv), len(wv)],
+           "fetch_kib_per_dispatch_median": statistics.median(fv),
+           "write_kib_per_dispatch_median": statistics.median(wv),
+           "copy_probe_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+           "kernel_source_hash": kernel_source_hash(), "commands": commands}
+    out = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),
+                                 sys.argv[6], sys.argv[7]), indent=1))
+    else:
+        raise SystemExit(__doc__)
