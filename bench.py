@@ -13,7 +13,7 @@ through enough distinct (u, mass, lap) buffer sets (>= 512 MB) that the 256 MB
 Infinity Cache cannot hold the working set: inputs are resident in HBM when the
 timed region starts.
 
-Prints one JSON line (rank 0).  --gpus above 1 exits: this build runs on one GPU.
+Prints one JSON line (rank 0).  --gpus above 1 exits: the path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -293,7 +293,7 @@ def main():
                     help="run a plain copy of this many MiB first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the path runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
