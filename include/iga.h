@@ -78,7 +78,9 @@ typedef enum { IGA_SPANS_SUPPORT = 0, IGA_SPANS_ELEMENT = 1, IGA_SPANS_CUSTOM = 
 typedef struct {
     int32_t dim;        /* 1, 2 or 3                                                  */
     int32_t p;          /* B-spline degree on every axis: 2 (C1) or 3 (C2)             */
-    int64_t ne[3];      /* elements per axis, >= 1 (entries beyond dim ignored)        */
+    int64_t ne[3];      /* elements per axis, >= 1 (entries beyond dim ignored); at    */
+                        /* most 2^31-1 coefficients in all, and in 2D every array and  */
+                        /* band table below 4 GiB: N_x N_y < 2^29, N_a (2p+1) < 2^29    */
     double lo[3];       /* domain per axis, lo < hi                                    */
     double hi[3];
     int32_t nq[3];      /* Gauss points per element per axis, 1..16                    */

@@ -325,6 +325,14 @@ int validate_desc(const iga_mesh_desc* d)
         ngauss *= (size_t)d->ne[a] * d->nq[a];
     }
     if (ncoef >= (size_t)1 << 31 || ngauss >= (size_t)1 << 40) return IGA_E_INVAL;
+    if (d->dim == 2) {
+        // the 2D kernel addresses every array through buffer resources with 32-bit byte
+        // offsets: each coefficient/row array and each band table stays below 4 GiB
+        if (ncoef * sizeof(double) >= ((size_t)1 << 32)) return IGA_E_INVAL;
+        for (int a = 0; a < 2; ++a)
+            if ((size_t)(d->ne[a] + d->p) * (2 * d->p + 1) * sizeof(double) >= ((size_t)1 << 32))
+                return IGA_E_INVAL;
+    }
     if (d->spans != IGA_SPANS_SUPPORT && d->spans != IGA_SPANS_ELEMENT &&
         d->spans != IGA_SPANS_CUSTOM)
         return IGA_E_INVAL;

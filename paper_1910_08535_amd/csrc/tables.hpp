@@ -9,15 +9,6 @@
 
 namespace iga {
 
-// Knot t_k of the open uniform knot vector of degree p with ne elements on [lo, hi]
-// (Section 2: the first and the last knot repeated p+1 times).
-__device__ __forceinline__ double open_knot(int k, int p, int ne, double lo, double hi)
-{
-    if (k <= p) return lo;
-    if (k >= ne + p) return hi;
-    return lo + (hi - lo) * (double)(k - p) / (double)ne;
-}
-
 // Legendre polynomial P_n(z) and its derivative, by the three-term recurrence.
 __device__ __forceinline__ void legendre(int n, double z, double* pn, double* dpn)
 {
@@ -53,42 +44,51 @@ __device__ void gauss_node(int n, int i, double* x, double* w)
 }
 
 // Values, first and second derivatives of the p+1 B-splines e..e+p that can be nonzero
-// on element e, at the point x of that element: bottom-up triangle of the Cox-de Boor
-// recurrence for degrees 0..p, then the derivative relation
+// on element e, at the point with local coordinate s in [0, 1] of that element: bottom-up
+// triangle of the Cox-de Boor recurrence for degrees 0..p, then the derivative relation
 //   d/dx B_{j,k} = k ( B_{j,k-1}/(t_{j+k}-t_j) - B_{j+1,k-1}/(t_{j+k+1}-t_{j+1}) )
 // applied once (first derivatives of degrees p-1 and p) and twice (second, degree p).
+// The recurrence runs in element units relative to element e: knot t_k becomes the small
+// integer clamp(k-p, 0, ne) - e, so every difference is exact however fine the mesh, and
+// the derivatives are scaled by 1/h and 1/h^2 at the end (uniform elements of length h).
 // out[m][a] = m-th derivative of B_{e+a}.
-__device__ void basis_ders(int p, int ne, double lo, double hi, int e, double x,
+__device__ __forceinline__ double local_knot(int k, int p, int ne, int e)
+{
+    const int i = k - p < 0 ? 0 : (k - p > ne ? ne : k - p);
+    return (double)(i - e);
+}
+
+__device__ void basis_ders(int p, int ne, int e, double s, double inv_h,
                            double out[3][kMaxP + 1])
 {
     const int mu = e + p;   // knot interval [t_mu, t_{mu+1})
-    // V[k][i] = B_{mu-k+i, k}(x), i = 0..k
+    // V[k][i] = B_{mu-k+i, k}(s), i = 0..k
     double V[kMaxP + 1][kMaxP + 1];
     V[0][0] = 1.0;
     for (int k = 1; k <= p; ++k) {
         for (int i = 0; i <= k; ++i) {
             const int j = mu - k + i;
-            const double tj = open_knot(j, p, ne, lo, hi);
-            const double tjk = open_knot(j + k, p, ne, lo, hi);
-            const double tj1 = open_knot(j + 1, p, ne, lo, hi);
-            const double tjk1 = open_knot(j + k + 1, p, ne, lo, hi);
+            const double tj = local_knot(j, p, ne, e);
+            const double tjk = local_knot(j + k, p, ne, e);
+            const double tj1 = local_knot(j + 1, p, ne, e);
+            const double tjk1 = local_knot(j + k + 1, p, ne, e);
             const double lft = (i > 0) ? V[k - 1][i - 1] : 0.0;   // B_{j,k-1}
             const double rgt = (i < k) ? V[k - 1][i] : 0.0;       // B_{j+1,k-1}
             double v = 0.0;
-            if (tjk > tj) v += (x - tj) / (tjk - tj) * lft;
-            if (tjk1 > tj1) v += (tjk1 - x) / (tjk1 - tj1) * rgt;
+            if (tjk > tj) v += (s - tj) / (tjk - tj) * lft;
+            if (tjk1 > tj1) v += (tjk1 - s) / (tjk1 - tj1) * rgt;
             V[k][i] = v;
         }
     }
-    // first derivatives of degree k in {p-1, p}: D1[k][i] for B_{mu-k+i, k}
+    // first derivatives (per unit of s) of degree k in {p-1, p}: D1[k][i] for B_{mu-k+i, k}
     double D1[kMaxP + 1][kMaxP + 1];
     for (int k = (p >= 2 ? p - 1 : 1); k <= p; ++k) {
         for (int i = 0; i <= k; ++i) {
             const int j = mu - k + i;
-            const double tj = open_knot(j, p, ne, lo, hi);
-            const double tjk = open_knot(j + k, p, ne, lo, hi);
-            const double tj1 = open_knot(j + 1, p, ne, lo, hi);
-            const double tjk1 = open_knot(j + k + 1, p, ne, lo, hi);
+            const double tj = local_knot(j, p, ne, e);
+            const double tjk = local_knot(j + k, p, ne, e);
+            const double tj1 = local_knot(j + 1, p, ne, e);
+            const double tjk1 = local_knot(j + k + 1, p, ne, e);
             const double lft = (i > 0) ? V[k - 1][i - 1] : 0.0;
             const double rgt = (i < k) ? V[k - 1][i] : 0.0;
             double d = 0.0;
@@ -99,20 +99,20 @@ __device__ void basis_ders(int p, int ne, double lo, double hi, int e, double x,
     }
     for (int i = 0; i <= p; ++i) {
         out[0][i] = V[p][i];
-        out[1][i] = D1[p][i];
+        out[1][i] = D1[p][i] * inv_h;
         double d2 = 0.0;
         if (p >= 2) {
             const int j = mu - p + i;
-            const double tj = open_knot(j, p, ne, lo, hi);
-            const double tjk = open_knot(j + p, p, ne, lo, hi);
-            const double tj1 = open_knot(j + 1, p, ne, lo, hi);
-            const double tjk1 = open_knot(j + p + 1, p, ne, lo, hi);
+            const double tj = local_knot(j, p, ne, e);
+            const double tjk = local_knot(j + p, p, ne, e);
+            const double tj1 = local_knot(j + 1, p, ne, e);
+            const double tjk1 = local_knot(j + p + 1, p, ne, e);
             const double lft = (i > 0) ? D1[p - 1][i - 1] : 0.0;
             const double rgt = (i < p) ? D1[p - 1][i] : 0.0;
             if (tjk > tj) d2 += (double)p / (tjk - tj) * lft;
             if (tjk1 > tj1) d2 -= (double)p / (tjk1 - tj1) * rgt;
         }
-        out[2][i] = d2;
+        out[2][i] = d2 * inv_h * inv_h;
     }
 }
 
@@ -140,13 +140,13 @@ __global__ void gauss_tables_kernel(AxisTables t)
     const int e = idx / t.nq, q = idx % t.nq;
     double xi, w;
     gauss_node(t.nq, q, &xi, &w);
-    const double a0 = open_knot(e + t.p, t.p, t.ne, t.lo, t.hi);
-    const double a1 = open_knot(e + t.p + 1, t.p, t.ne, t.lo, t.hi);
-    const double x = a0 + 0.5 * (xi + 1.0) * (a1 - a0);
-    t.xg[idx] = x;
-    t.wg[idx] = 0.5 * w * (a1 - a0);
+    // uniform elements: h itself, not a difference of two rounded knots
+    const double h = (t.hi - t.lo) / (double)t.ne;
+    const double sl = 0.5 * (xi + 1.0);   // local coordinate in [0, 1]
+    t.xg[idx] = t.lo + (t.hi - t.lo) * (((double)e + sl) / (double)t.ne);
+    t.wg[idx] = 0.5 * w * h;
     double B[3][kMaxP + 1];
-    basis_ders(t.p, t.ne, t.lo, t.hi, e, x, B);
+    basis_ders(t.p, t.ne, e, sl, (double)t.ne / (t.hi - t.lo), B);
     for (int m = 0; m < 3; ++m)
         for (int a = 0; a <= t.p; ++a) t.bq[((size_t)idx * 3 + m) * (t.p + 1) + a] = B[m][a];
 }
@@ -181,8 +181,7 @@ __global__ void band_tables_kernel(AxisTables t)
                 fs += t.wg[eq] * sin(M_PI * t.xg[eq]);
             }
         t.fs_pg[r] = fs;
-        t.inv_len[r] = 1.0 / (open_knot(l + p + 1, p, t.ne, t.lo, t.hi) -
-                              open_knot(s + p, p, t.ne, t.lo, t.hi));
+        t.inv_len[r] = (double)t.ne / ((double)(l - s + 1) * (t.hi - t.lo));
     }
     if (r < t.N) {
         const int e0 = r - p < 0 ? 0 : r - p;

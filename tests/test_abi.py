@@ -54,6 +54,8 @@ def _desc(iga, **kw):
     (dict(nq=(0, 3, 3)), -2), (dict(nq=(3, 17, 3)), -2),
     (dict(ne=(0, 8, 8)), -1), (dict(hi=0.0), -1), (dict(spans=7), -1),
     (dict(ne=(50000, 50000, 8)), -1),
+    # 2D arrays and band tables must stay below 4 GiB (32-bit buffer offsets)
+    (dict(ne=(23171, 23171, 1)), -1), (dict(p=3, ne=(76_700_000, 2, 1)), -1),
 ])
 def test_create_rejects_bad_descriptors(iga, kw, code):
     h = C.c_void_p()

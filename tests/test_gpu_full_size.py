@@ -1,0 +1,169 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+* 2D Laplace, p = 2, 1024^2 elements, 3x3 Gauss, fused Petrov-Galerkin apply (mass and
+  Laplacian rows): sampled slabs of rows (first, middle, last) against the oracle,
+  which computes any slab of rows of the outermost axis on its own.
+* 3D heat, p = 3, 128^3 elements, 4^3 Gauss, dt = 1e-6, sin source: the first explicit
+  step, and the hundredth step taken from the GPU's own state after 99 graph-replayed
+  steps, on sampled z slabs against the oracle; 100 steps in one graph equal 99 + 1
+  bit for bit; the l2 norm does not grow.
+* Properties that hold at any size, up to the largest accepted 2D arrays: the B-spline
+  coefficients of a quadratic polynomial (its blossom at the p inner knots of each
+  B-spline) reproduce that polynomial exactly, so the support-span rows are closed-form
+  integrals over the spans and the Laplacian rows are Lap(poly) |S|.
+
+Tolerance: normwise relative error <= 1e-12 over the sampled rows of each array, except
+for the Laplacian rows of a smooth polynomial, whose FP64 conditioning is derived in the
+test (the oracle works in long double and is not subject to it).
+"""
+import numpy as np
+import pytest
+
+from closed_forms import quad_coefs, support_span_moments
+from paper_1910_08535_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def relerr(got, ref):
+    got, ref = np.asarray(got), np.asarray(ref)
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+@pytest.fixture(scope="module")
+def iga():
+    import torch
+    from paper_1910_08535_amd import iga as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+def cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ---- 2D, full size ------------------------------------------------------------------------
+
+def test_c2_full_size_sampled_rows(iga, orc):
+    c = inputs.Apply2D()
+    u = c.coefs()
+    mesh = iga.Mesh(2, c.p, c.ne, c.nq)
+    m, l = mesh.apply(iga.PG, cuda(u))
+    m, l = host(m), host(l)
+    pb = orc.Problem(dim=2, p=c.p, ne=c.ne, nq=c.nq)
+    for r0, r1 in ((0, 6), (509, 517), (1018, 1026)):
+        rm = orc.rhs(pb, orc.PG, u, alpha=1.0, rows=(r0, r1))
+        rl = orc.rhs(pb, orc.PG, u, beta=1.0, rows=(r0, r1))
+        assert relerr(m[r0:r1], rm) <= TOL, (r0, relerr(m[r0:r1], rm))
+        assert relerr(l[r0:r1], rl) <= TOL, (r0, relerr(l[r0:r1], rl))
+
+
+@pytest.mark.parametrize("p,ne,cols,lap", [
+    (2, (1024, 1024), None, True),
+    (2, (23160, 23160), None, True),              # N_x N_y just below 2^29 (4.29 GB per array)
+    (3, (76_695_000, 2), 4096, False),            # x band table just below 4 GiB
+])
+def test_2d_quadratic_reproduction(iga, p, ne, cols, lap):
+    """u_h = x^2 + 3 y^2 exactly; PG rows: mass = int_S u, Laplacian = 8 |S|.  (With
+    h = 1.3e-8 the Laplacian rows of a smooth field are beyond FP64, see below: that
+    case checks the mass rows only.)"""
+    import torch
+    nx, ny = ne
+    cx, cy = quad_coefs(p, nx), quad_coefs(p, ny)
+    u = torch.from_numpy(cx).cuda()[None, :] + 3.0 * torch.from_numpy(cy).cuda()[:, None]
+    mesh = iga.Mesh(2, p, ne, (p + 1, p + 1))
+    m, l = mesh.apply(iga.PG, u.contiguous())
+    torch.cuda.synchronize()
+    del u
+    Nx, Ny = nx + p, ny + p
+    ysel = sorted(set([0, 1, p, p + 1, Ny // 2, Ny - p - 1, Ny - 2, Ny - 1]))
+    ysel = [y for y in ysel if 0 <= y < Ny]
+    if cols is None:
+        xsel = np.arange(Nx)
+    else:
+        xsel = np.concatenate([np.arange(cols), Nx // 2 + np.arange(cols), Nx - cols + np.arange(cols)])
+    wx, x2 = support_span_moments(p, nx, xsel)
+    wy, y2 = support_span_moments(p, ny, np.asarray(ysel))
+    X = torch.from_numpy(xsel).cuda()
+    got_m = np.stack([host(m[y].index_select(0, X)) for y in ysel])
+    got_l = np.stack([host(l[y].index_select(0, X)) for y in ysel])
+    ref_m = x2[None, :] * wy[:, None] + 3.0 * wx[None, :] * y2[:, None]
+    ref_l = 8.0 * wx[None, :] * wy[:, None]
+    assert relerr(got_m, ref_m) <= TOL
+    # The Laplacian rows of a smooth field are sums of terms of size |u|/h (band taps of
+    # int B'' times coefficients) that cancel down to |Lap u| |S| ~ |Lap u| h^2: FP64
+    # round-off of those terms leaves a relative error of order eps |u| / (h^2 |Lap u|),
+    # about 1.3e5 eps at 1024^2 and 6.7e7 eps at 23160^2.  Bound: 64 times that, and
+    # never looser than 1e-12 is asked of rough data.
+    if lap:
+        h = 1.0 / max(nx, ny)
+        tol_l = max(TOL, 64 * np.finfo(float).eps * 4.0 / (h * h * 8.0))
+        assert relerr(got_l, ref_l) <= tol_l, (relerr(got_l, ref_l), tol_l)
+
+
+# ---- 3D heat, full size --------------------------------------------------------------------
+
+def _oracle_step_slab(orc, pb, u, dt, rows):
+    """One lumped explicit step on a z slab: PG rows of (u + dt Lap u + dt f) over |S|."""
+    b = orc.rhs(pb, orc.PG, u, 1.0, dt, dt, sin_amp=1.0, rows=rows)
+    lx, ly, lz = orc.span_lengths(pb)
+    return b / (lz[rows[0]:rows[1], None, None] * ly[None, :, None] * lx[None, None, :])
+
+
+def test_c3_full_size_steps(iga, orc):
+    import torch
+    c = inputs.Heat3D()
+    u0 = c.coefs()
+    mesh = iga.Mesh(3, c.p, c.ne, c.nq)
+    pb = orc.Problem(dim=3, p=c.p, ne=c.ne, nq=c.nq)
+    slabs = ((0, 2), (64, 66), (129, 131))
+    # step 1
+    a = cuda(u0)
+    mesh.explicit_step(a, c.dt, sin_amp=c.sin_amp, nsteps=1)
+    a1 = host(a)
+    for rows in slabs:
+        ref = _oracle_step_slab(orc, pb, u0, c.dt, rows)
+        assert relerr(a1[rows[0]:rows[1]], ref) <= TOL, rows
+    # 100 steps in one graph (the benchmark's launch) == 99 steps + 1 step, bitwise
+    b = cuda(u0)
+    mesh.explicit_step(b, c.dt, sin_amp=c.sin_amp, nsteps=c.nsteps)
+    d = cuda(u0)
+    mesh.explicit_step(d, c.dt, sin_amp=c.sin_amp, nsteps=c.nsteps - 1)
+    u99 = host(d)
+    mesh.explicit_step(d, c.dt, sin_amp=c.sin_amp, nsteps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(b, d)
+    u100 = host(b)
+    for rows in slabs:
+        ref = _oracle_step_slab(orc, pb, u99, c.dt, rows)
+        assert relerr(u100[rows[0]:rows[1]], ref) <= TOL, rows
+    # the lumped step does not amplify: ||u_100|| <= ||u_0||
+    assert np.linalg.norm(u100) <= np.linalg.norm(u0)
+
+
+def test_c3_full_size_quadratic_step(iga):
+    """u_h = x^2 + y^2 + z^2, f = 0: one step gives mean_S(u) + 6 dt on every span."""
+    import torch
+    c = inputs.Heat3D()
+    n = c.ne[0]
+    q = quad_coefs(c.p, n)
+    qt = torch.from_numpy(q).cuda()
+    u = (qt[None, None, :] + qt[None, :, None] + qt[:, None, None]).contiguous()
+    mesh = iga.Mesh(3, c.p, c.ne, c.nq)
+    mesh.explicit_step(u, c.dt, nsteps=1)
+    got = host(u)
+    w, x2 = support_span_moments(c.p, n, np.arange(n + c.p))
+    mean = x2 / w
+    ref = mean[None, None, :] + mean[None, :, None] + mean[:, None, None] + 6.0 * c.dt
+    assert relerr(got, ref) <= TOL

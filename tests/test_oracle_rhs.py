@@ -220,3 +220,33 @@ def test_explicit_step_invariants(orc, dim, p, ne):
     inv = _kron_apply([np.diag(1.0 / l) for l in lens], b1)
     np.testing.assert_allclose(orc.explicit_step(pb, u, 1e-4, f_table=f, sin_amp=0.5), inv,
                                rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("p,ne", [(2, (7, 5)), (3, (6, 9)), (3, (1, 4))])
+def test_quadratic_precision_closed_forms(orc, p, ne):
+    """Quadratic precision of B-splines (coefficients = blossom of x^2 at the inner
+    knots of each B-spline) makes u_h = x^2 + 3 y^2 exactly, so:
+      PG rows (support spans):  int_S u_h = closed form, int_S Lap u_h = 8 |S|;
+      Galerkin rows:            int B_i B_j Lap u_h = 8 int B_i int B_j (Laplacian form)
+                                and the by-parts form differs from it only on the
+                                boundary rows;
+      explicit step (f = 0):    mean_S(u_h) + 8 dt."""
+    from closed_forms import bspline_integrals, quad_coefs, support_span_moments
+    nx, ny = ne
+    u = quad_coefs(p, nx)[None, :] + 3.0 * quad_coefs(p, ny)[:, None]
+    pb = orc.Problem(dim=2, p=p, ne=ne, nq=(p + 1, p + 1))
+    wx, x2 = support_span_moments(p, nx, np.arange(nx + p))
+    wy, y2 = support_span_moments(p, ny, np.arange(ny + p))
+    area = wx[None, :] * wy[:, None]
+    mass = x2[None, :] * wy[:, None] + 3.0 * wx[None, :] * y2[:, None]
+    np.testing.assert_allclose(orc.rhs(pb, orc.PG, u, alpha=1.0), mass, rtol=1e-14)
+    np.testing.assert_allclose(orc.rhs(pb, orc.PG, u, beta=1.0), 8.0 * area, rtol=1e-13)
+    gi = 8.0 * bspline_integrals(p, nx)[None, :] * bspline_integrals(p, ny)[:, None]
+    np.testing.assert_allclose(orc.rhs(pb, orc.GALERKIN_LAPLACIAN, u, beta=1.0), gi, rtol=1e-13)
+    bp = orc.rhs(pb, orc.GALERKIN_BYPARTS, u, beta=1.0)
+    inner = (slice(1, -1), slice(1, -1))
+    if ny + p > 2 and nx + p > 2:
+        np.testing.assert_allclose(bp[inner], gi[inner], rtol=1e-13)
+    dt = 1e-3
+    step = orc.explicit_step(pb, u, dt)
+    np.testing.assert_allclose(step, mass / area + 8.0 * dt, rtol=1e-14)
