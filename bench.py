@@ -220,7 +220,7 @@ def run_c3(args) -> dict:
             "note": "working set in the Infinity Cache across steps",
             "rotated_16_problems": {"us_per_step": rot_s * 1e6, "GPs": gp_step / rot_s,
                                     "hbm_frac": bytes_step / rot_s / (HBM_PEAK_GBS * 1e9)},
-            "kernel": "iga::apply3d_kernel<3, 32, 16, 9>"}
+            "kernel": "iga::apply3d_kernel<3, 9>"}
 
 
 def run_c4(args) -> dict:

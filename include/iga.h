@@ -79,8 +79,9 @@ typedef struct {
     int32_t dim;        /* 1, 2 or 3                                                  */
     int32_t p;          /* B-spline degree on every axis: 2 (C1) or 3 (C2)             */
     int64_t ne[3];      /* elements per axis, >= 1 (entries beyond dim ignored); at    */
-                        /* most 2^31-1 coefficients in all, and in 2D every array and  */
-                        /* band table below 4 GiB: N_x N_y < 2^29, N_a (2p+1) < 2^29    */
+                        /* most 2^31-1 coefficients in all; in 2D every array and band */
+                        /* table below 4 GiB: N_x N_y < 2^29, N_a (2p+1) < 2^29; in 3D */
+                        /* one plane below 4 GiB: N_x N_y < 2^29                       */
     double lo[3];       /* domain per axis, lo < hi                                    */
     double hi[3];
     int32_t nq[3];      /* Gauss points per element per axis, 1..16                    */
@@ -164,12 +165,13 @@ int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, i
      IGA_TILE_2D_ORDER   2D chunk order: 0 = XCD-aware, row bands first (default);
                          1 = XCD-aware, strips first; 2 = plain dispatch order
      IGA_TILE_3D_PLANES  output planes per 3D z-chunk: 1..32, 0 = automatic (default)
-     IGA_TILE_3D_SHAPE   3D in-plane tile: 0 = 32 x 16 (default), 1 = 64 x 8
+     IGA_TILE_3D_ROWS    output rows per 3D tile: even, 2..32, 0 = automatic (default;
+                         fewer when the tile's footprint would not fit a workgroup)
    Changing a setting drops the context's cached graph.
    Errors: IGA_E_INVAL (unknown key or value). */
 #define IGA_TILE_2D_ROWS 1
 #define IGA_TILE_3D_PLANES 2
-#define IGA_TILE_3D_SHAPE 4
+#define IGA_TILE_3D_ROWS 4
 #define IGA_TILE_2D_ORDER 5
 int iga_set_tile(iga_ctx *ctx, int32_t key, int32_t value);
 int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);

@@ -16,8 +16,8 @@
 // whose taps vary only in the first and last p rows of an axis (open knots).
 //
 // Memory: u is read once from HBM per tile plus p-wide halos (served by L2), rows are
-// written once.  The kernels are HBM-bound for p = 2 and near the FP64 ridge for
-// p = 3 in 3D; the per-tile data stays in LDS (x pass) and registers (z ring).
+// written once.  The 1D and 2D kernels live here; the 3D kernel (z pass first) is in
+// apply3d.hpp.
 #pragma once
 
 #include "common.hpp"
@@ -67,206 +67,6 @@ __global__ __launch_bounds__(kBlock) void apply1d_kernel(ApplyArgs g)
         d = fma(X.D[(size_t)r * W + k], uj, d);
     }
     finish_row<MODE>(g, r, m, d, X.S[r], X.F[r]);
-}
-
-// ---------------------------------------------------------------------------------
-// Shared pieces of the 2D / 3D kernels.
-//
-// A TX x TY output tile of one plane is processed by kBlock threads: thread t owns
-// column t % TX and rows t / TX + m * (kBlock / TX).  Its input is the coefficient tile
-// of (TY+2P) x (TX+2P) values, staged in LDS.
-// ---------------------------------------------------------------------------------
-template <int P, int TX, int TY>
-struct Tile {
-    static constexpr int W = 2 * P + 1;
-    static constexpr int HX = TX + 2 * P;
-    static constexpr int HY = TY + 2 * P;
-    static constexpr int RPP = kBlock / TX;                  // rows per pass
-    static constexpr int NXR = (HY + RPP - 1) / RPP;         // x-pass rows per thread
-    static constexpr int Q = TY / RPP;                       // output rows per thread
-    static constexpr int NL = (HY * HX + kBlock - 1) / kBlock;   // tile values per thread
-    static constexpr int NC = (TY * (2 * W + 2) + kBlock - 1) / kBlock;   // band values per thread
-    static_assert(kBlock % TX == 0 && TY % RPP == 0, "tile shape");
-};
-
-// The coefficient tile of one plane through registers.  issue() puts every global load
-// of the tile in flight; store() (which waits for them) moves the values to LDS.
-// Interior tiles use per-thread offsets computed once; tiles that touch the array's
-// edge clamp every index into the array (the clamped values only ever meet band
-// entries that are exactly zero, so they contribute nothing).
-template <int P, int TX, int TY>
-struct TileRegs {
-    using T = Tile<P, TX, TY>;
-    double v[T::NL];
-
-    __device__ __forceinline__ void issue(const double* __restrict__ plane, const int (&rel)[T::NL],
-                                          int x0, int y0, int Nx, int Ny)
-    {
-        const bool inner = x0 >= P && y0 >= P && x0 + TX + P <= Nx && y0 + TY + P <= Ny;
-        if (inner) {
-            const double* __restrict__ base = plane + ((size_t)(y0 - P) * Nx + (x0 - P));
-#pragma unroll
-            for (int j = 0; j < T::NL; ++j) v[j] = base[rel[j]];
-        } else {
-#pragma unroll
-            for (int j = 0; j < T::NL; ++j) {
-                const int i = min((int)threadIdx.x + j * kBlock, T::HY * T::HX - 1);
-                const int iy = i / T::HX, ix = i - iy * T::HX;
-                const int gy = min(max(y0 - P + iy, 0), Ny - 1);
-                const int gx = min(max(x0 - P + ix, 0), Nx - 1);
-                v[j] = plane[(size_t)gy * Nx + gx];
-            }
-        }
-    }
-
-    __device__ __forceinline__ void zero()
-    {
-#pragma unroll
-        for (int j = 0; j < T::NL; ++j) v[j] = 0.0;
-    }
-
-    __device__ __forceinline__ void store(double* __restrict__ su) const
-    {
-#pragma unroll
-        for (int j = 0; j < T::NL; ++j) {
-            const int i = (int)threadIdx.x + j * kBlock;
-            if (j < T::NL - 1 || i < T::HY * T::HX) su[i] = v[j];
-        }
-    }
-};
-
-// rel[j] = iy * Nx + ix of this thread's j-th tile value (index clamped into the tile)
-template <int P, int TX, int TY, int NL>
-__device__ __forceinline__ void tile_offsets(int (&rel)[NL], int Nx)
-{
-    using T = Tile<P, TX, TY>;
-    static_assert(NL == T::NL, "offset count");
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-        const int i = min((int)threadIdx.x + j * kBlock, T::HY * T::HX - 1);
-        const int iy = i / T::HX;
-        rel[j] = iy * Nx + (i - iy * T::HX);
-    }
-}
-
-// Per-column x factors of one tile column (registers) and the per-row band rows of the
-// tile's TY output rows (loaded into registers, one or two values per thread, then
-// published through LDS).
-template <int P, int TX, int TY>
-struct TileCoefs {
-    using T = Tile<P, TX, TY>;
-    static constexpr int W = T::W;
-    double mx[W], dx[W], sx, fx;
-    double cv[T::NC];
-
-    __device__ __forceinline__ void issue(const AxisOp& X, const AxisOp& Y, int x0, int y0)
-    {
-        const int gx = x0 + (int)threadIdx.x % TX;
-        const bool ok = gx < X.R;
-        const int r = ok ? gx : 0;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            mx[k] = X.M[(size_t)r * W + k];
-            dx[k] = X.D[(size_t)r * W + k];
-        }
-        sx = X.S[r];
-        fx = X.F[r];
-        if (!ok) {
-#pragma unroll
-            for (int k = 0; k < W; ++k) mx[k] = dx[k] = 0.0;
-            sx = fx = 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < T::NC; ++c) {
-            const int i = (int)threadIdx.x + c * kBlock;
-            const int row = i / (2 * W + 2), k = i - row * (2 * W + 2);
-            const int yr = min(y0 + row, Y.R - 1);
-            double v = 0.0;
-            if (k < W)
-                v = Y.M[(size_t)yr * W + k];
-            else if (k < 2 * W)
-                v = Y.D[(size_t)yr * W + (k - W)];
-            else if (k == 2 * W)
-                v = Y.S[yr];
-            else
-                v = Y.F[yr];
-            cv[c] = (y0 + row < Y.R && i < TY * (2 * W + 2)) ? v : 0.0;
-        }
-    }
-
-    // rows of the tile: cM[row*W+k], cD[row*W+k], cS[row], cF[row]
-    __device__ __forceinline__ void publish(double* cM, double* cD, double* cS, double* cF) const
-    {
-#pragma unroll
-        for (int c = 0; c < T::NC; ++c) {
-            const int i = (int)threadIdx.x + c * kBlock;
-            if (i >= TY * (2 * W + 2)) continue;
-            const int row = i / (2 * W + 2), k = i - row * (2 * W + 2);
-            if (k < W)
-                cM[row * W + k] = cv[c];
-            else if (k < 2 * W)
-                cD[row * W + (k - W)] = cv[c];
-            else if (k == 2 * W)
-                cS[row] = cv[c];
-            else
-                cF[row] = cv[c];
-        }
-    }
-};
-
-// x pass: A = Mx u, B = Dx u on all HY rows of the tile, this thread's column.
-template <int P, int TX, int TY>
-__device__ __forceinline__ void x_pass(const double* __restrict__ su, double* __restrict__ sA,
-                                       double* __restrict__ sB, const double (&mx)[2 * P + 1],
-                                       const double (&dx)[2 * P + 1])
-{
-    using T = Tile<P, TX, TY>;
-    const int c = (int)threadIdx.x % TX, r0 = (int)threadIdx.x / TX;
-#pragma unroll
-    for (int m = 0; m < T::NXR; ++m) {
-        const int r = r0 + m * T::RPP;
-        if (r < T::HY) {
-            double a = 0.0, b = 0.0;
-#pragma unroll
-            for (int k = 0; k < T::W; ++k) {
-                const double v = su[r * T::HX + c + k];
-                a = fma(mx[k], v, a);
-                b = fma(dx[k], v, b);
-            }
-            sA[r * TX + c] = a;
-            sB[r * TX + c] = b;
-        }
-    }
-}
-
-// Band rows r0 .. r0+n-1 of one axis staged in LDS (used for the z rows of a 3D chunk).
-template <int W>
-__device__ __forceinline__ void stage_band_rows(double* __restrict__ cM, double* __restrict__ cD,
-                                                double* __restrict__ cS, double* __restrict__ cF,
-                                                const AxisOp& A, int r0, int n)
-{
-    for (int i = threadIdx.x; i < n * (2 * W + 2); i += kBlock) {
-        const int row = i / (2 * W + 2), k = i - row * (2 * W + 2);
-        const int r = r0 + row;
-        const bool ok = r < A.R;
-        double v;
-        if (k < W)
-            v = ok ? A.M[(size_t)r * W + k] : 0.0;
-        else if (k < 2 * W)
-            v = ok ? A.D[(size_t)r * W + (k - W)] : 0.0;
-        else if (k == 2 * W)
-            v = ok ? A.S[r] : 0.0;
-        else
-            v = ok ? A.F[r] : 0.0;
-        if (k < W)
-            cM[row * W + k] = v;
-        else if (k < 2 * W)
-            cD[row * W + (k - W)] = v;
-        else if (k == 2 * W)
-            cS[row] = v;
-        else
-            cF[row] = v;
-    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -525,130 +325,6 @@ __global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
     const int bx = tg.TZ == 1 ? L / tg.ty : L % tg.tx;
     const int by = tg.TZ == 1 ? L % tg.ty : L / tg.tx;
     apply2d_chunk<P, TY, MODE, VEC>(g, bx, by, lds);
-}
-
-// ---------------------------------------------------------------------------------
-// 3D: in-plane output tile of TX x TY, streamed along z over a chunk of TZ output
-// planes.  Each input plane goes through the x pass (LDS) and the y pass; the y-pass
-// results of the last 2P+1 planes stay in a register ring from which the z pass forms
-// one output plane per input plane.  The coefficient planes flow through a second
-// register ring of 2P+1 slots: the loads of plane z+2P+1 are issued as soon as plane z
-// has been moved to LDS, so 2P+1 planes are in flight while one is computed.
-// ---------------------------------------------------------------------------------
-template <int P, int TX, int TY, int MODE>
-__global__ __launch_bounds__(kBlock) void apply3d_kernel(ApplyArgs g, TileGrid tg)
-{
-    constexpr int MAXTZ = 32;
-    using T = Tile<P, TX, TY>;
-    constexpr int W = T::W;
-    constexpr int Q = T::Q;
-    __shared__ double su[T::HY * T::HX];
-    __shared__ double sA[T::HY * TX];
-    __shared__ double sB[T::HY * TX];
-    __shared__ double yM[TY * W], yD[TY * W], yS[TY], yF[TY];
-    __shared__ double zM[MAXTZ * W], zD[MAXTZ * W], zS[MAXTZ], zF[MAXTZ];
-
-    const AxisOp &X = g.ax[0], &Y = g.ax[1], &Z = g.ax[2];
-    const int L = xcd_logical_block(blockIdx.x, tg.nblk);
-    const int bx = L % tg.tx;
-    const int by = (L / tg.tx) % tg.ty;
-    const int bz = L / (tg.tx * tg.ty);
-    const int x0 = bx * TX, y0 = by * TY;
-    const int z0 = bz * tg.TZ;
-    const int z1 = min(z0 + tg.TZ, Z.R);
-    const size_t plane_in = (size_t)X.N * Y.N;
-    const int zlo = max(z0 - P, 0);       // input planes that exist: [zlo, zhi)
-    const int zhi = min(z1 + P, Z.N);
-    const int c = (int)threadIdx.x % TX, r0 = (int)threadIdx.x / TX;
-
-    int rel[T::NL];
-    tile_offsets<P, TX, TY, T::NL>(rel, X.N);
-    // plane z0 - P + s sits in ring slot s (mod W)
-    TileRegs<P, TX, TY> pre[W];
-#pragma unroll
-    for (int s = 0; s < W; ++s) {
-        const int zi = z0 - P + s;
-        if (zi >= zlo && zi < zhi)
-            pre[s].issue(g.u + (size_t)zi * plane_in, rel, x0, y0, X.N, Y.N);
-        else
-            pre[s].zero();
-    }
-    TileCoefs<P, TX, TY> co;
-    co.issue(X, Y, x0, y0);
-    co.publish(yM, yD, yS, yF);
-    stage_band_rows<W>(zM, zD, zS, zF, Z, z0, z1 - z0);
-
-    double rc[W][Q], re[W][Q];
-#pragma unroll
-    for (int s = 0; s < W; ++s)
-#pragma unroll
-        for (int j = 0; j < Q; ++j) rc[s][j] = re[s][j] = 0.0;
-
-    for (int zb = z0 - P; zb < z1 + P; zb += W) {
-#pragma unroll
-        for (int ph = 0; ph < W; ++ph) {
-            const int zi = zb + ph;
-            if (zi >= z1 + P) break;
-            const bool have = zi >= zlo && zi < zhi;
-            if (have) {
-                // su was last read by the previous x pass, which every thread finished
-                // before the barrier that precedes the previous y pass.
-                pre[ph].store(su);
-                __syncthreads();
-            }
-            // refill this slot with plane zi + W (registers are private: no hazard even
-            // when plane zi itself lies outside the array)
-            if (zi + W >= zlo && zi + W < zhi)
-                pre[ph].issue(g.u + (size_t)(zi + W) * plane_in, rel, x0, y0, X.N, Y.N);
-            if (have) {
-                x_pass<P, TX, TY>(su, sA, sB, co.mx, co.dx);
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < Q; ++j) {
-                    const int oy = r0 + j * T::RPP;
-                    double cc = 0.0, e = 0.0;
-#pragma unroll
-                    for (int k = 0; k < W; ++k) {
-                        const double my = yM[oy * W + k];
-                        const double dy = yD[oy * W + k];
-                        const double a = sA[(oy + k) * TX + c];
-                        const double b = sB[(oy + k) * TX + c];
-                        cc = fma(my, a, cc);
-                        e = fma(dy, a, e);
-                        e = fma(my, b, e);
-                    }
-                    rc[ph][j] = cc;
-                    re[ph][j] = e;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < Q; ++j) rc[ph][j] = re[ph][j] = 0.0;
-            }
-            const int zo = zi - P;
-            if (zo >= z0) {
-                const int iz = zo - z0;
-                const int gx = x0 + c;
-#pragma unroll
-                for (int j = 0; j < Q; ++j) {
-                    double mass = 0.0, lap = 0.0;
-#pragma unroll
-                    for (int k = 0; k < W; ++k) {
-                        const int s = (ph + 1 + k) % W;   // ring slot of plane zo - P + k
-                        const double mz = zM[iz * W + k];
-                        const double dz = zD[iz * W + k];
-                        mass = fma(mz, rc[s][j], mass);
-                        lap = fma(dz, rc[s][j], lap);
-                        lap = fma(mz, re[s][j], lap);
-                    }
-                    const int oy = r0 + j * T::RPP;
-                    const int gy = y0 + oy;
-                    if (gx < X.R && gy < Y.R)
-                        finish_row<MODE>(g, ((size_t)zo * Y.R + gy) * X.R + gx, mass, lap,
-                                   co.sx * yS[oy] * zS[iz], co.fx * yF[oy] * zF[iz]);
-                }
-            }
-        }
-    }
 }
 
 // Rows without a u-term: out_r = S(r) ( gsep prod_a F_a(r_a) + garr farr_r ).

@@ -19,6 +19,11 @@ struct AxisOp {
     const double* F;   // [R] separable source factor or null
     int R;             // rows
     int N;             // basis functions (columns)
+    // Rows ilo..ihi (empty when ilo > ihi) have bitwise identical entries in M and D:
+    // rows whose elements and B-splines all lie away from the repeated end knots (the
+    // tables evaluate B-splines in element-local knot units, so every such element
+    // yields the same values, summed in the same order).
+    int ilo, ihi;
 };
 
 // out_r  = S(r) * ( alpha (Mass u)_r + beta (Lap u)_r + gsep * prod_a F_a(r_a) + garr * farr_r )

@@ -13,6 +13,7 @@
 #include "iga.h"
 
 #include "apply.hpp"
+#include "apply3d.hpp"
 #include "common.hpp"
 #include "source.hpp"
 #include "tables.hpp"
@@ -65,8 +66,8 @@ struct iga_ctx {
     // tile configuration
     int ty2d = 8;
     int order2d = 0;
-    int tz3d = 0;
-    int shape3d = 0;
+    int tz3d = 0;   // 3D planes per z-chunk, 0 = automatic
+    int ty3d = 0;   // 3D rows per tile, 0 = automatic
 };
 
 namespace {
@@ -142,21 +143,29 @@ ApplyArgs make_args(const iga_ctx* c, int form, bool step, bool sep_source)
                 o.R = t.N;
             }
             o.N = t.N;
+            // rows with identical band entries: every element of the row's span (or of
+            // supp B_i) and every B-spline there clear of the repeated end knots, i.e.
+            // elements p .. ne-1-p only
+            const int p = c->p, ne = c->ne[a];
+            if (form == IGA_PG && c->spans == IGA_SPANS_ELEMENT) {
+                o.ilo = p;
+                o.ihi = ne - 1 - p;
+            } else if (form == IGA_PG && c->spans == IGA_SPANS_CUSTOM) {
+                o.ilo = 1;
+                o.ihi = 0;
+            } else {
+                o.ilo = 2 * p;
+                o.ihi = ne - 1 - p;
+            }
         } else {
             o.M = o.D = c->unit;
             o.F = o.S = c->ones;
             o.R = o.N = 1;
+            o.ilo = 0;
+            o.ihi = 0;
         }
     }
     return g;
-}
-
-int pick_tz(int tx, int ty, int R2)
-{
-    // enough z-chunks that the launch has several workgroups per CU
-    int TZ = 16;
-    while (TZ > 4 && (size_t)tx * ty * ((R2 + TZ - 1) / TZ) < 1024) TZ /= 2;
-    return TZ;
 }
 
 template <int P, int TY, int MODE>
@@ -177,17 +186,74 @@ void launch_2d(const ApplyArgs& g, hipStream_t s, int order)
                            tg);
 }
 
-template <int P, int TX, int TY, int MODE>
+// Geometry of a 3D launch: tiles of about 64 output columns; the largest even number of
+// rows whose footprint fits the threads' register rings and whose y and x tasks fit one
+// pass of the workgroup; then the z-chunk depth that fills the chip in the fewest rounds
+// of workgroups (a halo plane costs loads only, counted as a third of a plane).
+iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t* lds_bytes)
+{
+    using namespace iga;
+    const int P = c->p, Rx = g.ax[0].R, Ry = g.ax[1].R, Rz = g.ax[2].R;
+    Plan3D pl;
+    pl.tx = std::max(1, (Rx + 32) / 66);
+    pl.TX = (Rx + pl.tx - 1) / pl.tx;
+    pl.TX += pl.TX & 1;
+    pl.tx = (Rx + pl.TX - 1) / pl.TX;
+    pl.LW = pl.TX + 2 * P;
+    const int NT = kMaxNT3;
+    int TY = 2;
+    for (int cand = 2; cand <= 32; cand += 2) {
+        if ((cand + 2 * P) * pl.LW > kNPZ * NT) break;
+        if ((cand / 2) * pl.LW > NT || cand * (pl.TX / 2) > NT) break;
+        if (lds3d_doubles(cand, pl.LW, P) * sizeof(double) > 64 * 1024) break;
+        TY = cand;
+    }
+    if (c->ty3d > 0) TY = c->ty3d;
+    // every footprint point needs a ring slot of some thread; LDS stays within 64 KB
+    while (TY > 2 && ((TY + 2 * P) * pl.LW > kNPZ * NT ||
+                      lds3d_doubles(TY, pl.LW, P) * sizeof(double) > 64 * 1024))
+        TY -= 2;
+    TY = std::min(TY, Ry + (Ry & 1));
+    pl.ty = (Ry + TY - 1) / TY;
+    TY = (Ry + pl.ty - 1) / pl.ty;
+    TY += TY & 1;
+    pl.TY = TY;
+    pl.ty = (Ry + TY - 1) / TY;
+    if (c->tz3d > 0) {
+        pl.TZ = std::min(c->tz3d, Rz);
+    } else {
+        const int slots = 2 * 256;
+        double best = 1e300;
+        pl.TZ = 1;
+        for (int tz = 1; tz <= std::min(Rz, 64); ++tz) {
+            const long blocks = (long)pl.tx * pl.ty * ((Rz + tz - 1) / tz);
+            const long rounds = (blocks + slots - 1) / slots;
+            const double cost = (double)rounds * (tz + 2.0 * P / 3.0);
+            if (cost <= best) {
+                best = cost;
+                pl.TZ = tz;
+            }
+        }
+    }
+    pl.tz = (Rz + pl.TZ - 1) / pl.TZ;
+    pl.nblk = pl.tx * pl.ty * pl.tz;
+    // threads: enough for the footprint and the y and x tasks, in whole waves
+    const int need = std::max({((pl.TY + 2 * P) * pl.LW + kNPZ - 1) / kNPZ, (pl.TY / 2) * pl.LW,
+                               pl.TY * (pl.TX / 2)});
+    *nthreads = std::min(NT, std::max(64, (need + 63) / 64 * 64));
+    // every footprint point needs a ring slot
+    while ((size_t)*nthreads * kNPZ < (size_t)(pl.TY + 2 * P) * pl.LW && *nthreads < NT) *nthreads += 64;
+    *lds_bytes = lds3d_doubles(pl.TY, pl.LW, P) * sizeof(double);
+    return pl;
+}
+
+template <int P, int MODE>
 void launch_3d(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
 {
-    TileGrid tg;
-    tg.tx = (g.ax[0].R + TX - 1) / TX;
-    tg.ty = (g.ax[1].R + TY - 1) / TY;
-    tg.TZ = c->tz3d > 0 ? c->tz3d : pick_tz(tg.tx, tg.ty, g.ax[2].R);
-    tg.tz = (g.ax[2].R + tg.TZ - 1) / tg.TZ;
-    tg.nblk = tg.tx * tg.ty * tg.tz;
-    hipLaunchKernelGGL((iga::apply3d_kernel<P, TX, TY, MODE>), dim3(tg.nblk), dim3(kBlock), 0, s,
-                       g, tg);
+    int nt = 0;
+    size_t lds = 0;
+    const iga::Plan3D pl = plan_3d(c, g, &nt, &lds);
+    hipLaunchKernelGGL((iga::apply3d_kernel<P, MODE>), dim3(pl.nblk), dim3(nt), lds, s, g, pl);
 }
 
 template <int P, int MODE>
@@ -206,10 +272,7 @@ void launch_apply_pm(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
         else
             launch_2d<P, 4, MODE>(g, s, c->order2d);
     } else {
-        if (c->shape3d == 1)
-            launch_3d<P, 64, 8, MODE>(c, g, s);
-        else
-            launch_3d<P, 32, 16, MODE>(c, g, s);
+        launch_3d<P, MODE>(c, g, s);
     }
 }
 
@@ -332,6 +395,11 @@ int validate_desc(const iga_mesh_desc* d)
         for (int a = 0; a < 2; ++a)
             if ((size_t)(d->ne[a] + d->p) * (2 * d->p + 1) * sizeof(double) >= ((size_t)1 << 32))
                 return IGA_E_INVAL;
+    }
+    if (d->dim == 3) {
+        // the 3D kernel reads one coefficient plane through a buffer resource
+        if ((size_t)(d->ne[0] + d->p) * (size_t)(d->ne[1] + d->p) * sizeof(double) >= ((size_t)1 << 32))
+            return IGA_E_INVAL;
     }
     if (d->spans != IGA_SPANS_SUPPORT && d->spans != IGA_SPANS_ELEMENT &&
         d->spans != IGA_SPANS_CUSTOM)
@@ -539,9 +607,9 @@ int iga_set_tile(iga_ctx* c, int32_t key, int32_t value)
         if (value < 0 || value > 32) return IGA_E_INVAL;
         c->tz3d = value;
         break;
-    case IGA_TILE_3D_SHAPE:
-        if (value != 0 && value != 1) return IGA_E_INVAL;
-        c->shape3d = value;
+    case IGA_TILE_3D_ROWS:
+        if (value < 0 || value > 32 || (value & 1)) return IGA_E_INVAL;
+        c->ty3d = value;
         break;
     default:
         return IGA_E_INVAL;
@@ -557,7 +625,7 @@ int iga_get_tile(const iga_ctx* c, int32_t key, int32_t* value)
     case IGA_TILE_2D_ROWS: *value = c->ty2d; break;
     case IGA_TILE_2D_ORDER: *value = c->order2d; break;
     case IGA_TILE_3D_PLANES: *value = c->tz3d; break;
-    case IGA_TILE_3D_SHAPE: *value = c->shape3d; break;
+    case IGA_TILE_3D_ROWS: *value = c->ty3d; break;
     default: return IGA_E_INVAL;
     }
     return IGA_OK;

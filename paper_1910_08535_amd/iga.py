@@ -21,7 +21,7 @@ IGA_OK, IGA_E_INVAL, IGA_E_UNSUPPORTED, IGA_E_NOMEM, IGA_E_DEVICE, IGA_E_AGAIN =
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM = 0, 1, 2
-TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_SHAPE, TILE_2D_ORDER = 1, 2, 4, 5
+TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_ROWS, TILE_2D_ORDER = 1, 2, 4, 5
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 _P64 = C.POINTER(C.c_int64)

@@ -196,3 +196,47 @@ def test_graph_equals_single_launches(iga):
         mesh.explicit_step(b, 1e-5, sin_amp=1.0, nsteps=1)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("spans", ["support", "element"])
+def test_interior_band_rows_identical(iga, p, spans):
+    """The 3D kernel loads one set of taps for the interior rows of an axis (elements
+    p .. ne-1-p only): those rows of every banded factor must be bitwise identical."""
+    import torch
+    ne = 40
+    mesh = iga.Mesh(1, p, (ne,), (p + 1,), spans=spans)
+    for form in FORMS:
+        bands = mesh.assemble(form)
+        torch.cuda.synchronize()
+        b = bands[0].cpu().numpy()
+        if form == iga.PG and spans == "element":
+            lo, hi = p, ne - 1 - p
+        else:
+            lo, hi = 2 * p, ne - 1 - p
+        for f in range(2):
+            rows = b[f, lo:hi + 1]
+            assert (rows == rows[0]).all(), (form, f)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_3d_tile_settings(iga, orc, p):
+    """Every rows-per-tile / planes-per-chunk setting matches the oracle (odd sizes,
+    several tiles along every axis, ragged last tiles)."""
+    ne = (71, 45, 29)
+    nq = (p + 1,) * 3
+    mesh = iga.Mesh(3, p, ne, nq)
+    pb = orc.Problem(dim=3, p=p, ne=ne, nq=nq)
+    u = inputs.normal_coefs(ne, p, seed=21)
+    ud = cuda(u)
+    rm = orc.rhs(pb, orc.PG, u, alpha=1.0)
+    rl = orc.rhs(pb, orc.PG, u, beta=1.0)
+    for rows, planes in ((0, 0), (2, 1), (4, 3), (6, 32), (32, 5), (10, 7)):
+        mesh.set_tile(iga.TILE_3D_ROWS, rows)
+        mesh.set_tile(iga.TILE_3D_PLANES, planes)
+        assert mesh.get_tile(iga.TILE_3D_ROWS) == rows
+        m, l = mesh.apply(iga.PG, ud)
+        assert relerr(host(m), rm) <= TOL, (rows, planes)
+        assert relerr(host(l), rl) <= TOL, (rows, planes)
+    with pytest.raises(iga.IGAError):
+        mesh.set_tile(iga.TILE_3D_ROWS, 3)
