@@ -48,6 +48,41 @@ __device__ __forceinline__ void finish_row(const ApplyArgs& g, size_t idx, doubl
     }
 }
 
+// The rows idx and idx + 1 (the second only when `two`) with one 16-byte access per array
+// where both exist.
+template <int MODE>
+__device__ __forceinline__ double row_value(const ApplyArgs& g, double mass, double lap, double scale,
+                                            double fsep, double farr)
+{
+    double v = fma(g.alpha, mass, g.beta * lap);
+    if constexpr ((MODE & kScaleSrc) != 0) v = fma(g.gsep, fsep, v);
+    if constexpr ((MODE & kFarr) != 0) v = fma(g.garr, farr, v);
+    if constexpr ((MODE & kScaleSrc) != 0) v *= scale;
+    return v;
+}
+
+template <int MODE>
+__device__ __forceinline__ void finish_pair(const ApplyArgs& g, size_t idx, double m0, double l0, double s0,
+                                            double f0, double m1, double l1, double s1, double f1, bool two)
+{
+    typedef double pair_t __attribute__((ext_vector_type(2), aligned(8)));
+    if (two) {
+        if constexpr ((MODE & kMass) != 0) *reinterpret_cast<pair_t*>(g.omass + idx) = pair_t{m0, m1};
+        if constexpr ((MODE & kOut) != 0) {
+            double a0 = 0.0, a1 = 0.0;
+            if constexpr ((MODE & kFarr) != 0) {
+                const pair_t fa = *reinterpret_cast<const pair_t*>(g.farr + idx);
+                a0 = fa.x;
+                a1 = fa.y;
+            }
+            *reinterpret_cast<pair_t*>(g.out + idx) =
+                pair_t{row_value<MODE>(g, m0, l0, s0, f0, a0), row_value<MODE>(g, m1, l1, s1, f1, a1)};
+        }
+    } else {
+        finish_row<MODE>(g, idx, m0, l0, s0, f0);
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // 1D: one thread per row, coefficients through the L1/L2 caches.
 // ---------------------------------------------------------------------------------

@@ -32,14 +32,57 @@ struct Plan3D {
     int LW;                 // LDS row length: TX + 2p (even)
 };
 
-constexpr int kNPZ = 3;        // footprint points per thread (z pass)
+// footprint points per thread (z pass): the register ring holds (2p+1) x npz values
+__host__ __device__ constexpr int npz(int P)
+{
+    return P == 3 ? 2 : 3;
+}
 constexpr int kMaxNT3 = 512;   // threads per workgroup, at most
 
-// LDS doubles of a plan: Z1, Z2 of TY + 2p rows and Y1, Y2 of TY rows, LW each
-__host__ __device__ inline size_t lds3d_doubles(int TY, int LW, int P)
+// LDS of a plan.  Z1, Z2 are stored by column (LW columns of zcol(TY, P) doubles: the
+// footprint's TY + 2p rows, padded to an odd count so that lanes reading neighbouring
+// columns hit different banks) -- the y pass then reads consecutive addresses; Y1, Y2
+// are stored by row (TY rows of LW doubles) for the x pass.
+__host__ __device__ inline int zcol(int TY, int P)
 {
-    return (size_t)(4 * TY + 4 * P) * (size_t)LW;
+    return (TY + 2 * P) | 1;
 }
+
+// After them, staged once per workgroup: the band rows of the tile's x columns and y
+// rows ([M (2p+1) | D (2p+1)] each; read only by tasks on the first or last 2p rows of
+// an axis) and their S and F factors.  The plane loop then issues no global loads besides
+// the coefficient prefetch, so no memory wait in it drains that prefetch.
+__host__ __device__ inline size_t lds3d_doubles(int TX, int TY, int LW, int P)
+{
+    return (size_t)(2 * zcol(TY, P) + 2 * TY) * (size_t)LW + (size_t)(TX + TY) * (4 * P + 2) +
+           2 * (size_t)(TX + TY);
+}
+
+// Band rows r0 .. r0+n-1 of an axis into LDS rows of 2W doubles (rows past the axis: 0).
+template <int W>
+__device__ __forceinline__ void stage_taps(double* dst, const AxisOp& A, int r0, int n, int tid, int NT)
+{
+    for (int i = tid; i < n * 2 * W; i += NT) {
+        const int j = i / (2 * W), k = i - j * (2 * W);
+        const int r = r0 + j;
+        double v = 0.0;
+        if (r < A.R) v = k < W ? A.M[(size_t)r * W + k] : A.D[(size_t)r * W + k - W];
+        dst[i] = v;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void lds_taps(double (&m)[W], double (&d)[W], const double* row)
+{
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        m[k] = row[k];
+        d[k] = row[W + k];
+    }
+}
+
+// Unaligned (8-byte) pair of doubles: one 16-byte store where the hardware allows it.
+typedef double dv2u __attribute__((ext_vector_type(2), aligned(8)));
 
 // Loads through the constant address space: with a uniform address the compiler issues
 // scalar loads, and the taps then occupy scalar registers instead of vector ones.
@@ -55,17 +98,6 @@ __device__ __forceinline__ void uniform_row(double (&m)[W], double (&d)[W], cons
     for (int k = 0; k < W; ++k) {
         m[k] = pm[k];
         d[k] = pd[k];
-    }
-}
-
-template <int W>
-__device__ __forceinline__ void lane_row(double (&m)[W], double (&d)[W], const AxisOp& A, int row)
-{
-    const int r = row < A.R ? row : A.R - 1;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        m[k] = A.M[(size_t)r * W + k];
-        d[k] = A.D[(size_t)r * W + k];
     }
 }
 
@@ -117,6 +149,7 @@ template <int P, int MODE>
 __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D pl)
 {
     constexpr int W = 2 * P + 1;
+    constexpr int kNPZ = npz(P);
     extern __shared__ __attribute__((aligned(16))) double lds3[];
     const AxisOp &X = g.ax[0], &Y = g.ax[1], &Z = g.ax[2];
     const int NT = (int)blockDim.x, tid = (int)threadIdx.x;
@@ -125,15 +158,35 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
     const int x0 = bx * pl.TX, y0 = by * pl.TY, z0 = bz * pl.TZ;
     const int x1 = min(x0 + pl.TX, X.R), y1 = min(y0 + pl.TY, Y.R), z1 = min(z0 + pl.TZ, Z.R);
     if (x0 >= x1 || y0 >= y1 || z0 >= z1) return;   // the whole workgroup
-    const int LW = pl.LW, LH = pl.TY + 2 * P;
-    double* sZ1 = lds3;
+    const int LW = pl.LW, LH = zcol(pl.TY, P);
+    double* sZ1 = lds3;                 // [LW][LH]: column-major
     double* sZ2 = sZ1 + LH * LW;
-    double* sY1 = sZ2 + LH * LW;
+    double* sY1 = sZ2 + LH * LW;        // [TY][LW]: row-major
     double* sY2 = sY1 + pl.TY * LW;
 
+    // band rows of the tile's columns and rows, then their S and F: [x S | x F | y S | y F]
+    double* tx_ = sY2 + pl.TY * LW;
+    double* ty_ = tx_ + pl.TX * 2 * W;
+    double* sfx = ty_ + pl.TY * 2 * W;
+    double* sfy = sfx + 2 * pl.TX;
+    stage_taps<W>(tx_, X, x0, pl.TX, tid, NT);
+    stage_taps<W>(ty_, Y, y0, pl.TY, tid, NT);
+
     // LDS slots outside the array stay zero for the whole chunk
-    const int nl = (int)lds3d_doubles(pl.TY, LW, P);
+    const int nl = (2 * LH + 2 * pl.TY) * LW;
     for (int i = tid; i < nl; i += NT) lds3[i] = 0.0;
+    if constexpr ((MODE & kScaleSrc) != 0) {
+        for (int i = tid; i < pl.TX; i += NT) {
+            const int x = min(x0 + i, X.R - 1);
+            sfx[i] = X.S[x];
+            sfx[pl.TX + i] = X.F[x];
+        }
+        for (int i = tid; i < pl.TY; i += NT) {
+            const int y = min(y0 + i, Y.R - 1);
+            sfy[i] = Y.S[y];
+            sfy[pl.TY + i] = Y.F[y];
+        }
+    }
 
     // footprint of the tile: input columns xa..xb-1 and rows ya..yb-1
     const int NX = X.N, NY = Y.N, NZ = Z.N;
@@ -148,7 +201,7 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
         const int r = j / RW, cc = j - r * RW;
         const bool ok = j < npt;
         goff[i] = ok ? (unsigned)((ya + r) * NX + xa + cc) * 8u : kOOB;
-        loff[i] = ok ? (ya + r - (y0 - P)) * LW + (xa + cc - (x0 - P)) : -1;
+        loff[i] = ok ? (xa + cc - (x0 - P)) * LH + (ya + r - (y0 - P)) : -1;
     }
     const size_t plane = (size_t)NX * NY;
     auto plane_buf = [&](int zi) {
@@ -180,6 +233,9 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
     const int nI = ib - ia, nB = npx - nI;
     const int ntxI = TYv * nI, ntx = TYv * npx;
     const int lc0 = xa - (x0 - P);   // LDS column of input column xa
+    // strides of the division-free task walks (NT tasks per step)
+    const int ydq = NT / RW, ydc = NT - (NT / RW) * RW;
+    const int xdr = nI > 0 ? NT / nI : 0, xdi = nI > 0 ? NT - (NT / nI) * nI : 0;
 
     int cur = 0;   // slot of plane zo - P
     for (int zo = z0; zo < z1; ++zo) {
@@ -215,26 +271,27 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
         // ---- y pass: rows y0 + 2q, y0 + 2q + 1 of footprint column xa + c ----
         double yim[W], yid[W];
         uniform_row<W>(yim, yid, Y.M, Y.D, opaque(Y.ilo <= Y.ihi ? Y.ilo : 0));
-        for (int t = tid; t < nty; t += NT) {
-            const int q = t / RW, c = t - q * RW;
+        // task t = q * RW + c, walked without divisions
+        int q = tid / RW, c = tid - (tid / RW) * RW;
+        for (; q < npy;) {
             const int r0 = y0 + 2 * q;
             const int lc = lc0 + c;
-            const double* z1p = sZ1 + (2 * q) * LW + lc;   // LDS row of input row r0 - P
-            const double* z2p = sZ2 + (2 * q) * LW + lc;
+            const double* z1p = sZ1 + lc * LH + 2 * q;   // input rows r0 - P .. r0 + P + 1
+            const double* z2p = sZ2 + lc * LH + 2 * q;
             double a[2 * P + 2], b[2 * P + 2];
 #pragma unroll
             for (int k = 0; k < 2 * P + 2; ++k) {
-                a[k] = z1p[k * LW];
-                b[k] = z2p[k * LW];
+                a[k] = z1p[k];
+                b[k] = z2p[k];
             }
             double y10, y20, y11, y21;
             if (r0 >= Y.ilo && r0 + 1 <= Y.ihi) {
                 ypair<P>(a, b, yim, yid, yim, yid, y10, y20, y11, y21);
             } else {
                 double m[W], d[W];
-                lane_row<W>(m, d, Y, r0);
+                lds_taps<W>(m, d, ty_ + (2 * q) * 2 * W);
                 pstep<P>(a, b, 0, m, d, y10, y20);
-                lane_row<W>(m, d, Y, r0 + 1);
+                lds_taps<W>(m, d, ty_ + (2 * q + 1) * 2 * W);
                 pstep<P>(a, b, 1, m, d, y11, y21);
             }
             sY1[(2 * q) * LW + lc] = y10;
@@ -242,6 +299,12 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
             if (r0 + 1 < y1) {
                 sY1[(2 * q + 1) * LW + lc] = y11;
                 sY2[(2 * q + 1) * LW + lc] = y21;
+            }
+            c += ydc;
+            q += ydq;
+            if (c >= RW) {
+                c -= RW;
+                ++q;
             }
         }
         __syncthreads();
@@ -251,12 +314,18 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
         const double sz = Z.S[oz], fz = Z.F[oz];
         double xim[W], xid[W];
         uniform_row<W>(xim, xid, X.M, X.D, opaque(X.ilo <= X.ihi ? X.ilo : 0));
+        // interior tasks t = row * nI + ii, walked without divisions
+        int irow = 0, ii = 0;
+        if (nI > 0) {
+            irow = tid / nI;
+            ii = tid - irow * nI;
+        }
         for (int t = tid; t < ntx; t += NT) {
             int row, i;
             bool inner;
             if (t < ntxI) {
-                row = t / nI;
-                i = ia + (t - row * nI);
+                row = irow;
+                i = ia + ii;
                 inner = true;
             } else {
                 const int b = t - ntxI;
@@ -283,24 +352,27 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
                 ypair<P>(a, b, xim, xid, xim, xid, ms0, lp0, ms1, lp1);
             } else {
                 double m[W], d[W];
-                lane_row<W>(m, d, X, gx);
+                lds_taps<W>(m, d, tx_ + (2 * i) * 2 * W);
                 pstep<P>(a, b, 0, m, d, ms0, lp0);
-                lane_row<W>(m, d, X, gx + 1);
+                lds_taps<W>(m, d, tx_ + (2 * i + 1) * 2 * W);
                 pstep<P>(a, b, 1, m, d, ms1, lp1);
             }
             const size_t idx = ((size_t)oz * Y.R + gy) * X.R + gx;
             double s0 = 1.0, s1 = 1.0, f0 = 1.0, f1 = 1.0;
             if constexpr ((MODE & kScaleSrc) != 0) {
-                const double syz = Y.S[gy] * sz, fyz = Y.F[gy] * fz;
-                s0 = X.S[gx] * syz;
-                f0 = X.F[gx] * fyz;
-                if (gx + 1 < x1) {
-                    s1 = X.S[gx + 1] * syz;
-                    f1 = X.F[gx + 1] * fyz;
-                }
+                const double syz = sfy[row] * sz, fyz = sfy[pl.TY + row] * fz;
+                s0 = sfx[2 * i] * syz;
+                f0 = sfx[pl.TX + 2 * i] * fyz;
+                s1 = sfx[2 * i + 1] * syz;
+                f1 = sfx[pl.TX + 2 * i + 1] * fyz;
             }
-            finish_row<MODE>(g, idx, ms0, lp0, s0, f0);
-            if (gx + 1 < x1) finish_row<MODE>(g, idx + 1, ms1, lp1, s1, f1);
+            finish_pair<MODE>(g, idx, ms0, lp0, s0, f0, ms1, lp1, s1, f1, gx + 1 < x1);
+            ii += xdi;
+            irow += xdr;
+            if (ii >= nI) {
+                ii -= nI;
+                ++irow;
+            }
         }
     }
 }

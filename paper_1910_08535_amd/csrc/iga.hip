@@ -201,17 +201,18 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     pl.tx = (Rx + pl.TX - 1) / pl.TX;
     pl.LW = pl.TX + 2 * P;
     const int NT = kMaxNT3;
+    const int kNPZ = npz(P);
     int TY = 2;
     for (int cand = 2; cand <= 32; cand += 2) {
         if ((cand + 2 * P) * pl.LW > kNPZ * NT) break;
         if ((cand / 2) * pl.LW > NT || cand * (pl.TX / 2) > NT) break;
-        if (lds3d_doubles(cand, pl.LW, P) * sizeof(double) > 64 * 1024) break;
+        if (lds3d_doubles(pl.TX, cand, pl.LW, P) * sizeof(double) > 64 * 1024) break;
         TY = cand;
     }
     if (c->ty3d > 0) TY = c->ty3d;
     // every footprint point needs a ring slot of some thread; LDS stays within 64 KB
     while (TY > 2 && ((TY + 2 * P) * pl.LW > kNPZ * NT ||
-                      lds3d_doubles(TY, pl.LW, P) * sizeof(double) > 64 * 1024))
+                      lds3d_doubles(pl.TX, TY, pl.LW, P) * sizeof(double) > 64 * 1024))
         TY -= 2;
     TY = std::min(TY, Ry + (Ry & 1));
     pl.ty = (Ry + TY - 1) / TY;
@@ -243,7 +244,7 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     *nthreads = std::min(NT, std::max(64, (need + 63) / 64 * 64));
     // every footprint point needs a ring slot
     while ((size_t)*nthreads * kNPZ < (size_t)(pl.TY + 2 * P) * pl.LW && *nthreads < NT) *nthreads += 64;
-    *lds_bytes = lds3d_doubles(pl.TY, pl.LW, P) * sizeof(double);
+    *lds_bytes = lds3d_doubles(pl.TX, pl.TY, pl.LW, P) * sizeof(double);
     return pl;
 }
 
