@@ -28,13 +28,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector, vendor figure
 GP_C2 = 1024 * 1024 * 9
 BYTES_C2 = 1026 * 1026 * 24
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str = "apply2d") -> str:
     from paper_1910_08535_amd.profiling import kernel_source_hash as h
-    return h()
+    return h(kernel)
 
 
 def copy_probe(mib: int) -> None:
@@ -59,7 +60,7 @@ def measured_traffic(workload: str):
             rec = json.load(fh)
     except OSError:
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(rec.get("family", "apply2d")):
         return None
     return rec.get("bytes_per_launch")
 
@@ -212,11 +213,16 @@ def run_c3(args) -> dict:
     for m in meshes:
         m.close()
     mesh.close()
+    # sum-factorized work per output row: z pass 2 x (2p+1) FMA, y and x passes 3 x (2p+1)
+    flops_step = 2 * 8 * (2 * c.p + 1) * ncoef
     return {"workload": "3D heat, cubic C2 B-splines, 128^3 elements, 4^3 Gauss, FP64, dt = 1e-6, "
                         "100 explicit PG steps (lumped), f = sin(pi x) sin(pi y) sin(pi z)",
             "gauss_points_per_step": gp_step, "algorithmic_bytes_per_step": bytes_step,
             "us_per_step": step_s * 1e6, "GPs": gp_step / step_s,
             "hbm_frac_if_from_hbm": bytes_step / step_s / (HBM_PEAK_GBS * 1e9),
+            "algorithmic_flop_per_step": flops_step,
+            "fp64_frac": flops_step / step_s / (FP64_PEAK_TFLOPS * 1e12),
+            "traffic_bytes_per_step": measured_traffic("heat3d_p3_128"),
             "note": "working set in the Infinity Cache across steps",
             "rotated_16_problems": {"us_per_step": rot_s * 1e6, "GPs": gp_step / rot_s,
                                     "hbm_frac": bytes_step / rot_s / (HBM_PEAK_GBS * 1e9)},

@@ -9,7 +9,7 @@ Used by hand after a profiling run:
 `traffic` scales each counter by what it reads for a plain copy of known size (the
 torch copy kernel the benchmark runs with --copy-probe-mb), giving HBM bytes per launch
 of the kernel, and writes profiles/traffic_<workload>.json stamped with the hash of the
-kernel sources (bench.py reports the figure only while the sources are unchanged).
+sources of that kernel (bench.py reports the figure only while they are unchanged).
 """
 from __future__ import annotations
 
@@ -23,10 +23,18 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def kernel_source_hash() -> str:
+# sources each profiled kernel is compiled from (its code and the types it uses)
+KERNEL_SOURCES = {
+    "apply2d": ("apply.hpp", "common.hpp"),
+    "apply3d": ("apply3d.hpp", "apply.hpp", "common.hpp"),
+    "batch2d": ("batch.hpp", "apply.hpp", "common.hpp"),
+}
+
+
+def kernel_source_hash(kernel: str = "apply2d") -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1910_08535_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
@@ -44,7 +52,8 @@ def stats_markdown(stats_csv: str, out_md: str, command: str) -> None:
                      f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
                      f"{float(r['Percentage']):.1f}% |")
     lines.append("")
-    lines.append(f"Kernel sources hash: `{kernel_source_hash()}`")
+    for k in KERNEL_SOURCES:
+        lines.append(f"Sources hash of {k} ({', '.join(KERNEL_SOURCES[k])}): `{kernel_source_hash(k)}`")
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
@@ -56,6 +65,13 @@ def _per_dispatch(csv_path: str, counter: str):
             continue
         vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return vals
+
+
+def _family(kernel: str) -> str:
+    for k in KERNEL_SOURCES:
+        if k in kernel:
+            return k
+    raise SystemExit(f"no source list for kernel {kernel!r}")
 
 
 def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, workload: str,
@@ -85,7 +101,8 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, worklo
            "copy_probe_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": f_scale, "write_scale": w_scale,
            "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-           "kernel_source_hash": kernel_source_hash(), "commands": commands}
+           "family": _family(kernel), "kernel_source_hash": kernel_source_hash(_family(kernel)),
+           "commands": commands}
     out = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
