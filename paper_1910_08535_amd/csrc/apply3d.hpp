@@ -222,7 +222,6 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
     // task counts of the y and x passes
     const int TYv = y1 - y0, TXv = x1 - x0;
     const int npy = (TYv + 1) >> 1;
-    const int nty = npy * RW;
     const int npx = (TXv + 1) >> 1;
     int ia = X.ilo - x0;
     ia = ia <= 0 ? 0 : (ia + 1) >> 1;                  // first pair with x0 + 2i >= ilo

@@ -421,20 +421,6 @@ int validate_desc(const iga_mesh_desc* d)
     return IGA_OK;
 }
 
-// Spans of the built-in kinds, generated on the device (kind 0 support, 1 element).
-__global__ void spans_kernel(int* first, int* last, int R, int p, int ne, int kind)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    if (kind == IGA_SPANS_SUPPORT) {
-        first[r] = r - p > 0 ? r - p : 0;
-        last[r] = r < ne - 1 ? r : ne - 1;
-    } else {
-        first[r] = r;
-        last[r] = r;
-    }
-}
-
 // Tables of one axis, carved out of one device allocation and filled by kernels on the
 // context's stream (no host synchronisation except for caller span tables).
 int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
@@ -449,19 +435,22 @@ int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
     t.hi = d->hi[a];
     t.R = d->spans == IGA_SPANS_SUPPORT ? t.N : (d->spans == IGA_SPANS_ELEMENT ? t.ne : (int)d->nspan[a]);
     const size_t ng = (size_t)t.ne * t.nq;
-    const size_t nd[11] = {ng, ng, ng * 3 * (t.p + 1), (size_t)t.R * t.W, (size_t)t.R * t.W,
-                           (size_t)t.R, (size_t)t.R, (size_t)t.N * t.W, (size_t)t.N * t.W,
-                           (size_t)t.N * t.W, (size_t)t.N};
-    double** dst[11] = {&t.xg, &t.wg, &t.bq, &t.pm, &t.pd, &t.inv_len, &t.fs_pg,
-                        &t.gm, &t.gl, &t.gb, &t.fs_g};
+    constexpr int NA = 17;
+    const size_t ncl = (size_t)iga::n_classes(t.p, t.ne) * t.nq * 3 * (t.p + 1);
+    const size_t nd[NA] = {ncl, (size_t)t.nq, (size_t)t.nq, ng, ng, ng * 3 * (t.p + 1), ng,
+                           (size_t)t.ne, (size_t)t.ne * (t.p + 1), (size_t)t.R * t.W,
+                           (size_t)t.R * t.W, (size_t)t.R, (size_t)t.R, (size_t)t.N * t.W,
+                           (size_t)t.N * t.W, (size_t)t.N * t.W, (size_t)t.N};
+    double** dst[NA] = {&t.cls, &t.gw, &t.gs, &t.xg, &t.wg, &t.bq, &t.sx, &t.es, &t.eg,
+                        &t.pm, &t.pd, &t.inv_len, &t.fs_pg, &t.gm, &t.gl, &t.gb, &t.fs_g};
     auto up = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
     size_t total = 0;
-    for (int i = 0; i < 11; ++i) total += up(nd[i] * sizeof(double));
+    for (int i = 0; i < NA; ++i) total += up(nd[i] * sizeof(double));
     total += 2 * up((size_t)t.R * sizeof(int));
     void* base = nullptr;
     IGA_TRY(dalloc(c, &base, total));
     char* cur = (char*)base;
-    for (int i = 0; i < 11; ++i) {
+    for (int i = 0; i < NA; ++i) {
         *dst[i] = (double*)cur;
         cur += up(nd[i] * sizeof(double));
     }
@@ -474,17 +463,21 @@ int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
             first[r] = (int)d->span_first[a][r];
             last[r] = (int)d->span_last[a][r];
         }
-        IGA_HIP(hipMemcpy(t.first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice));
-        IGA_HIP(hipMemcpy(t.last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice));
-    } else {
-        hipLaunchKernelGGL(spans_kernel, dim3((t.R + kBlock - 1) / kBlock), dim3(kBlock), 0, c->stream,
-                           t.first, t.last, t.R, t.p, t.ne, d->spans);
+        // stream-ordered like the allocation; waited for, since the host vectors end here
+        IGA_HIP(hipMemcpyAsync(t.first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice,
+                               c->stream));
+        IGA_HIP(hipMemcpyAsync(t.last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice,
+                               c->stream));
+        IGA_HIP(hipStreamSynchronize(c->stream));
     }
-    const unsigned g1 = (unsigned)((ng + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(iga::gauss_tables_kernel, dim3(g1), dim3(kBlock), 0, c->stream, t);
-    const int nr = std::max(t.R, t.N);
-    hipLaunchKernelGGL(iga::band_tables_kernel, dim3((nr + kBlock - 1) / kBlock), dim3(kBlock), 0,
+    const int nc = iga::n_classes(t.p, t.ne);
+    hipLaunchKernelGGL(iga::class_tables_kernel, dim3(1), dim3((nc * t.nq + 63) / 64 * 64), 0, c->stream, t);
+    hipLaunchKernelGGL(iga::element_tables_kernel, dim3((t.ne + kBlock - 1) / kBlock), dim3(kBlock), 0,
                        c->stream, t);
+    const int nr = std::max(t.R, t.N);
+    const size_t lds = (ncl + (size_t)t.nq) * sizeof(double);
+    hipLaunchKernelGGL(iga::band_tables_kernel, dim3((nr + kBlock - 1) / kBlock), dim3(kBlock), lds,
+                       c->stream, t, (int)d->spans);
     IGA_HIP(hipGetLastError());
     return IGA_OK;
 }

@@ -31,12 +31,13 @@ __device__ void gauss_node(int n, int i, double* x, double* w)
     const double nn = (double)n;
     double z = (1.0 - 1.0 / (8.0 * nn * nn) + 1.0 / (8.0 * nn * nn * nn)) *
                cos(M_PI * (4.0 * k - 1.0) / (4.0 * nn + 2.0));
+    // quadratic convergence: once a step is below 1e-15 the iterate is exact to rounding
     double pn, dp;
-    for (int it = 0; it < 60; ++it) {
+    for (int it = 0; it < 30; ++it) {
         legendre(n, z, &pn, &dp);
         const double dz = pn / dp;
         z -= dz;
-        if (fabs(dz) <= 1e-17) break;
+        if (fabs(dz) <= 1e-15) break;
     }
     legendre(n, z, &pn, &dp);
     *x = z;
@@ -116,9 +117,34 @@ __device__ void basis_ders(int p, int ne, int e, double s, double inv_h,
     }
 }
 
+// Elements of an axis fall into at most 2p+1 classes by their local knot pattern: the
+// first p elements, the interior (all alike), the last p.  Basis values at the Gauss
+// points depend only on the class, so they are evaluated once per class.
+__host__ __device__ inline int n_classes(int p, int ne)
+{
+    return ne <= 2 * p + 1 ? ne : 2 * p + 1;
+}
+
+__host__ __device__ inline int class_of(int e, int p, int ne)
+{
+    if (ne <= 2 * p + 1) return e;
+    return e < p ? e : (e > ne - 1 - p ? e - (ne - (2 * p + 1)) : p);
+}
+
+__host__ __device__ inline int class_element(int c, int p, int ne)
+{
+    if (ne <= 2 * p + 1) return c;
+    return c <= p ? c : ne - (2 * p + 1) + c;
+}
+
 // Per-axis device tables.  Layout of one axis (all doubles unless noted):
+//   cls[ncls*nq*3*(p+1)]      cls[((c*nq+q)*3 + m)*(p+1) + a] = B^{(m)}_{e+a} at point q of
+//                             an element e of class c
+//   gw[nq], gs[nq]            weight*Jacobian and local coordinate in [0, 1] of point q
 //   xg[ne*nq], wg[ne*nq]      Gauss points and weight*Jacobian, point q of element e at e*nq+q
+//   sx[ne*nq]                 sin(pi x) at the Gauss points
 //   bq[ne*nq*3*(p+1)]         bq[((e*nq+q)*3 + m)*(p+1) + a] = B^{(m)}_{e+a}(x_{e,q})
+//   es[ne], eg[ne*(p+1)]      element sums of W sin(pi x) and of W B_{e+a} sin(pi x)
 //   pm[R*W], pd[R*W]          PG factors  int_{S_r} B_j,  int_{S_r} B_j''   (column r+k-p)
 //   inv_len[R], fs_pg[R]      1/|S_r|,  int_{S_r} sin(pi x)  (Gauss rule)
 //   gm[N*W], gl[N*W], gb[N*W] Galerkin int B_i B_j, int B_i B_j'', -int B_i' B_j'
@@ -127,89 +153,133 @@ __device__ void basis_ders(int p, int ne, int e, double s, double inv_h,
 struct AxisTables {
     int p, ne, nq, N, R, W;
     double lo, hi;
-    double *xg, *wg, *bq;
+    double *cls, *gw, *gs;
+    double *xg, *wg, *bq, *sx, *es, *eg;
     double *pm, *pd, *inv_len, *fs_pg;
     double *gm, *gl, *gb, *fs_g;
     int *first, *last;
 };
 
-__global__ void gauss_tables_kernel(AxisTables t)
+// One thread per (class, Gauss point): the Gauss rule and the basis values of the class.
+__global__ void class_tables_kernel(AxisTables t)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= t.ne * t.nq) return;
-    const int e = idx / t.nq, q = idx % t.nq;
+    const int idx = threadIdx.x;
+    const int nc = n_classes(t.p, t.ne);
+    if (idx >= nc * t.nq) return;
+    const int c = idx / t.nq, q = idx - c * t.nq;
     double xi, w;
     gauss_node(t.nq, q, &xi, &w);
     // uniform elements: h itself, not a difference of two rounded knots
     const double h = (t.hi - t.lo) / (double)t.ne;
     const double sl = 0.5 * (xi + 1.0);   // local coordinate in [0, 1]
-    t.xg[idx] = t.lo + (t.hi - t.lo) * (((double)e + sl) / (double)t.ne);
-    t.wg[idx] = 0.5 * w * h;
+    if (c == 0) {
+        t.gw[q] = 0.5 * w * h;
+        t.gs[q] = sl;
+    }
     double B[3][kMaxP + 1];
-    basis_ders(t.p, t.ne, e, sl, (double)t.ne / (t.hi - t.lo), B);
+    basis_ders(t.p, t.ne, class_element(c, t.p, t.ne), sl, (double)t.ne / (t.hi - t.lo), B);
     for (int m = 0; m < 3; ++m)
-        for (int a = 0; a <= t.p; ++a) t.bq[((size_t)idx * 3 + m) * (t.p + 1) + a] = B[m][a];
+        for (int a = 0; a <= t.p; ++a) t.cls[((size_t)idx * 3 + m) * (t.p + 1) + a] = B[m][a];
 }
 
-// One thread per row: the Gauss sums of the banded factors.  PG rows never multiply by
-// a test function -- the integrand is summed with weight 1 over the span's elements.
-__global__ void band_tables_kernel(AxisTables t)
+// One thread per element: its Gauss points, weights, basis values (copied from the class
+// tables), sin(pi x), and the element sums of the sine source.
+__global__ void element_tables_kernel(AxisTables t)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= t.ne) return;
+    const int np1 = t.p + 1, nb = 3 * np1;
+    const int c = class_of(e, t.p, t.ne);
+    double es = 0.0, eg[kMaxP + 1] = {};
+    for (int q = 0; q < t.nq; ++q) {
+        const size_t idx = (size_t)e * t.nq + q;
+        const double x = t.lo + (t.hi - t.lo) * (((double)e + t.gs[q]) / (double)t.ne);
+        const double sx = sin(M_PI * x), w = t.gw[q];
+        t.xg[idx] = x;
+        t.sx[idx] = sx;
+        t.wg[idx] = w;
+        const double* B = t.cls + ((size_t)c * t.nq + q) * nb;
+        for (int i = 0; i < nb; ++i) t.bq[idx * nb + i] = B[i];
+        es += w * sx;
+        for (int a = 0; a <= t.p; ++a) eg[a] += w * B[a] * sx;
+    }
+    t.es[e] = es;
+    for (int a = 0; a <= t.p; ++a) t.eg[(size_t)e * np1 + a] = eg[a];
+}
+
+// One thread per row: the Gauss sums of the banded factors, from the class tables staged
+// in LDS.  PG rows never multiply by a test function -- the integrand is summed with
+// weight 1 over the span's elements.  Spans of the built-in kinds (kind 0 support, 1
+// element) are generated here; caller spans (kind 2) are already in first/last.
+__global__ void band_tables_kernel(AxisTables t, int kind)
+{
+    extern __shared__ double sb[];
     const int p = t.p, np1 = t.p + 1, nq = t.nq, W = t.W;
+    const int nb = 3 * np1, nc = n_classes(p, t.ne);
+    double* scls = sb;                       // [nc*nq*3*np1]
+    double* sgw = sb + (size_t)nc * nq * nb; // [nq]
+    for (int i = threadIdx.x; i < nc * nq * nb; i += blockDim.x) scls[i] = t.cls[i];
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) sgw[i] = t.gw[i];
+    __syncthreads();
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < t.R) {
-        const int s = t.first[r], l = t.last[r];
-        double fs = 0.0;
+        int s, l;
+        if (kind == 0) {
+            s = r - p > 0 ? r - p : 0;
+            l = r < t.ne - 1 ? r : t.ne - 1;
+            t.first[r] = s;
+            t.last[r] = l;
+        } else if (kind == 1) {
+            s = l = r;
+            t.first[r] = s;
+            t.last[r] = l;
+        } else {
+            s = t.first[r];
+            l = t.last[r];
+        }
         for (int k = 0; k < W; ++k) {
             const int j = r + k - p;
             double m0 = 0.0, d0 = 0.0;
             for (int e = s; e <= l; ++e) {
                 const int a = j - e;
                 if (a < 0 || a > p) continue;
+                const double* B = scls + (size_t)class_of(e, p, t.ne) * nq * nb;
                 for (int q = 0; q < nq; ++q) {
-                    const size_t eq = (size_t)e * nq + q;
-                    m0 += t.wg[eq] * t.bq[(eq * 3 + 0) * np1 + a];
-                    d0 += t.wg[eq] * t.bq[(eq * 3 + 2) * np1 + a];
+                    m0 += sgw[q] * B[q * nb + a];
+                    d0 += sgw[q] * B[q * nb + 2 * np1 + a];
                 }
             }
             t.pm[(size_t)r * W + k] = m0;
             t.pd[(size_t)r * W + k] = d0;
         }
-        for (int e = s; e <= l; ++e)
-            for (int q = 0; q < nq; ++q) {
-                const size_t eq = (size_t)e * nq + q;
-                fs += t.wg[eq] * sin(M_PI * t.xg[eq]);
-            }
+        double fs = 0.0;
+        for (int e = s; e <= l; ++e) fs += t.es[e];
         t.fs_pg[r] = fs;
         t.inv_len[r] = (double)t.ne / ((double)(l - s + 1) * (t.hi - t.lo));
     }
     if (r < t.N) {
         const int e0 = r - p < 0 ? 0 : r - p;
         const int e1 = r < t.ne - 1 ? r : t.ne - 1;
-        double fs = 0.0;
         for (int k = 0; k < W; ++k) {
             const int j = r + k - p;
             double gm = 0.0, gl = 0.0, gb = 0.0;
             for (int e = e0; e <= e1; ++e) {
                 const int c = r - e, a = j - e;
                 if (a < 0 || a > p) continue;
+                const double* Bc = scls + (size_t)class_of(e, p, t.ne) * nq * nb;
                 for (int q = 0; q < nq; ++q) {
-                    const size_t eq = (size_t)e * nq + q;
-                    const double* B = &t.bq[eq * 3 * np1];
-                    gm += t.wg[eq] * B[c] * B[a];
-                    gl += t.wg[eq] * B[c] * B[2 * np1 + a];
-                    gb -= t.wg[eq] * B[np1 + c] * B[np1 + a];
+                    const double* B = Bc + q * nb;
+                    gm += sgw[q] * B[c] * B[a];
+                    gl += sgw[q] * B[c] * B[2 * np1 + a];
+                    gb -= sgw[q] * B[np1 + c] * B[np1 + a];
                 }
             }
             t.gm[(size_t)r * W + k] = gm;
             t.gl[(size_t)r * W + k] = gl;
             t.gb[(size_t)r * W + k] = gb;
         }
-        for (int e = e0; e <= e1; ++e)
-            for (int q = 0; q < nq; ++q) {
-                const size_t eq = (size_t)e * nq + q;
-                fs += t.wg[eq] * t.bq[(eq * 3) * np1 + (r - e)] * sin(M_PI * t.xg[eq]);
-            }
+        double fs = 0.0;
+        for (int e = e0; e <= e1; ++e) fs += t.eg[(size_t)e * np1 + (r - e)];
         t.fs_g[r] = fs;
     }
 }
