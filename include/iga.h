@@ -104,7 +104,14 @@ typedef struct iga_ctx iga_ctx;
    hip_stream: a hipStream_t (NULL = the default stream) on which every call of this
    context is enqueued.  The set-up kernels are enqueued on that stream too (every later
    call of the context is ordered after them); only caller span tables (CUSTOM) are
-   copied synchronously.
+   copied synchronously.  The tables of an axis depend only on (p, ne, nq, lo, hi, span
+   kind): contexts with equal axes share one copy (built once, on the stream of the first
+   context that needs it; later contexts' streams wait for that build), and tables no
+   context uses stay cached up to 4 GiB per device, least recently released first out.
+   Device memory comes from the device's default stream-ordered pool; the first call on
+   a device sets that pool to keep freed memory (no release threshold) so that contexts
+   can be created and destroyed at a high rate.  Contexts must not be created from
+   several host threads at once.
    Errors: IGA_E_INVAL (null out, bad sizes or spans), IGA_E_UNSUPPORTED,
    IGA_E_NOMEM, IGA_E_DEVICE. */
 int iga_create(const iga_mesh_desc *desc, void *hip_stream, iga_ctx **out);
@@ -153,8 +160,9 @@ int iga_apply(iga_ctx *ctx, int32_t form, const double *u, double *mass_out, dou
    sum_j int_{S_r} B_j = |S_r|):
      u_r <- int_{S_r} (u_h + dt Lap u_h + dt f) / |S_r|.
    u: device coefficients, updated in place.  Requires IGA_SPANS_SUPPORT (square
-   system).  For nsteps >= 2 the launches are captured once into a HIP graph that is
-   cached on the context and replayed while (u, dt, f, nsteps) stay the same.
+   system).  For nsteps >= 2, the second consecutive call with the same
+   (u, dt, f, nsteps) captures the launches into a HIP graph that is cached on the
+   context and replayed while they stay the same (a first call launches directly).
    Errors: IGA_E_INVAL (also for other span kinds), IGA_E_NOMEM. */
 int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, int32_t nsteps);
 
@@ -227,6 +235,63 @@ int iga_batch_wait(iga_batch *b);
    time per launch in milliseconds to best_ms (host, both nullable). */
 int iga_batch_autotune(iga_batch *b, int32_t reps, int32_t *best_rows, float *best_ms);
 int iga_batch_destroy(iga_batch *b);
+
+/* ---------------------------------------------------------------------------------
+ * Serving: a request loop inside the library, for a stream of independent requests on
+ * meshes of any size.  A request is either
+ *   IGA_REQ_RHS   the fused Petrov-Galerkin apply of iga_apply (mass and Laplacian rows,
+ *                 support spans), or
+ *   IGA_REQ_STEP  nsteps explicit steps of iga_explicit_step (u updated in place) with a
+ *                 source sin_amp * prod_a sin(pi x_a),
+ * on dim axes of ne[a] elements on [0, 1], degree p, p+1 Gauss points per axis.
+ * Requests are admitted in submission order while the bytes of the requests in flight
+ * (u and both outputs, or u and the step's work buffer) stay within the budget.  An
+ * admitted request runs at once on the stream of its mesh's context: contexts are cached
+ * (least recently used first out beyond cache_bytes of tables) and bound round-robin to
+ * the server's streams.  2D RHS requests instead join the queue of the persistent batch
+ * launch of iga_batch: whenever no launch is running, one launch takes every queued
+ * 2D RHS request (continuous batching).  Completion is observed from HIP events; no call
+ * blocks except iga_server_destroy.  Results equal those of the same request run alone
+ * through iga_apply / iga_explicit_step, bit for bit.  All buffers are caller-owned
+ * device memory and must stay valid until the request is reported done.
+ * ------------------------------------------------------------------------------ */
+#define IGA_REQ_RHS 0
+#define IGA_REQ_STEP 1
+
+typedef struct {
+    int32_t kind;          /* IGA_REQ_RHS or IGA_REQ_STEP                               */
+    int32_t dim, p;        /* 1..3; 2 or 3                                              */
+    int64_t ne[3];         /* elements per axis (x, y, z), >= 1                          */
+    int32_t nsteps;        /* STEP: steps, >= 1                                          */
+    double dt, sin_amp;    /* STEP: time step, source amplitude                          */
+    double *u;             /* device coefficients (N_z, N_y, N_x); STEP: updated         */
+    double *mass_out;      /* RHS: device rows, same shape as u                          */
+    double *lap_out;       /* RHS: device rows, same shape as u                          */
+} iga_request;
+
+typedef struct iga_server iga_server;
+
+/* nstreams (1..64) streams of default priority; mem_budget_bytes > 0; cache_bytes:
+   limit on the cached contexts' table bytes.  Errors: IGA_E_INVAL, IGA_E_NOMEM. */
+int iga_server_create(int32_t nstreams, size_t mem_budget_bytes, size_t cache_bytes,
+                      iga_server **out);
+/* Queues n requests (host array; all or nothing) and admits what fits; tickets (host,
+   [n]) receive their ids.  Errors: IGA_E_INVAL (bad request), IGA_E_UNSUPPORTED (dim or
+   p), IGA_E_NOMEM (a request larger than the whole budget). */
+int iga_server_submit(iga_server *s, const iga_request *reqs, int32_t n, uint64_t *tickets);
+/* Harvests completions, admits queued requests that now fit and starts a batch launch
+   if none runs; then reports up to cap completed requests (host arrays): ticket, time in
+   seconds since the server was created (when the completion was observed), state
+   (IGA_JOB_DONE or IGA_JOB_FAILED) and, if done_launch is not NULL, the index of the
+   batch launch that ran it (-1 for none).  *ndone receives the count.  Never blocks. */
+int iga_server_progress(iga_server *s, uint64_t *done, double *done_time, int32_t *done_state,
+                        int64_t *done_launch, int32_t cap, int32_t *ndone);
+/* Bytes in flight, their peak, batch launches so far, and the server's clock (seconds
+   since creation); every output is nullable. */
+int iga_server_stats(const iga_server *s, size_t *used, size_t *peak, int64_t *batch_launches,
+                     double *now);
+/* Waits for the server's streams, then releases its contexts, streams and events. */
+int iga_server_destroy(iga_server *s);
 
 #ifdef __cplusplus
 }

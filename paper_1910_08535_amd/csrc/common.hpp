@@ -56,4 +56,24 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nblk)
     return x * q + (x < r ? x : r) + k;
 }
 
+// Elements of an axis fall into at most 2p+1 classes by their local knot pattern: the
+// first p elements, the interior (all alike), the last p.  Basis values at the Gauss
+// points depend only on the class, so they are evaluated once per class.
+__host__ __device__ inline int n_classes(int p, int ne)
+{
+    return ne <= 2 * p + 1 ? ne : 2 * p + 1;
+}
+
+__host__ __device__ inline int class_of(int e, int p, int ne)
+{
+    if (ne <= 2 * p + 1) return e;
+    return e < p ? e : (e > ne - 1 - p ? e - (ne - (2 * p + 1)) : p);
+}
+
+__host__ __device__ inline int class_element(int c, int p, int ne)
+{
+    if (ne <= 2 * p + 1) return c;
+    return c <= p ? c : ne - (2 * p + 1) + c;
+}
+
 }  // namespace iga

@@ -7,7 +7,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <list>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "iga.h"
@@ -40,8 +43,12 @@ using iga::TileGrid;
         if (rc_ != IGA_OK) return rc_; \
     } while (0)
 
+struct AxisEntry;
+
 struct iga_ctx {
     int dim = 0, p = 0, W = 0, spans = 0;
+    size_t table_bytes = 0;   // device bytes of the context's tables
+    struct AxisEntry* shared[3] = {nullptr, nullptr, nullptr};   // cached axis tables in use
     int ne[3] = {1, 1, 1}, nq[3] = {1, 1, 1}, N[3] = {1, 1, 1}, R[3] = {1, 1, 1};
     double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
     hipStream_t stream = nullptr;
@@ -63,6 +70,11 @@ struct iga_ctx {
     const double* g_tab = nullptr;
     double g_dt = 0, g_amp = 0;
     int g_n = 0;
+    // the previous multi-step call's arguments: a graph is captured when they repeat
+    const double* l_u = nullptr;
+    const double* l_tab = nullptr;
+    double l_dt = 0, l_amp = 0;
+    int l_n = 0;
     // tile configuration
     int ty2d = 8;
     int order2d = 0;
@@ -73,7 +85,27 @@ struct iga_ctx {
 namespace {
 
 // Device memory of a context comes from the stream-ordered pool of its stream
-// (hipMallocAsync): setting up a context costs no device-wide synchronisation.
+// (hipMallocAsync): setting up a context costs no device-wide synchronisation.  The
+// device's default pool keeps memory freed by destroyed contexts (no release threshold),
+// so contexts created and destroyed at a high rate reuse it instead of mapping new
+// memory after every synchronisation.
+void retain_pool_memory()
+{
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done[dev]) return;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    done[dev] = true;
+}
+
 int dalloc(iga_ctx* c, void** p, size_t bytes)
 {
     if (bytes == 0) bytes = 8;
@@ -333,16 +365,18 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
             x.nq = t.nq;
             x.np1 = t.p + 1;
             x.R = form == IGA_PG ? t.R : t.N;
-            x.wg = t.wg;
-            x.bq = t.bq;
+            x.gw = t.gw;
+            x.cls = t.cls;
+            x.p = t.p;
             x.first = t.first;
             x.last = t.last;
             nel *= (size_t)t.ne;
             np1 *= t.p + 1;
         } else {
             x.ne = x.nq = x.np1 = x.R = 1;
-            x.wg = c->unit;
-            x.bq = c->unit;
+            x.p = 0;
+            x.gw = c->unit;
+            x.cls = c->unit;
             x.first = x.last = c->zero;
         }
     }
@@ -421,12 +455,32 @@ int validate_desc(const iga_mesh_desc* d)
     return IGA_OK;
 }
 
-// Tables of one axis, carved out of one device allocation and filled by kernels on the
-// context's stream (no host synchronisation except for caller span tables).
-int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
+// Byte layout of one axis' tables (offsets from the axis' base, 256-byte aligned).
+size_t axis_layout(AxisTables& t, char* base)
 {
-    AxisTables& t = c->t[a];
-    t.p = c->p;
+    constexpr int NA = 13;
+    const size_t ncl = (size_t)iga::n_classes(t.p, t.ne) * t.nq * 3 * (t.p + 1);
+    const size_t nd[NA] = {ncl, (size_t)t.nq, (size_t)t.nq, (size_t)t.ne, (size_t)t.ne * (t.p + 1),
+                           (size_t)t.R * t.W, (size_t)t.R * t.W, (size_t)t.R, (size_t)t.R,
+                           (size_t)t.N * t.W, (size_t)t.N * t.W, (size_t)t.N * t.W, (size_t)t.N};
+    double** dst[NA] = {&t.cls, &t.gw, &t.gs, &t.es, &t.eg, &t.pm, &t.pd, &t.inv_len, &t.fs_pg,
+                        &t.gm, &t.gl, &t.gb, &t.fs_g};
+    auto up = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+    size_t off = 0;
+    for (int i = 0; i < NA; ++i) {
+        if (base) *dst[i] = (double*)(base + off);
+        off += up(nd[i] * sizeof(double));
+    }
+    if (base) t.first = (int*)(base + off);
+    off += up((size_t)t.R * sizeof(int));
+    if (base) t.last = (int*)(base + off);
+    off += up((size_t)t.R * sizeof(int));
+    return off;
+}
+
+void axis_sizes(AxisTables& t, int p, int a, const iga_mesh_desc* d)
+{
+    t.p = p;
     t.ne = (int)d->ne[a];
     t.nq = d->nq[a];
     t.N = t.ne + t.p;
@@ -434,62 +488,191 @@ int build_axis(iga_ctx* c, int a, const iga_mesh_desc* d)
     t.lo = d->lo[a];
     t.hi = d->hi[a];
     t.R = d->spans == IGA_SPANS_SUPPORT ? t.N : (d->spans == IGA_SPANS_ELEMENT ? t.ne : (int)d->nspan[a]);
-    const size_t ng = (size_t)t.ne * t.nq;
-    constexpr int NA = 17;
-    const size_t ncl = (size_t)iga::n_classes(t.p, t.ne) * t.nq * 3 * (t.p + 1);
-    const size_t nd[NA] = {ncl, (size_t)t.nq, (size_t)t.nq, ng, ng, ng * 3 * (t.p + 1), ng,
-                           (size_t)t.ne, (size_t)t.ne * (t.p + 1), (size_t)t.R * t.W,
-                           (size_t)t.R * t.W, (size_t)t.R, (size_t)t.R, (size_t)t.N * t.W,
-                           (size_t)t.N * t.W, (size_t)t.N * t.W, (size_t)t.N};
-    double** dst[NA] = {&t.cls, &t.gw, &t.gs, &t.xg, &t.wg, &t.bq, &t.sx, &t.es, &t.eg,
-                        &t.pm, &t.pd, &t.inv_len, &t.fs_pg, &t.gm, &t.gl, &t.gb, &t.fs_g};
-    auto up = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
-    size_t total = 0;
-    for (int i = 0; i < NA; ++i) total += up(nd[i] * sizeof(double));
-    total += 2 * up((size_t)t.R * sizeof(int));
-    void* base = nullptr;
-    IGA_TRY(dalloc(c, &base, total));
-    char* cur = (char*)base;
-    for (int i = 0; i < NA; ++i) {
-        *dst[i] = (double*)cur;
-        cur += up(nd[i] * sizeof(double));
+}
+
+}  // namespace
+
+// ---- tables shared between contexts ---------------------------------------------------
+// The tables of an axis depend only on (p, ne, nq, domain, span kind); contexts with the
+// same axis share one copy.  An entry is built once, on the stream of the context that
+// first needs it, and every later user waits for its build event.  Entries nobody uses
+// stay cached (least recently released first out beyond a byte limit); when one is freed,
+// the free is ordered after the last use on every stream that used it.
+struct AxisEntry {
+    AxisTables t;
+    void* mem = nullptr;
+    size_t bytes = 0;
+    int refs = 0;
+    hipEvent_t ready = nullptr;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;   // last release per stream
+    std::tuple<int, int, int, int, double, double> key;
+    std::list<AxisEntry*>::iterator idle_pos;
+    bool idle = false;
+    bool orphan = false;   // build failed: out of the map, freed when its last user goes
+};
+
+namespace {
+
+struct AxisCache {
+    std::mutex mu;
+    std::map<std::tuple<int, int, int, int, double, double>, AxisEntry*> map;
+    std::list<AxisEntry*> idle;   // refs == 0, least recently released first
+    size_t idle_bytes = 0;
+    size_t limit = (size_t)4 << 30;
+    // constants shared by every context of the device: {1, 0 x 7} | two int zeros | ones
+    double* consts = nullptr;
+    size_t nones = 0;
+};
+
+AxisCache g_cache[64];
+
+AxisCache* device_cache()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    return &g_cache[dev];
+}
+
+__global__ void fill_consts_kernel(double* base, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 + n; i += (size_t)gridDim.x * blockDim.x) {
+        if (i < 8)
+            base[i] = i == 0 ? 1.0 : 0.0;
+        else if (i == 8)
+            ((int*)(base + 8))[0] = ((int*)(base + 8))[1] = 0;
+        else
+            base[i] = 1.0;
     }
-    t.first = (int*)cur;
-    cur += up((size_t)t.R * sizeof(int));
-    t.last = (int*)cur;
-    if (d->spans == IGA_SPANS_CUSTOM) {
-        std::vector<int> first(t.R), last(t.R);
-        for (int r = 0; r < t.R; ++r) {
-            first[r] = (int)d->span_first[a][r];
-            last[r] = (int)d->span_last[a][r];
+}
+
+// The device's shared constants with at least n ones.  Growing them replaces the buffer
+// (older ones stay allocated: contexts may still point at them) and waits for the fill.
+int shared_consts(iga_ctx* c, size_t n)
+{
+    AxisCache* g = device_cache();
+    if (!g) return IGA_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (g->nones < n) {
+        const size_t m = std::max(n, 2 * g->nones);
+        void* p = nullptr;
+        if (hipMalloc(&p, (9 + m) * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return IGA_E_NOMEM;
         }
-        // stream-ordered like the allocation; waited for, since the host vectors end here
-        IGA_HIP(hipMemcpyAsync(t.first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice,
-                               c->stream));
-        IGA_HIP(hipMemcpyAsync(t.last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice,
-                               c->stream));
+        hipLaunchKernelGGL(fill_consts_kernel, dim3(256), dim3(kBlock), 0, c->stream, (double*)p, m);
+        IGA_HIP(hipGetLastError());
         IGA_HIP(hipStreamSynchronize(c->stream));
+        g->consts = (double*)p;
+        g->nones = m;
     }
-    const int nc = iga::n_classes(t.p, t.ne);
-    hipLaunchKernelGGL(iga::class_tables_kernel, dim3(1), dim3((nc * t.nq + 63) / 64 * 64), 0, c->stream, t);
-    hipLaunchKernelGGL(iga::element_tables_kernel, dim3((t.ne + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                       c->stream, t);
-    const int nr = std::max(t.R, t.N);
-    const size_t lds = (ncl + (size_t)t.nq) * sizeof(double);
-    hipLaunchKernelGGL(iga::band_tables_kernel, dim3((nr + kBlock - 1) / kBlock), dim3(kBlock), lds,
-                       c->stream, t, (int)d->spans);
-    IGA_HIP(hipGetLastError());
+    c->unit = g->consts;
+    c->zero = (int*)(g->consts + 8);
+    c->ones = g->consts + 9;
     return IGA_OK;
 }
 
-// unit = {1, 0, ..., 0} (8 doubles), zero = two ints 0, ones = n doubles 1
-__global__ void consts_kernel(double* base, size_t n)
+void axis_free(AxisEntry* e, hipStream_t s)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 8) base[i] = i == 0 ? 1.0 : 0.0;
-    else if (i == 8) ((int*)(base + 8))[0] = ((int*)(base + 8))[1] = 0;
-    else if (i < 9 + n) base[i] = 1.0;
+    for (auto& u : e->uses) {
+        if (u.first != s) (void)hipStreamWaitEvent(s, u.second, 0);
+    }
+    (void)hipFreeAsync(e->mem, s);
+    for (auto& u : e->uses) (void)hipEventDestroy(u.second);
+    if (e->ready) (void)hipEventDestroy(e->ready);
+    delete e;
 }
+
+// An entry for axis a of the descriptor, in use by the caller; *built tells whether its
+// tables still have to be built (by the caller, on its stream, then axis_built()).
+int axis_acquire(iga_ctx* c, int a, const iga_mesh_desc* d, AxisEntry** out, bool* built)
+{
+    AxisCache* g = device_cache();
+    if (!g) return IGA_E_DEVICE;
+    const auto key = std::make_tuple(c->p, (int)d->ne[a], d->nq[a], d->spans, d->lo[a], d->hi[a]);
+    std::lock_guard<std::mutex> lock(g->mu);
+    auto it = g->map.find(key);
+    if (it != g->map.end()) {
+        AxisEntry* e = it->second;
+        if (e->idle) {
+            g->idle.erase(e->idle_pos);
+            g->idle_bytes -= e->bytes;
+            e->idle = false;
+        }
+        ++e->refs;
+        // no build event yet: the entry is being built by this very call (two axes alike)
+        if (e->ready) IGA_HIP(hipStreamWaitEvent(c->stream, e->ready, 0));
+        *out = e;
+        *built = false;
+        return IGA_OK;
+    }
+    AxisEntry* e = new (std::nothrow) AxisEntry;
+    if (!e) return IGA_E_NOMEM;
+    e->t = c->t[a];
+    e->bytes = axis_layout(e->t, nullptr);
+    if (hipMallocAsync(&e->mem, e->bytes, c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        delete e;
+        return IGA_E_NOMEM;
+    }
+    axis_layout(e->t, (char*)e->mem);
+    e->key = key;
+    e->refs = 1;
+    g->map[key] = e;
+    *out = e;
+    *built = true;
+    return IGA_OK;
+}
+
+// The build of a fresh entry is enqueued on stream s: later users wait for this event.
+int axis_built(AxisEntry* e, hipStream_t s)
+{
+    IGA_HIP(hipEventCreateWithFlags(&e->ready, hipEventDisableTiming));
+    IGA_HIP(hipEventRecord(e->ready, s));
+    return IGA_OK;
+}
+
+// A fresh entry whose build failed: taken out of the map at once, so that no later
+// context finds it; the failing context's release frees it.
+void axis_discard(AxisEntry* e)
+{
+    AxisCache* g = device_cache();
+    if (!g) return;
+    std::lock_guard<std::mutex> lock(g->mu);
+    auto it = g->map.find(e->key);
+    if (it != g->map.end() && it->second == e) g->map.erase(it);
+    e->orphan = true;
+}
+
+// A context on stream s stops using the entry.
+void axis_release(AxisEntry* e, hipStream_t s)
+{
+    AxisCache* g = device_cache();
+    if (!g) return;
+    std::lock_guard<std::mutex> lock(g->mu);
+    hipEvent_t ev = nullptr;
+    for (auto& u : e->uses)
+        if (u.first == s) ev = u.second;
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) e->uses.push_back({s, ev});
+    if (ev) (void)hipEventRecord(ev, s);
+    if (--e->refs > 0) return;
+    if (e->orphan) {
+        axis_free(e, s);
+        return;
+    }
+    e->idle = true;
+    g->idle.push_back(e);
+    e->idle_pos = std::prev(g->idle.end());
+    g->idle_bytes += e->bytes;
+    while (g->idle_bytes > g->limit && !g->idle.empty()) {
+        AxisEntry* old = g->idle.front();
+        g->idle.pop_front();
+        g->idle_bytes -= old->bytes;
+        g->map.erase(old->key);
+        axis_free(old, s);
+    }
+}
+
+
 
 __global__ void bands_out_kernel(double* dst, const double* f0, const double* f1, int R, int Rmax,
                                  int W, int write1)
@@ -523,6 +706,7 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
     if (!out) return IGA_E_INVAL;
     *out = nullptr;
     IGA_TRY(validate_desc(desc));
+    retain_pool_memory();
     iga_ctx* c = new (std::nothrow) iga_ctx;
     if (!c) return IGA_E_NOMEM;
     c->dim = desc->dim;
@@ -530,30 +714,96 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
     c->W = 2 * desc->p + 1;
     c->spans = desc->spans;
     c->stream = (hipStream_t)hip_stream;
-    int rc = IGA_OK;
-    void* p = nullptr;
-    // unit {1, 0 x 7} | zero (two ints) | ones[nmax]
     int64_t nmax = 1;
-    for (int a = 0; a < c->dim; ++a) nmax = std::max<int64_t>(nmax, desc->ne[a] + desc->p);
-    rc = dalloc(c, &p, (size_t)(8 + 1 + nmax) * sizeof(double));
-    if (rc == IGA_OK) {
-        c->unit = (double*)p;
-        c->zero = (int*)(c->unit + 8);
-        c->ones = c->unit + 9;
-        hipLaunchKernelGGL(consts_kernel, dim3((unsigned)((nmax + 9 + kBlock - 1) / kBlock)), dim3(kBlock),
-                           0, c->stream, c->unit, (size_t)nmax);
-        if (hipGetLastError() != hipSuccess) rc = IGA_E_DEVICE;
-    }
-    for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
+    for (int a = 0; a < c->dim; ++a) {
+        nmax = std::max<int64_t>(nmax, desc->ne[a] + desc->p);
+        axis_sizes(c->t[a], c->p, a, desc);
         c->ne[a] = (int)desc->ne[a];
         c->nq[a] = desc->nq[a];
         c->lo[a] = desc->lo[a];
         c->hi[a] = desc->hi[a];
-        rc = build_axis(c, a, desc);
         c->N[a] = c->t[a].N;
         c->R[a] = c->t[a].R;
     }
+    int rc = shared_consts(c, (size_t)nmax);
+    // tables: shared cached axes for the built-in span kinds, or tables of the context's
+    // own for caller spans; the axes that still need building are built together below
+    iga::AxisSet set;
+    std::memset(&set, 0, sizeof(set));
+    AxisEntry* fresh[3] = {nullptr, nullptr, nullptr};
+    int nbuild = 0;
+    if (rc == IGA_OK && desc->spans != IGA_SPANS_CUSTOM) {
+        for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
+            bool built = false;
+            rc = axis_acquire(c, a, desc, &c->shared[a], &built);
+            if (rc == IGA_OK) {
+                c->t[a] = c->shared[a]->t;
+                c->table_bytes += c->shared[a]->bytes;
+                if (built) {
+                    fresh[a] = c->shared[a];
+                    set.t[nbuild++] = c->t[a];
+                }
+            }
+        }
+    } else if (rc == IGA_OK) {
+        size_t total = 0, off[3] = {0, 0, 0};
+        for (int a = 0; a < c->dim; ++a) {
+            off[a] = total;
+            total += axis_layout(c->t[a], nullptr);
+        }
+        void* base = nullptr;
+        rc = dalloc(c, &base, total);
+        if (rc == IGA_OK) {
+            c->table_bytes = total;
+            for (int a = 0; a < c->dim; ++a) {
+                axis_layout(c->t[a], (char*)base + off[a]);
+                set.t[nbuild++] = c->t[a];
+            }
+        }
+        for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
+            const AxisTables& t = c->t[a];
+            std::vector<int> first(t.R), last(t.R);
+            for (int r = 0; r < t.R; ++r) {
+                first[r] = (int)desc->span_first[a][r];
+                last[r] = (int)desc->span_last[a][r];
+            }
+            // stream-ordered like the allocation; waited for, since the host vectors end here
+            if (hipMemcpyAsync(t.first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice,
+                               c->stream) != hipSuccess ||
+                hipMemcpyAsync(t.last, last.data(), last.size() * sizeof(int), hipMemcpyHostToDevice,
+                               c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess)
+                rc = IGA_E_DEVICE;
+        }
+    }
+    if (rc == IGA_OK && nbuild > 0) {
+        int ncq = 1, nemax = 1, nrmax = 1;
+        size_t lds = 0;
+        for (int k = 0; k < nbuild; ++k) {
+            const AxisTables& t = set.t[k];
+            const int nc = iga::n_classes(t.p, t.ne);
+            ncq = std::max(ncq, nc * t.nq);
+            nemax = std::max(nemax, t.ne);
+            nrmax = std::max(nrmax, std::max(t.R, t.N));
+            lds = std::max(lds, ((size_t)nc * t.nq * 3 * (t.p + 1) + t.nq) * sizeof(double));
+        }
+        set.dim = nbuild;
+        set.kind = desc->spans;
+        set.consts = nullptr;
+        set.nones = 0;
+        hipLaunchKernelGGL(iga::class_tables_kernel, dim3(nbuild), dim3((ncq + 63) / 64 * 64), 0, c->stream,
+                           set);
+        hipLaunchKernelGGL(iga::element_tables_kernel, dim3((nemax + kBlock - 1) / kBlock, nbuild), dim3(kBlock),
+                           0, c->stream, set);
+        hipLaunchKernelGGL(iga::band_tables_kernel, dim3((nrmax + kBlock - 1) / kBlock, nbuild), dim3(kBlock),
+                           lds, c->stream, set);
+        if (hipGetLastError() != hipSuccess) rc = IGA_E_DEVICE;
+        for (int a = 0; a < c->dim && rc == IGA_OK; ++a)
+            if (fresh[a]) rc = axis_built(fresh[a], c->stream);
+    }
     if (rc != IGA_OK) {
+        for (int a = 0; a < c->dim; ++a)
+            if (fresh[a]) axis_discard(fresh[a]);   // never made ready: nobody else uses it
         iga_destroy(c);
         return rc;
     }
@@ -569,6 +819,9 @@ int iga_destroy(iga_ctx* c)
         free_graph(c);
     }
     if (c->cap) (void)hipStreamDestroy(c->cap);
+    // shared axis tables: released after the work queued on this stream
+    for (int a = 0; a < 3; ++a)
+        if (c->shared[a]) axis_release(c->shared[a], c->stream);
     // released in stream order: after every kernel already queued on the stream
     for (void* p : c->allocs) (void)hipFreeAsync(p, c->stream);
     delete c;
@@ -732,6 +985,18 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
     const bool hit = c->gexec && c->g_u == u && c->g_tab == table && c->g_dt == dt &&
                      c->g_amp == amp && c->g_n == nsteps;
     if (!hit) {
+        // a graph pays off only when the same call repeats: the first call of a new set of
+        // arguments launches directly and is remembered
+        const bool repeat = c->l_u == u && c->l_tab == table && c->l_dt == dt && c->l_amp == amp &&
+                            c->l_n == nsteps;
+        if (!repeat) {
+            c->l_u = u;
+            c->l_tab = table;
+            c->l_dt = dt;
+            c->l_amp = amp;
+            c->l_n = nsteps;
+            return enqueue(c->stream);
+        }
         free_graph(c);
         if (!c->cap) IGA_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
         IGA_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
@@ -760,3 +1025,4 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
 
 // batch API (uses the context machinery above)
 #include "batch_host.hpp"
+#include "serve_host.hpp"

@@ -16,13 +16,19 @@
 namespace iga {
 
 struct SrcAxis {
-    int ne, nq, np1;          // elements, Gauss points per element, local functions (p+1)
+    int ne, nq, np1, p;       // elements, Gauss points per element, local functions, degree
     int R;                    // rows of this axis
-    const double* wg;         // [ne*nq] weight * Jacobian
-    const double* bq;         // [ne*nq*3*np1] basis values (Galerkin)
+    const double* gw;         // [nq] weight * Jacobian (the same on every element)
+    const double* cls;        // basis values by element class (see class_of)
     const int* first;         // [R] PG spans
     const int* last;
 };
+
+// W B_{e+a} at Gauss point q of element e
+__device__ __forceinline__ double wbasis(const SrcAxis& A, int e, int q, int a)
+{
+    return A.gw[q] * A.cls[(((size_t)class_of(e, A.p, A.ne) * A.nq + q) * 3) * A.np1 + a];
+}
 
 struct SrcArgs {
     SrcAxis ax[3];            // axes beyond dim: ne = nq = np1 = R = 1, unit tables
@@ -51,10 +57,10 @@ __global__ void pg_src_elem_kernel(SrcArgs s, size_t nel)
     double acc = 0.0;
     for (int qz = 0; qz < Z.nq; ++qz)
         for (int qy = 0; qy < Y.nq; ++qy) {
-            const double wyz = Z.wg[gz0 + qz] * Y.wg[gy0 + qy];
+            const double wyz = Z.gw[qz] * Y.gw[qy];
             const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0;
             double t = 0.0;
-            for (int qx = 0; qx < X.nq; ++qx) t = fma(X.wg[gx0 + qx], row[qx], t);
+            for (int qx = 0; qx < X.nq; ++qx) t = fma(X.gw[qx], row[qx], t);
             acc = fma(wyz, t, acc);
         }
     s.elem[idx] = acc;
@@ -93,12 +99,12 @@ __global__ void gal_src_elem_kernel(SrcArgs s, size_t nel)
         double acc = 0.0;
         for (int qz = 0; qz < Z.nq; ++qz)
             for (int qy = 0; qy < Y.nq; ++qy) {
-                const double tz = Z.wg[gz0 + qz] * Z.bq[((gz0 + qz) * 3) * Z.np1 + az];
-                const double ty = Y.wg[gy0 + qy] * Y.bq[((gy0 + qy) * 3) * Y.np1 + ay];
+                const double tz = wbasis(Z, e[2], qz, az);
+                const double ty = wbasis(Y, e[1], qy, ay);
                 const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0;
                 double t = 0.0;
                 for (int qx = 0; qx < X.nq; ++qx)
-                    t = fma(X.wg[gx0 + qx] * X.bq[((gx0 + qx) * 3) * X.np1 + ax], row[qx], t);
+                    t = fma(wbasis(X, e[0], qx, ax), row[qx], t);
                 acc = fma(tz * ty, t, acc);
             }
         s.elem[idx * nloc + a] = acc;

@@ -117,33 +117,11 @@ __device__ void basis_ders(int p, int ne, int e, double s, double inv_h,
     }
 }
 
-// Elements of an axis fall into at most 2p+1 classes by their local knot pattern: the
-// first p elements, the interior (all alike), the last p.  Basis values at the Gauss
-// points depend only on the class, so they are evaluated once per class.
-__host__ __device__ inline int n_classes(int p, int ne)
-{
-    return ne <= 2 * p + 1 ? ne : 2 * p + 1;
-}
-
-__host__ __device__ inline int class_of(int e, int p, int ne)
-{
-    if (ne <= 2 * p + 1) return e;
-    return e < p ? e : (e > ne - 1 - p ? e - (ne - (2 * p + 1)) : p);
-}
-
-__host__ __device__ inline int class_element(int c, int p, int ne)
-{
-    if (ne <= 2 * p + 1) return c;
-    return c <= p ? c : ne - (2 * p + 1) + c;
-}
-
 // Per-axis device tables.  Layout of one axis (all doubles unless noted):
 //   cls[ncls*nq*3*(p+1)]      cls[((c*nq+q)*3 + m)*(p+1) + a] = B^{(m)}_{e+a} at point q of
 //                             an element e of class c
 //   gw[nq], gs[nq]            weight*Jacobian and local coordinate in [0, 1] of point q
-//   xg[ne*nq], wg[ne*nq]      Gauss points and weight*Jacobian, point q of element e at e*nq+q
-//   sx[ne*nq]                 sin(pi x) at the Gauss points
-//   bq[ne*nq*3*(p+1)]         bq[((e*nq+q)*3 + m)*(p+1) + a] = B^{(m)}_{e+a}(x_{e,q})
+//                             (the same on every element: uniform elements)
 //   es[ne], eg[ne*(p+1)]      element sums of W sin(pi x) and of W B_{e+a} sin(pi x)
 //   pm[R*W], pd[R*W]          PG factors  int_{S_r} B_j,  int_{S_r} B_j''   (column r+k-p)
 //   inv_len[R], fs_pg[R]      1/|S_r|,  int_{S_r} sin(pi x)  (Gauss rule)
@@ -154,15 +132,26 @@ struct AxisTables {
     int p, ne, nq, N, R, W;
     double lo, hi;
     double *cls, *gw, *gs;
-    double *xg, *wg, *bq, *sx, *es, *eg;
+    double *es, *eg;
     double *pm, *pd, *inv_len, *fs_pg;
     double *gm, *gl, *gb, *fs_g;
     int *first, *last;
 };
 
-// One thread per (class, Gauss point): the Gauss rule and the basis values of the class.
-__global__ void class_tables_kernel(AxisTables t)
+// The tables of every axis of a context, filled by three launches in all.
+struct AxisSet {
+    AxisTables t[3];
+    int dim;
+    int kind;         // span kind (iga_spans)
+    double* consts;   // {1, 0 x 7} | two int zeros | ones[nones]
+    size_t nones;
+};
+
+// One workgroup per axis, one thread per (class, Gauss point): the Gauss rule and the
+// basis values of the class.
+__global__ void class_tables_kernel(AxisSet set)
 {
+    const AxisTables& t = set.t[blockIdx.x];
     const int idx = threadIdx.x;
     const int nc = n_classes(t.p, t.ne);
     if (idx >= nc * t.nq) return;
@@ -182,24 +171,33 @@ __global__ void class_tables_kernel(AxisTables t)
         for (int a = 0; a <= t.p; ++a) t.cls[((size_t)idx * 3 + m) * (t.p + 1) + a] = B[m][a];
 }
 
-// One thread per element: its Gauss points, weights, basis values (copied from the class
-// tables), sin(pi x), and the element sums of the sine source.
-__global__ void element_tables_kernel(AxisTables t)
+// One thread per element (blockIdx.y = axis): the element sums of the sine source over
+// its Gauss points (basis values from the class tables).  Row blockIdx.y == dim fills
+// the context's constants when the set carries them.
+__global__ void element_tables_kernel(AxisSet set)
 {
+    if ((int)blockIdx.y == set.dim) {
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 9 + set.nones;
+             i += (size_t)gridDim.x * blockDim.x) {
+            if (i < 8)
+                set.consts[i] = i == 0 ? 1.0 : 0.0;
+            else if (i == 8)
+                ((int*)(set.consts + 8))[0] = ((int*)(set.consts + 8))[1] = 0;
+            else
+                set.consts[i] = 1.0;
+        }
+        return;
+    }
+    const AxisTables& t = set.t[blockIdx.y];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= t.ne) return;
     const int np1 = t.p + 1, nb = 3 * np1;
     const int c = class_of(e, t.p, t.ne);
     double es = 0.0, eg[kMaxP + 1] = {};
     for (int q = 0; q < t.nq; ++q) {
-        const size_t idx = (size_t)e * t.nq + q;
         const double x = t.lo + (t.hi - t.lo) * (((double)e + t.gs[q]) / (double)t.ne);
         const double sx = sin(M_PI * x), w = t.gw[q];
-        t.xg[idx] = x;
-        t.sx[idx] = sx;
-        t.wg[idx] = w;
         const double* B = t.cls + ((size_t)c * t.nq + q) * nb;
-        for (int i = 0; i < nb; ++i) t.bq[idx * nb + i] = B[i];
         es += w * sx;
         for (int a = 0; a <= t.p; ++a) eg[a] += w * B[a] * sx;
     }
@@ -211,8 +209,10 @@ __global__ void element_tables_kernel(AxisTables t)
 // in LDS.  PG rows never multiply by a test function -- the integrand is summed with
 // weight 1 over the span's elements.  Spans of the built-in kinds (kind 0 support, 1
 // element) are generated here; caller spans (kind 2) are already in first/last.
-__global__ void band_tables_kernel(AxisTables t, int kind)
+__global__ void band_tables_kernel(AxisSet set)
 {
+    const AxisTables& t = set.t[blockIdx.y];
+    const int kind = set.kind;
     extern __shared__ double sb[];
     const int p = t.p, np1 = t.p + 1, nq = t.nq, W = t.W;
     const int nb = 3 * np1, nc = n_classes(p, t.ne);

@@ -43,6 +43,15 @@ class Job(C.Structure):
                 ("mass_out", C.c_void_p), ("lap_out", C.c_void_p)]
 
 
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dim", C.c_int32), ("p", C.c_int32), ("ne", C.c_int64 * 3),
+                ("nsteps", C.c_int32), ("dt", C.c_double), ("sin_amp", C.c_double),
+                ("u", C.c_void_p), ("mass_out", C.c_void_p), ("lap_out", C.c_void_p)]
+
+
+REQ_RHS, REQ_STEP = 0, 1
+
+
 class IGAError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -71,6 +80,13 @@ _SIGS = {
     "iga_batch_wait": [C.c_void_p],
     "iga_batch_autotune": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float)],
     "iga_batch_destroy": [C.c_void_p],
+    "iga_server_create": [C.c_int32, C.c_size_t, C.c_size_t, C.POINTER(C.c_void_p)],
+    "iga_server_submit": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "iga_server_progress": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                            C.POINTER(C.c_int32)],
+    "iga_server_stats": [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                         C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+    "iga_server_destroy": [C.c_void_p],
 }
 
 
@@ -349,6 +365,73 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "h", None):
             _check(lib().iga_batch_destroy(self.h), "iga_batch_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving ----------------------------------------------------------------------
+
+def request_dtype():
+    """numpy record layout of iga_request (checked against the ctypes structure)."""
+    import numpy as np
+    dt = np.dtype({"names": [f[0] for f in Request._fields_],
+                   "formats": [np.int32, np.int32, np.int32, (np.int64, 3), np.int32, np.float64,
+                               np.float64, np.uint64, np.uint64, np.uint64],
+                   "offsets": [getattr(Request, f[0]).offset for f in Request._fields_],
+                   "itemsize": C.sizeof(Request)})
+    return dt
+
+
+class NativeServer:
+    """The library's request loop (iga_server_*).  Buffers of submitted requests must stay
+    alive until they are reported done."""
+
+    def __init__(self, nstreams: int = 4, budget_bytes: int = 200 * 10**9,
+                 cache_bytes: int = 16 << 30):
+        import numpy as np
+        self.h = C.c_void_p()
+        _check(lib().iga_server_create(nstreams, budget_bytes, cache_bytes, C.byref(self.h)),
+               "iga_server_create")
+        self.dtype = request_dtype()
+        self._cap = 4096
+        self._done = np.zeros(self._cap, dtype=np.uint64)
+        self._time = np.zeros(self._cap, dtype=np.float64)
+        self._state = np.zeros(self._cap, dtype=np.int32)
+        self._launch = np.zeros(self._cap, dtype=np.int64)
+
+    def submit(self, recs) -> "object":
+        """recs: numpy array of request_dtype(); returns the tickets (numpy uint64)."""
+        import numpy as np
+        recs = np.ascontiguousarray(recs, dtype=self.dtype)
+        tickets = np.zeros(max(1, len(recs)), dtype=np.uint64)
+        _check(lib().iga_server_submit(self.h, recs.ctypes.data, len(recs), tickets.ctypes.data),
+               "iga_server_submit")
+        return tickets[: len(recs)]
+
+    def progress(self):
+        """Completions observed now: (tickets, times, states, batch launch indices)."""
+        n = C.c_int32()
+        _check(lib().iga_server_progress(self.h, self._done.ctypes.data, self._time.ctypes.data,
+                                         self._state.ctypes.data, self._launch.ctypes.data,
+                                         self._cap, C.byref(n)), "iga_server_progress")
+        k = n.value
+        return (self._done[:k].copy(), self._time[:k].copy(), self._state[:k].copy(),
+                self._launch[:k].copy())
+
+    def stats(self):
+        used, peak, launches, now = C.c_size_t(), C.c_size_t(), C.c_int64(), C.c_double()
+        _check(lib().iga_server_stats(self.h, C.byref(used), C.byref(peak), C.byref(launches),
+                                      C.byref(now)), "iga_server_stats")
+        return used.value, peak.value, launches.value, now.value
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            _check(lib().iga_server_destroy(self.h), "iga_server_destroy")
             self.h = None
 
     def __del__(self):

@@ -108,6 +108,8 @@ class Request:
     ne: Tuple[int, ...]    # elements per axis (x, y, z)
     nsteps: int            # explicit steps (0 for rhs)
     seed: int              # seed of this request's coefficients
+    u: object = None       # the coefficients already on the device (optional)
+    out: object = None     # RHS: its two output arrays on the device, (2,) + u.shape (optional)
 
 
 def request_stream(rate: float = 2000.0, seconds: float = 10.0, seed: int = 5,

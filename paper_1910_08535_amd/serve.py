@@ -1,22 +1,19 @@
 """Continuous-batching server for right-hand-side and explicit-step requests.
 
-Every computation runs in the library's kernels; this module only schedules them:
+The request loop itself is native (iga_server_* in the library, see include/iga.h):
+admission by device memory, a context cache bound to a pool of streams, 2D RHS requests
+riding the next persistent batch launch, event-based completion.  This module replays
+arrivals in wall-clock time, hands each arriving group of requests to the library in one
+call, and records latencies:
 
 * Requests arrive over time (``inputs.request_stream``: Poisson arrivals, 1D/2D/3D,
   p in {2,3}, RHS = fused Petrov-Galerkin apply (mass and Laplacian rows), STEP =
   nsteps explicit steps of u_t = Lap u + sin source with dt = h_min^2 / 64).
-* Admission by device memory: a request is admitted, in arrival order, when its
-  resident state (coefficients plus outputs or the step's work buffer) fits in the
-  budget next to everything admitted and not yet finished; its state stays on the
-  device until it completes.
-* 2D RHS requests go to the persistent batch kernel (iga_batch).  Whenever no batch
-  launch is running and jobs are queued, one launch takes all of them; requests that
-  arrive while a launch runs ride the next one (iteration-level continuous batching).
-* Explicit steps and 1D/3D RHS requests run on a pool of streams, concurrently with
-  the batch launch and with each other; every mesh gets a context (tables built once,
-  cached) bound to one stream of the pool.
-* Latency of a request = completion time - arrival time (wall clock; completion is
-  observed from the HIP events of its launch).
+* A request may bring its coefficients already on the device (Request.u; the server
+  then updates them in place for a step request) and its two output arrays
+  (Request.out, shape (2,) + coefficient shape); otherwise they are drawn from its seed
+  and allocated at submission.
+* Latency of a request = time its completion is observed - its arrival time.
 
 Results do not depend on the mix: a request runs the same kernels with the same
 launch geometry alone and among others (tests check equality bit for bit).
@@ -25,8 +22,10 @@ from __future__ import annotations
 
 import collections
 import time
-from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Tuple
+from dataclasses import dataclass
+from typing import Dict, List, Tuple
+
+import numpy as np
 
 from . import iga
 from .inputs import Request
@@ -35,23 +34,29 @@ from .inputs import Request
 @dataclass
 class Record:
     req: Request
-    t_admit: float = -1.0
-    t_done: float = -1.0
-    bytes: int = 0
+    t_arrive: float = -1.0          # arrival, in the library's clock (seconds)
+    t_done: float = -1.0            # completion observed, same clock
     gauss_points: int = 0
     hbm_bytes: int = 0
-    tensors: Tuple = ()
-    ticket: Optional[int] = None    # batch ticket (2D RHS)
-    event: object = None            # stream event (others)
-    batch_launch: int = -1
+    tensors: Tuple = ()             # (u, mass rows, Laplacian rows) or (u,)
+    batch_launch: int = -1          # index of the batch launch that ran it, -1 for none
 
     @property
     def latency(self) -> float:
-        return self.t_done - self.req.t_arrive
+        return self.t_done - self.t_arrive
 
 
 def request_shape(req: Request) -> Tuple[int, ...]:
     return tuple(n + req.p for n in reversed(req.ne))
+
+
+def context_bytes(dim: int, p: int, ne: Tuple[int, ...]) -> int:
+    """Approximate device bytes of a mesh context (Gauss-point and band tables)."""
+    w = 2 * p + 1
+    total = 0
+    for n in ne[:dim]:
+        total += 8 * (n * (p + 2) + (n + p) * (5 * w + 4))
+    return total
 
 
 def request_work(req: Request) -> Tuple[int, int]:
@@ -67,147 +72,147 @@ def request_work(req: Request) -> Tuple[int, int]:
     return gp * req.nsteps, 16 * ncoef * req.nsteps
 
 
-class Server:
-    def __init__(self, budget_bytes: int = 200 * 10**9, streams: int = 4, max_batch: int = 4096,
-                 batch_rows: int = 8, max_meshes: int = 512, keep_outputs: bool = False):
-        import torch
-        self.torch = torch
-        self.budget = budget_bytes
-        self.used = 0
-        self.streams = [torch.cuda.Stream() for _ in range(streams)]
-        self.batch_stream = torch.cuda.Stream()
-        self.batch = iga.Batch(max_jobs=max_batch, stream=self.batch_stream)
-        self.batch_rows = batch_rows
-        self.meshes: "collections.OrderedDict[tuple, iga.Mesh]" = collections.OrderedDict()
-        self.max_meshes = max_meshes
-        self.next_stream = 0
-        self.keep = keep_outputs
-        self.batch_running: List[Record] = []
-        self.batch_queued: List[Record] = []
-        self.batch_event = None
-        self.batch_launches = 0
-        # launches on one stream complete in order: one FIFO of records per stream
-        self.inflight: Dict[int, "collections.deque[Record]"] = {
-            id(st): collections.deque() for st in self.streams}
-        self.gen = torch.Generator(device="cuda")
-        self.done: List[Record] = []
+class MeshCache:
+    """Contexts by (dim, p, element counts), least recently used first out once their
+    device bytes exceed a limit; new contexts are bound round-robin to the given streams."""
 
-    # ---- meshes ------------------------------------------------------------------
-    def mesh(self, req: Request) -> "iga.Mesh":
-        key = (req.dim, req.p, req.ne)
+    def __init__(self, streams, limit_bytes: int = 16 << 30):
+        self.streams = streams
+        self.limit = limit_bytes
+        self.bytes = 0
+        self.next = 0
+        self.meshes: "collections.OrderedDict[tuple, iga.Mesh]" = collections.OrderedDict()
+
+    def get(self, dim: int, p: int, ne: Tuple[int, ...]) -> "iga.Mesh":
+        key = (dim, p, ne)
         m = self.meshes.get(key)
         if m is not None:
             self.meshes.move_to_end(key)
             return m
-        s = self.streams[self.next_stream % len(self.streams)]
-        self.next_stream += 1
-        m = iga.Mesh(req.dim, req.p, req.ne, (req.p + 1,) * req.dim, stream=s)
+        s = self.streams[self.next % len(self.streams)] if self.streams else None
+        self.next += 1
+        m = iga.Mesh(dim, p, ne, (p + 1,) * dim, stream=s)
         self.meshes[key] = m
-        while len(self.meshes) > self.max_meshes:
-            _, old = self.meshes.popitem(last=False)
+        self.bytes += context_bytes(dim, p, ne)
+        while self.bytes > self.limit and len(self.meshes) > 1:
+            (d, q, n), old = self.meshes.popitem(last=False)
+            self.bytes -= context_bytes(d, q, n)
             old.close()
         return m
 
-    # ---- admission and dispatch -----------------------------------------------------
-    def footprint(self, req: Request) -> int:
-        n = 1
-        for d in request_shape(req):
-            n *= d
-        return (3 if req.kind == "rhs" else 2) * 8 * n
+    def close(self) -> None:
+        for m in self.meshes.values():
+            m.close()
+        self.meshes.clear()
+        self.bytes = 0
 
-    def admit(self, req: Request, now: float) -> Optional[Record]:
-        need = self.footprint(req)
-        if self.used + need > self.budget:
-            return None
+
+def footprint(req: Request) -> int:
+    """Bytes a request holds while in flight: coefficients plus both outputs (RHS), or
+    coefficients plus the step's work buffer."""
+    n = 1
+    for d in request_shape(req):
+        n *= d
+    return (3 if req.kind == "rhs" else 2) * 8 * n
+
+
+class Server:
+    def __init__(self, budget_bytes: int = 200 * 10**9, streams: int = 4,
+                 mesh_cache_bytes: int = 16 << 30, keep_outputs: bool = False):
+        import torch
+        self.torch = torch
+        self.native = iga.NativeServer(streams, budget_bytes, mesh_cache_bytes)
+        self.keep = keep_outputs
+        self.gen = torch.Generator(device="cuda")
+        self.done: List[Record] = []
+        self.live: Dict[int, Record] = {}
+
+    @property
+    def used(self) -> int:
+        return self.native.stats()[0]
+
+    @property
+    def peak(self) -> int:
+        return self.native.stats()[1]
+
+    def _tensors(self, req: Request):
         torch = self.torch
-        rec = Record(req=req, t_admit=now, bytes=need)
-        rec.gauss_points, rec.hbm_bytes = request_work(req)
-        self.used += need
         shape = request_shape(req)
-        gen = self.gen
-        gen.manual_seed(req.seed)
-        if req.dim == 2 and req.kind == "rhs":
-            with torch.cuda.stream(self.batch_stream):
-                u = torch.randn(shape, dtype=torch.float64, device="cuda", generator=gen)
-                m, l = torch.empty_like(u), torch.empty_like(u)
-            rec.tensors = (u, m, l)
-            self.batch_queued.append(rec)
-            return rec
-        mesh = self.mesh(req)
-        s = mesh.stream
-        with torch.cuda.stream(s):
-            u = torch.randn(shape, dtype=torch.float64, device="cuda", generator=gen)
+        u = req.u
+        if u is None:
+            self.gen.manual_seed(req.seed)
+            u = torch.randn(shape, dtype=torch.float64, device="cuda", generator=self.gen)
+        if req.kind != "rhs":
+            return (u,)
+        out = getattr(req, "out", None)
+        if out is None:
+            out = torch.empty((2,) + shape, dtype=torch.float64, device="cuda")
+        return (u, out[0], out[1])
+
+    def submit(self, reqs: List[Request], arrivals: List[float]) -> None:
+        """Hands a group of arrived requests to the library (arrival times in the
+        library's clock)."""
+        if not reqs:
+            return
+        recs = np.zeros(len(reqs), dtype=self.native.dtype)
+        records = []
+        fresh = False
+        for k, req in enumerate(reqs):
+            fresh = fresh or req.u is None or (req.kind == "rhs" and getattr(req, "out", None) is None)
+            tens = self._tensors(req)
+            r = recs[k]
+            r["kind"] = iga.REQ_RHS if req.kind == "rhs" else iga.REQ_STEP
+            r["dim"], r["p"] = req.dim, req.p
+            r["ne"][: req.dim] = req.ne
+            r["ne"][req.dim:] = 1
+            r["u"] = tens[0].data_ptr()
             if req.kind == "rhs":
-                m, l = mesh.apply(iga.PG, u)
-                rec.tensors = (u, m, l)
+                r["mass_out"], r["lap_out"] = tens[1].data_ptr(), tens[2].data_ptr()
             else:
                 h = min(1.0 / n for n in req.ne)
-                dt = h * h / 64.0
-                for _ in range(req.nsteps):
-                    mesh.explicit_step(u, dt, sin_amp=1.0, nsteps=1)
-                rec.tensors = (u,)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        rec.event = ev
-        self.inflight[id(s)].append(rec)
-        return rec
+                r["nsteps"], r["dt"], r["sin_amp"] = req.nsteps, h * h / 64.0, 1.0
+            rec = Record(req=req, t_arrive=arrivals[k], tensors=tens)
+            rec.gauss_points, rec.hbm_bytes = request_work(req)
+            records.append(rec)
+        if fresh:   # coefficients drawn or outputs allocated on torch's stream just now
+            self.torch.cuda.current_stream().synchronize()
+        tickets = self.native.submit(recs)
+        for t, rec in zip(tickets.tolist(), records):
+            self.live[t] = rec
 
-    def _flush_batch(self, now: float) -> None:
-        if self.batch_running or not self.batch_queued:
-            return
-        jobs = [(r.req.p, r.req.ne, *r.tensors) for r in self.batch_queued]
-        for r in self.batch_queued:
-            r.batch_launch = self.batch_launches
-        tickets = self.batch.submit(jobs)
-        for r, t in zip(self.batch_queued, tickets):
-            r.ticket = t
-        self.batch.flush()
-        ev = self.torch.cuda.Event()
-        ev.record(self.batch_stream)
-        self.batch_event = ev
-        self.batch_running = self.batch_queued
-        self.batch_queued = []
-        self.batch_launches += 1
-
-    def _complete(self, rec: Record, now: float) -> None:
-        rec.t_done = now
-        self.used -= rec.bytes
-        if not self.keep:
-            rec.tensors = ()
-        self.done.append(rec)
-
-    def _progress(self, now: float) -> None:
-        if self.batch_running and self.batch_event.query():
-            for r in self.batch_running:
-                self._complete(r, now)
-            self.batch_running = []
-        for q in self.inflight.values():
-            while q and q[0].event.query():
-                self._complete(q.popleft(), now)
+    def _progress(self) -> None:
+        tickets, times, states, launches = self.native.progress()
+        for t, tm, st, ln in zip(tickets.tolist(), times.tolist(), states.tolist(), launches.tolist()):
+            rec = self.live.pop(t)
+            if st != iga.JOB_DONE:
+                raise RuntimeError(f"request failed: {rec.req}")
+            rec.t_done = tm
+            rec.batch_launch = ln
+            if not self.keep:
+                rec.tensors = ()
+            self.done.append(rec)
 
     # ---- the loop --------------------------------------------------------------------
     def run(self, requests: List[Request], time_scale: float = 1.0) -> Dict[str, float]:
         """Serve `requests` (sorted by arrival; arrivals replayed in wall-clock time scaled
-        by time_scale) until all are done; returns latency and throughput figures."""
+        by time_scale, every request at once for 0) until all are done; returns latency
+        and throughput figures."""
         pending = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
-        waiting: "collections.deque[Request]" = collections.deque()
+        total = len(requests) + len(self.done)
+        start = self.native.stats()[3]
         t0 = time.perf_counter()
-        total = len(requests)
         while len(self.done) < total:
             now = time.perf_counter() - t0
+            group = []
             while pending and pending[0].t_arrive * time_scale <= now:
-                waiting.append(pending.popleft())
-            while waiting:
-                if self.admit(waiting[0], now) is None:
-                    break
-                waiting.popleft()
-            self._flush_batch(now)
-            self._progress(time.perf_counter() - t0)
+                group.append(pending.popleft())
+            self.submit(group, [start + r.t_arrive * time_scale for r in group])
+            self._progress()
         wall = time.perf_counter() - t0
-        return self.summary(wall, time_scale)
+        return self.summary(wall)
 
-    def summary(self, wall: float, time_scale: float = 1.0) -> Dict[str, float]:
-        lat = sorted((r.t_done - r.req.t_arrive * time_scale) for r in self.done)
+    def summary(self, wall: float) -> Dict[str, float]:
+        lat = sorted(r.latency for r in self.done)
         n = len(lat)
         gp = sum(r.gauss_points for r in self.done)
         by = sum(r.hbm_bytes for r in self.done)
@@ -217,11 +222,8 @@ class Server:
 
         return {"requests": n, "wall_s": wall, "p50_ms": pct(0.50) * 1e3, "p99_ms": pct(0.99) * 1e3,
                 "max_ms": (lat[-1] * 1e3) if n else float("nan"), "GPs": gp / wall,
-                "algorithmic_GBs": by / wall / 1e9, "batch_launches": self.batch_launches}
+                "algorithmic_GBs": by / wall / 1e9, "batch_launches": self.native.stats()[2]}
 
     def close(self) -> None:
         self.torch.cuda.synchronize()
-        self.batch.close()
-        for m in self.meshes.values():
-            m.close()
-        self.meshes.clear()
+        self.native.close()

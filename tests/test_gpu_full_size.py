@@ -135,9 +135,11 @@ def test_c3_full_size_steps(iga, orc):
     for rows in slabs:
         ref = _oracle_step_slab(orc, pb, u0, c.dt, rows)
         assert relerr(a1[rows[0]:rows[1]], ref) <= TOL, rows
-    # 100 steps in one graph (the benchmark's launch) == 99 steps + 1 step, bitwise
+    # 50 steps launched directly, then the same 50-step call again from its captured graph
+    # (how the benchmark runs) == 99 steps + 1 step, bitwise
     b = cuda(u0)
-    mesh.explicit_step(b, c.dt, sin_amp=c.sin_amp, nsteps=c.nsteps)
+    for _ in range(2):
+        mesh.explicit_step(b, c.dt, sin_amp=c.sin_amp, nsteps=c.nsteps // 2)
     d = cuda(u0)
     mesh.explicit_step(d, c.dt, sin_amp=c.sin_amp, nsteps=c.nsteps - 1)
     u99 = host(d)

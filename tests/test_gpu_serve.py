@@ -73,21 +73,43 @@ def test_mix_equals_alone_and_oracle(mods, orc):
 
 
 def test_budget_limits_admission(mods):
-    import torch
     iga, serve = mods
     reqs = inputs.request_stream(rate=2000.0, seconds=0.02, seed=3, max_1d=5000, max_2d=96,
                                  max_3d=16)
-    budget = max(serve.Server.footprint(None, r) for r in reqs)   # one request at a time
+    budget = max(serve.footprint(r) for r in reqs)   # one request at a time
     srv = serve.Server(budget_bytes=budget, streams=2)
-    peak = []
-    orig = srv.admit
-
-    def admit(req, now):
-        rec = orig(req, now)
-        peak.append(srv.used)
-        return rec
-
-    srv.admit = admit
     srv.run(reqs)
-    assert max(peak) <= budget and len(srv.done) == len(reqs)
+    assert len(srv.done) == len(reqs)
+    assert 0 < srv.peak <= budget and srv.used == 0
     srv.close()
+
+
+def test_server_rejects_bad_requests(mods):
+    import torch
+    iga, serve = mods
+    s = iga.NativeServer(nstreams=1, budget_bytes=1 << 20)
+    u = torch.zeros(40, dtype=torch.float64, device="cuda")
+    m, l = torch.empty_like(u), torch.empty_like(u)
+    good = np.zeros(1, dtype=s.dtype)
+    good["kind"], good["dim"], good["p"] = iga.REQ_RHS, 1, 2
+    good["ne"][0] = [38, 1, 1]
+    good["u"], good["mass_out"], good["lap_out"] = u.data_ptr(), m.data_ptr(), l.data_ptr()
+    for field, value, code in (("p", 4, iga.IGA_E_UNSUPPORTED), ("dim", 0, iga.IGA_E_UNSUPPORTED),
+                               ("kind", 7, iga.IGA_E_INVAL), ("lap_out", 0, iga.IGA_E_INVAL)):
+        bad = good.copy()
+        bad[field] = value
+        with pytest.raises(iga.IGAError) as e:
+            s.submit(bad)
+        assert e.value.code == code, field
+    big = good.copy()
+    big["ne"][0] = [100000, 1, 1]   # more bytes than the whole budget
+    with pytest.raises(iga.IGAError) as e:
+        s.submit(big)
+    assert e.value.code == iga.IGA_E_NOMEM
+    t = s.submit(good)
+    while True:
+        done = s.progress()[0]
+        if len(done):
+            break
+    assert done.tolist() == t.tolist() and s.stats()[0] == 0
+    s.close()
