@@ -242,3 +242,37 @@ def test_3d_tile_settings(iga, orc, p):
         assert relerr(host(l), rl) <= TOL, (rows, planes)
     with pytest.raises(iga.IGAError):
         mesh.set_tile(iga.TILE_3D_ROWS, 3)
+
+
+def test_shared_axis_tables_across_streams(iga, orc):
+    """Contexts with equal axes share one copy of the tables: built on the first context's
+    stream and waited for by the others; destroying a context while another still has
+    work queued on the shared tables leaves that work intact; results equal a context of
+    their own (bitwise) and the oracle."""
+    import torch
+    p, ne = 3, (57, 57, 23)   # two equal axes in one context, the third shared across contexts
+    u = cuda(inputs.normal_coefs(ne, p, seed=31))
+    ref_m, ref_l = iga.Mesh(3, p, ne, (4, 4, 4)).apply(iga.PG, u)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs = []
+    for k, s in enumerate(streams):
+        mesh = iga.Mesh(3, p, ne, (4, 4, 4), stream=s)
+        with torch.cuda.stream(s):
+            m = torch.empty_like(u)
+            l = torch.empty_like(u)
+        s.wait_stream(torch.cuda.current_stream())
+        for _ in range(3):   # keep the stream busy, then drop the context at once
+            mesh.apply(iga.PG, u, out_mass=m, out_lap=l)
+        mesh.close()
+        outs.append((m, l))
+    # a context on a 2D mesh sharing the x axis, created after the others were destroyed
+    mesh2 = iga.Mesh(2, p, ne[:2], (4, 4))
+    u2 = cuda(inputs.normal_coefs(ne[:2], p, seed=32))
+    m2, l2 = mesh2.apply(iga.PG, u2)
+    torch.cuda.synchronize()
+    for m, l in outs:
+        assert torch.equal(m, ref_m) and torch.equal(l, ref_l)
+    pb = orc.Problem(dim=2, p=p, ne=ne[:2], nq=(4, 4))
+    assert relerr(host(l2), orc.rhs(pb, orc.PG, u2.cpu().numpy(), beta=1.0)) <= TOL
+    assert relerr(host(m2), orc.rhs(pb, orc.PG, u2.cpu().numpy(), alpha=1.0)) <= TOL
