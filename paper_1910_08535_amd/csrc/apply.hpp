@@ -125,9 +125,16 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned byte_
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
 }
 
+// Cache policy of a buffer store: kStream marks it non-temporal, for outputs that
+// this kernel never reads back (their lines then do not displace the halo rows of
+// the input that neighbouring tiles still have to fetch).
+constexpr int kKeep = 0;
+constexpr int kStream = 2;
+
+template <int POLICY = kKeep>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double v)
 {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2, v), r, (int)byte_off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2, v), r, (int)byte_off, 0, POLICY);
 }
 
 typedef int iv4 __attribute__((ext_vector_type(4)));
@@ -138,12 +145,13 @@ __device__ __forceinline__ dv2 bload2(__amdgpu_buffer_rsrc_t r, unsigned byte_of
     return __builtin_bit_cast(dv2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
 }
 
+template <int POLICY = kKeep>
 __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double a, double b)
 {
     dv2 v;
     v.x = a;
     v.y = b;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4, v), r, (int)byte_off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4, v), r, (int)byte_off, 0, POLICY);
 }
 
 // byte offset of element (row, col) of a rows x cols array, kOOB outside it
@@ -314,10 +322,10 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
             const unsigned o1 = rowok && okc1 ? ob + 8u : kOOB;
             if constexpr ((MODE & kMass) != 0) {
                 if constexpr (VEC) {
-                    bstore2(rm, o0, ms0, ms1);
+                    bstore2<kStream>(rm, o0, ms0, ms1);
                 } else {
-                    bstore(rm, o0, ms0);
-                    bstore(rm, o1, ms1);
+                    bstore<kStream>(rm, o0, ms0);
+                    bstore<kStream>(rm, o1, ms1);
                 }
             }
             double w0 = fma(g.alpha, ms0, g.beta * (lx0 + ly0));
@@ -341,10 +349,10 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
                 w1 *= sx1 * cr[2 * W];
             }
             if constexpr (VEC) {
-                bstore2(ro, o0, w0, w1);
+                bstore2<kStream>(ro, o0, w0, w1);
             } else {
-                bstore(ro, o0, w0);
-                bstore(ro, o1, w1);
+                bstore<kStream>(ro, o0, w0);
+                bstore<kStream>(ro, o1, w1);
             }
         }
     }
