@@ -7,7 +7,8 @@ built by ``oracle/build.py``) and shares no code with the GPU library.
 Axis order is (x, y, z) in every per-axis argument; numpy arrays are C-ordered
 (N_z, N_y, N_x), x fastest.  Definitions follow arXiv:1910.08535: Section 2 for
 the basis and the row sums, Section 3 for the tensor product, Section 4.1 for the
-generation loops, Section 4.2 for the explicit step.
+generation loops and the alternating-directions solve with the Galerkin mass,
+Section 4.2 for the explicit steps.
 """
 from __future__ import annotations
 
@@ -248,3 +249,41 @@ def span_lengths(pb: Problem) -> Tuple[np.ndarray, ...]:
         f, l = pb._spans[a]
         out.append((l - f + 1) * h)
     return tuple(out)
+
+
+def galerkin_mass_1d(pb: Problem, a: int) -> np.ndarray:
+    """Dense 1D Galerkin mass matrix M_a(i, j) = int B_i B_j of axis a (Section 4.1)."""
+    return matrix_1d(pb.p, pb.ne[a], pb.nq[a], MAT_GAL_MASS, pb.lo[a], pb.hi[a])
+
+
+def ads_solve(pb: Problem, b: np.ndarray) -> np.ndarray:
+    """Solves (M_z (x) M_y (x) M_x) x = b, x fastest, with M_a the 1D Galerkin mass.
+
+    The alternating-directions direct solver of Section 4.1: the Kronecker structure
+    turns the solve into three families of 1D systems with many right-hand sides,
+    first along x (one right-hand side per (y, z) line), then along y, then along z.
+    Each family is one call of numpy.linalg.solve (dense LU with partial pivoting)
+    on all of its lines at once."""
+    x = np.array(b, dtype=np.float64, copy=True)
+    assert x.shape == pb.coef_shape(), (x.shape, pb.coef_shape())
+    for a in range(pb.dim):
+        M = galerkin_mass_1d(pb, a)
+        ax = pb.dim - 1 - a                      # numpy axis of mesh axis a
+        lines = np.moveaxis(x, ax, 0)
+        sol = np.linalg.solve(M, lines.reshape(M.shape[0], -1))
+        x = np.moveaxis(sol.reshape(lines.shape), 0, ax)
+    return np.ascontiguousarray(x)
+
+
+def galerkin_step(pb: Problem, u: np.ndarray, dt: float, form: int = GALERKIN_LAPLACIAN,
+                  f_table: Optional[np.ndarray] = None, sin_amp: float = 0.0,
+                  nsteps: int = 1) -> np.ndarray:
+    """nsteps forward-Euler steps of u_t = Lap u + f in a Galerkin form with the
+    consistent mass (Section 4.2): M u_{t+1} = int B_r (u_t + dt Lap u_t + dt f), the
+    right-hand side generated as in the projection problem and the mass system solved
+    with the alternating-directions solver."""
+    v = np.array(u, dtype=np.float64, copy=True)
+    for _ in range(nsteps):
+        b = rhs(pb, form, v, 1.0, dt, dt, f_table, sin_amp)
+        v = ads_solve(pb, b)
+    return v

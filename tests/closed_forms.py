@@ -33,3 +33,10 @@ def support_span_moments(p, ne, rows):
     a, b = s / ne, (t + 1) / ne
     width = (t + 1 - s) / ne
     return width, width * (a * a + a * b + b * b) / 3.0
+
+
+def lin_coefs(p, ne):
+    """Coefficients c_j with sum_j c_j B_j(x) = x on [0, 1]: the Greville abscissae, the
+    mean of the knots t_{j+1} .. t_{j+p}."""
+    t = knots(p, ne)
+    return np.mean(np.stack([t[i + 1:i + 1 + ne + p] for i in range(p)]), axis=0)
