@@ -70,6 +70,7 @@ extern "C" {
 #define IGA_E_NOMEM (-3)       /* device allocation failed / batch over its memory budget */
 #define IGA_E_DEVICE (-4)      /* a HIP call failed */
 #define IGA_E_AGAIN (-5)       /* batch queue full: poll and submit again */
+#define IGA_E_SINGULAR (-6)    /* solve with the Petrov-Galerkin form (singular system)  */
 
 typedef enum { IGA_GALERKIN_BYPARTS = 0, IGA_GALERKIN_LAPLACIAN = 1, IGA_PG = 2 } iga_form;
 typedef enum { IGA_OP_MASS = 0, IGA_OP_LAPLACE = 1 } iga_op;
@@ -165,6 +166,32 @@ int iga_apply(iga_ctx *ctx, int32_t form, const double *u, double *mass_out, dou
    context and replayed while they stay the same (a first call launches directly).
    Errors: IGA_E_INVAL (also for other span kinds), IGA_E_NOMEM. */
 int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, int32_t nsteps);
+
+/* Alternating-directions direct solve with the Galerkin mass (Section 4.1):
+     (M_z (x) M_y (x) M_x) x = b,   M_a(i, j) = int B_i B_j  on axis a,
+   the matrix of the Galerkin L2 projection.  The Kronecker structure reduces it to
+   three families of 1D banded systems with many right-hand sides: along x for every
+   (y, z) line, then along y, then along z.  Each M_a (bandwidth p, symmetric positive
+   definite) is factorized once, M_a = L_a L_a^T, at the context's first solve (kernels
+   on its stream; the factors stay with the context), and every solve runs a forward and
+   a backward substitution along every line.
+   b, x: device coefficient arrays (N_z, N_y, N_x); x may equal b (in place); b is not
+   modified unless x == b.  form: IGA_GALERKIN_BYPARTS or IGA_GALERKIN_LAPLACIAN (one
+   mass matrix for both).
+   Errors: IGA_E_INVAL, IGA_E_SINGULAR for IGA_PG (with spans made of whole elements the
+   PG mass matrix has rank at most prod_a ne[a] < prod_a N_a), IGA_E_NOMEM. */
+int iga_solve(iga_ctx *ctx, int32_t form, const double *b, double *x);
+
+/* nsteps forward-Euler steps of u_t = Lap u + f (Section 4.2) in a Galerkin form with
+   the consistent mass:
+     M u_{t+1} = int B_r (u_t + dt Lap u_t + dt f)   (Laplacian term by parts for
+   IGA_GALERKIN_BYPARTS),
+   the right-hand side generated as by iga_rhs and the mass system solved as by
+   iga_solve.  u: device coefficients, updated in place.  The scheme is stable only for
+   dt below 2 / lambda_max(M^{-1} K) (of order h^2).
+   Errors: IGA_E_INVAL, IGA_E_SINGULAR for IGA_PG, IGA_E_NOMEM. */
+int iga_galerkin_step(iga_ctx *ctx, int32_t form, double *u, double dt, const iga_source *f,
+                      int32_t nsteps);
 
 /* Tile configuration of the context's kernels (what the autotuner varies).  A setting
    fixes the order of every sum, so results are reproducible for a given setting; other

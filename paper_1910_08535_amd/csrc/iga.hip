@@ -15,6 +15,7 @@
 
 #include "iga.h"
 
+#include "ads.hpp"
 #include "apply.hpp"
 #include "apply3d.hpp"
 #include "common.hpp"
@@ -64,6 +65,8 @@ struct iga_ctx {
     size_t elem_n = 0;
     double* work = nullptr;
     size_t work_n = 0;
+    // banded Cholesky factors of the Galerkin mass per axis (built at the first solve)
+    double* chol[3] = {nullptr, nullptr, nullptr};
     // cached explicit-step graph
     hipGraphExec_t gexec = nullptr;
     const double* g_u = nullptr;
@@ -686,6 +689,52 @@ __global__ void bands_out_kernel(double* dst, const double* f0, const double* f1
 
 }  // namespace
 
+namespace {
+
+// Factors of the Galerkin mass of every axis, computed once on the context's stream.
+int ensure_factors(iga_ctx* c)
+{
+    for (int a = 0; a < c->dim; ++a) {
+        if (c->chol[a]) continue;
+        const int N = c->N[a], p = c->p;
+        void* mem = nullptr;
+        IGA_TRY(dalloc(c, &mem, (size_t)(N + p) * (p + 1) * sizeof(double)));
+        c->chol[a] = (double*)mem;
+        // rows with identical mass bands: B_i and its neighbours clear of the end knots
+        const int ilo = 2 * p, ihi = c->ne[a] - 1 - p;
+        if (p == 2)
+            hipLaunchKernelGGL(iga::chol_band_kernel<2>, dim3(1), dim3(256), 0, c->stream,
+                               (const double*)c->t[a].gm, N, ilo, ihi, c->chol[a]);
+        else
+            hipLaunchKernelGGL(iga::chol_band_kernel<3>, dim3(1), dim3(256), 0, c->stream,
+                               (const double*)c->t[a].gm, N, ilo, ihi, c->chol[a]);
+        IGA_HIP(hipGetLastError());
+    }
+    return IGA_OK;
+}
+
+// x = (M_z (x) M_y (x) M_x)^{-1} b: the x family from b into x, then y and z in place.
+int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s)
+{
+    const long long Nx = c->N[0], Ny = c->N[1], Nz = c->N[2];
+    const long long inner[3] = {1, Nx, Nx * Ny};
+    const long long lines[3] = {Ny * Nz, Nx * Nz, Nx * Ny};
+    for (int a = 0; a < c->dim; ++a) {
+        const double* src = a == 0 ? b : x;
+        const unsigned grid = (unsigned)((lines[a] + iga::kAdsBlock - 1) / iga::kAdsBlock);
+        if (c->p == 2)
+            hipLaunchKernelGGL(iga::ads_sweep_kernel<2>, dim3(grid), dim3(iga::kAdsBlock), 0, s,
+                               (const double*)c->chol[a], c->N[a], lines[a], inner[a], src, x);
+        else
+            hipLaunchKernelGGL(iga::ads_sweep_kernel<3>, dim3(grid), dim3(iga::kAdsBlock), 0, s,
+                               (const double*)c->chol[a], c->N[a], lines[a], inner[a], src, x);
+        IGA_HIP(hipGetLastError());
+    }
+    return IGA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* iga_strerror(int code)
@@ -697,6 +746,7 @@ const char* iga_strerror(int code)
     case IGA_E_NOMEM: return "out of device memory or over the memory budget";
     case IGA_E_DEVICE: return "HIP runtime error";
     case IGA_E_AGAIN: return "queue full, try again";
+    case IGA_E_SINGULAR: return "singular system: Petrov-Galerkin spans of whole elements";
     default: return "unknown error";
     }
 }
@@ -1018,6 +1068,43 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
         c->g_n = nsteps;
     }
     IGA_HIP(hipGraphLaunch(c->gexec, c->stream));
+    return IGA_OK;
+}
+
+int iga_solve(iga_ctx* c, int32_t form, const double* b, double* x)
+{
+    if (!c || !b || !x || !valid_form(form)) return IGA_E_INVAL;
+    if (form == IGA_PG) return IGA_E_SINGULAR;
+    IGA_TRY(ensure_factors(c));
+    return launch_solve(c, b, x, c->stream);
+}
+
+int iga_galerkin_step(iga_ctx* c, int32_t form, double* u, double dt, const iga_source* f,
+                      int32_t nsteps)
+{
+    if (!c || !u || nsteps < 0 || !std::isfinite(dt) || !valid_form(form)) return IGA_E_INVAL;
+    if (form == IGA_PG) return IGA_E_SINGULAR;
+    const double amp = f ? f->sin_amp : 0.0;
+    const double* table = f ? f->table : nullptr;
+    if (!std::isfinite(amp)) return IGA_E_INVAL;
+    if (nsteps == 0) return IGA_OK;
+    IGA_TRY(scratch(c, &c->work, &c->work_n, prod3(c->N)));
+    IGA_TRY(ensure_factors(c));
+    ApplyArgs g = make_args(c, form, false, amp != 0.0);
+    g.alpha = 1.0;
+    g.beta = dt;
+    g.gsep = dt * amp;
+    g.garr = dt;
+    if (table) {
+        IGA_TRY(source_rows(c, form, table, c->stream));
+        g.farr = c->farr;
+    }
+    g.u = u;
+    g.out = c->work;
+    for (int k = 0; k < nsteps; ++k) {   // b = int B (u + dt Lap u + dt f), then u = M^{-1} b
+        IGA_TRY(launch_apply(c, g, c->stream, amp != 0.0));
+        IGA_TRY(launch_solve(c, c->work, u, c->stream));
+    }
     return IGA_OK;
 }
 

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiga.so")
 
 IGA_OK, IGA_E_INVAL, IGA_E_UNSUPPORTED, IGA_E_NOMEM, IGA_E_DEVICE, IGA_E_AGAIN = 0, -1, -2, -3, -4, -5
+IGA_E_SINGULAR = -6
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM = 0, 1, 2
@@ -70,6 +71,9 @@ _SIGS = {
                 C.POINTER(Source), C.c_void_p],
     "iga_apply": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "iga_explicit_step": [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Source), C.c_int32],
+    "iga_solve": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "iga_galerkin_step": [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.POINTER(Source),
+                          C.c_int32],
     "iga_strerror": [C.c_int],
     "iga_set_tile": [C.c_void_p, C.c_int32, C.c_int32],
     "iga_get_tile": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
@@ -163,6 +167,17 @@ def iga_explicit_step(h, u_ptr: int, dt: float, src: Optional[Source], nsteps: i
     _check(lib().iga_explicit_step(h, C.c_void_p(u_ptr), dt,
                                    C.byref(src) if src is not None else None, nsteps),
            "iga_explicit_step")
+
+
+def iga_solve(h, form: int, b_ptr: int, x_ptr: int) -> None:
+    _check(lib().iga_solve(h, form, C.c_void_p(b_ptr), C.c_void_p(x_ptr)), "iga_solve")
+
+
+def iga_galerkin_step(h, form: int, u_ptr: int, dt: float, src: Optional[Source],
+                      nsteps: int) -> None:
+    _check(lib().iga_galerkin_step(h, form, C.c_void_p(u_ptr), dt,
+                                   C.byref(src) if src is not None else None, nsteps),
+           "iga_galerkin_step")
 
 
 def iga_set_tile(h, key: int, value: int) -> None:
@@ -285,6 +300,18 @@ class Mesh:
     def explicit_step(self, u, dt: float, f_table=None, sin_amp: float = 0.0, nsteps: int = 1):
         """In place on u (returned)."""
         iga_explicit_step(self.h, _ptr(u), dt, self._src(f_table, sin_amp), nsteps)
+        return u
+
+    def solve(self, b, form: int = GALERKIN_LAPLACIAN, out=None):
+        """x = (M_z (x) M_y (x) M_x)^{-1} b with the Galerkin mass; out may be b."""
+        x = out if out is not None else self._new(self.coef_shape())
+        iga_solve(self.h, form, _ptr(b), _ptr(x))
+        return x
+
+    def galerkin_step(self, u, dt: float, form: int = GALERKIN_LAPLACIAN, f_table=None,
+                      sin_amp: float = 0.0, nsteps: int = 1):
+        """Consistent-mass Euler steps in place on u (returned)."""
+        iga_galerkin_step(self.h, form, _ptr(u), dt, self._src(f_table, sin_amp), nsteps)
         return u
 
     def assemble(self, form: int, op: int = OP_LAPLACE):

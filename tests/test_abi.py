@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(iga):
 
 
 def test_strerror(iga):
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert iga.strerror(code) and "unknown" not in iga.strerror(code)
     assert "unknown" in iga.strerror(-99)
 
@@ -82,3 +82,5 @@ def test_null_arguments(iga):
     assert L.iga_rhs(None, 2, None, 1.0, 0.0, 0.0, None, None) == -1
     assert L.iga_apply(None, 2, None, None, None) == -1
     assert L.iga_explicit_step(None, None, 0.1, None, 1) == -1
+    assert L.iga_solve(None, 1, None, None) == -1
+    assert L.iga_galerkin_step(None, 1, None, 0.1, None, 1) == -1
