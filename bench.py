@@ -298,6 +298,61 @@ def run_c4(args) -> dict:
             "batched_round_ms_host_inclusive": round_s * 1e3}
 
 
+def run_ads(args) -> dict:
+    """Galerkin L2 projection with the alternating-directions direct solve, at the size of
+    the paper's projection table (3D, 256^3 elements, p = 2 and 3, (p+1)^3 Gauss points):
+    right-hand side b_r = int B_r f with f = sin(pi x) sin(pi y) sin(pi z), then
+    (M_z (x) M_y (x) M_x) u = b in three families of 1D banded solves (factors computed
+    once per mesh, outside the timed region).  Also one consistent-mass Galerkin Euler step
+    of the 3D heat workload (128^3, p = 3; the step is unstable at dt = 1e-6, so only its
+    time is reported).  Every call is timed with HIP events on the mesh's stream over
+    `reps` calls after two warm-up calls.  Algorithmic HBM bytes of a solve: each of the
+    three families reads and writes every coefficient once, 48 B per coefficient."""
+    import torch
+    from paper_1910_08535_amd import iga
+
+    reps = max(1, args.ads_reps)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    out = {}
+    for p in (2, 3):
+        ne = (256, 256, 256)
+        mesh = iga.Mesh(3, p, ne, (p + 1,) * 3, stream=stream)
+        b = torch.empty(mesh.coef_shape(), dtype=torch.float64, device="cuda")
+        u = torch.empty_like(b)
+        n = b.numel()
+        t_rhs = timed(lambda: mesh.rhs(iga.GALERKIN_BYPARTS, None, 0.0, 0.0, 1.0, sin_amp=1.0, out=b))
+        t_solve = timed(lambda: mesh.solve(b, out=u))
+        out[f"projection_256_p{p}"] = {
+            "dofs": n, "us_rhs": t_rhs * 1e6, "us_solve": t_solve * 1e6,
+            "us_projection": (t_rhs + t_solve) * 1e6,
+            "dofs_per_s_solve": n / t_solve,
+            "solve_hbm_frac": 48.0 * n / t_solve / (HBM_PEAK_GBS * 1e9)}
+        mesh.close()
+        del b, u
+    mesh = iga.Mesh(3, 3, (128, 128, 128), (4, 4, 4), stream=stream)
+    u = torch.zeros(mesh.coef_shape(), dtype=torch.float64, device="cuda")
+    t_step = timed(lambda: mesh.galerkin_step(u, 1e-6, iga.GALERKIN_LAPLACIAN, sin_amp=1.0))
+    out["galerkin_step_128_p3"] = {"us_per_step": t_step * 1e6,
+                                   "GPs": 128 ** 3 * 64 / t_step}
+    mesh.close()
+    out["kernel"] = "iga::ads_seg_kernel<P> (one launch per axis)"
+    return out
+
+
 def stage_requests(reqs) -> int:
     """Puts every request's coefficients (seeded N(0,1), as the request's seed draws them)
     and, for RHS requests, its two output arrays on the device, so that the timed serving
@@ -373,6 +428,8 @@ def main():
     ap.add_argument("--no-heat3d", action="store_true", help="skip the 3D explicit-step leg")
     ap.add_argument("--c3-reps", type=int, default=5, help="100-step runs timed in the 3D leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-ads", action="store_true", help="skip the Galerkin projection/solve leg")
+    ap.add_argument("--ads-reps", type=int, default=10)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter scaling)")
@@ -387,6 +444,8 @@ def main():
     out = run_c2(args)
     if not args.no_heat3d:
         out["heat3d"] = run_c3(args)
+    if not args.no_ads:
+        out["ads"] = run_ads(args)
     if not args.no_batched:
         out["batched"] = run_c4(args)
     if not args.no_serving:

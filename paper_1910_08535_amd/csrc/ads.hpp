@@ -11,11 +11,18 @@
 
 namespace iga {
 
-// Row r of a factor table holds [L(r, r-P), ..., L(r, r-1), 1 / L(r, r)] (entries of
-// columns < 0 are 0), and P rows of zeros follow the last row so that the backward
-// substitution needs no bounds test.
-template <int P>
-constexpr int factor_row() { return P + 1; }
+typedef int iv2s __attribute__((ext_vector_type(2)));
+
+// Factor tables of one axis, P+1 doubles per row, kFactorPad rows of zeros after the
+// last row (rows past the end of a line then solve to 0 and couple to nothing, so the
+// substitutions need no bounds tests; kFactorPad covers the padding of the last segment
+// plus the band):
+//   L: [L(r, r-P), ..., L(r, r-1), 1 / L(r, r)]        (entries of columns < 0 are 0)
+//   F: [L(r, r-P) d_r, ..., L(r, r-1) d_r, d_r]         d_r = 1 / L(r, r)
+//   B: [L(r+1, r) d_r, ..., L(r+P, r) d_r, d_r]
+// With F and B the forward step is y_r = b_r d_r - sum_k F(r,k) y_{r-P+k} and the backward
+// step x_r = y_r d_r - sum_j B(r,j-1) x_{r+j}: the newest value enters one FMA only.
+constexpr int kFactorPad = 64;
 
 // ---------------------------------------------------------------------------------
 // Banded Cholesky factor of one axis (one workgroup).
@@ -96,7 +103,7 @@ __global__ __launch_bounds__(256) void chol_band_kernel(const double* __restrict
     for (size_t i = (size_t)from * FR + threadIdx.x; i < (size_t)to * FR; i += blockDim.x)
         L[i] = s_row[(i - (size_t)from * FR) % FR];
     // the zero rows after the last row
-    for (int i = threadIdx.x; i < P * FR; i += blockDim.x) L[(size_t)N * FR + i] = 0.0;
+    for (int i = threadIdx.x; i < kFactorPad * FR; i += blockDim.x) L[(size_t)N * FR + i] = 0.0;
     if (threadIdx.x == 0) {
         // the window after the copied rows: P copies of the repeated row
         for (int r = resume; r < N; ++r) {
@@ -117,6 +124,28 @@ __global__ __launch_bounds__(256) void chol_band_kernel(const double* __restrict
     }
 }
 
+// F and B from L, one thread per row (pad rows included).
+template <int P>
+__global__ void scaled_factor_kernel(const double* __restrict__ L, int N, double* __restrict__ F,
+                                     double* __restrict__ B)
+{
+    constexpr int FR = P + 1;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N + kFactorPad) return;
+    if (r >= N) {
+#pragma unroll
+        for (int k = 0; k < FR; ++k) F[(size_t)r * FR + k] = B[(size_t)r * FR + k] = 0.0;
+        return;
+    }
+    const double d = L[(size_t)r * FR + P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) F[(size_t)r * FR + k] = L[(size_t)r * FR + k] * d;
+#pragma unroll
+    for (int j = 1; j <= P; ++j) B[(size_t)r * FR + j - 1] = L[(size_t)(r + j) * FR + P - j] * d;
+    F[(size_t)r * FR + P] = d;
+    B[(size_t)r * FR + P] = d;
+}
+
 // ---------------------------------------------------------------------------------
 // One family of 1D solves: x = (L L^T)^{-1} b along every line of one axis.
 // Line t = (o, i), o in [0, lines / inner), i in [0, inner): element r (0 <= r < n) of
@@ -131,7 +160,8 @@ __global__ __launch_bounds__(256) void chol_band_kernel(const double* __restrict
 constexpr int kAdsBlock = 256;
 
 template <int P>
-__global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __restrict__ L, int n,
+__global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __restrict__ F,
+                                                              const double* __restrict__ B, int n,
                                                               long long lines, long long inner,
                                                               const double* b, double* x)
 {
@@ -142,7 +172,7 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
     const double* bl = b + o * (long long)n * inner + i;
     double* xl = x + o * (long long)n * inner + i;
 
-    // forward: y_r = (b_r - sum_k L(r, r-P+k) y_{r-P+k}) / L(r, r)
+    // forward: y_r = b_r d_r - sum_k F(r, k) y_{r-P+k}
     double yw[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) yw[k] = 0.0;
@@ -156,11 +186,10 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
         for (int u = 0; u < U; ++u) {
             const int r = r0 + u;
             if (r < n) {
-                const double* lr = L + (size_t)r * FR;
-                double s = cur[u];
+                const double* fr = F + (size_t)r * FR;
+                double y = cur[u] * fr[P];
 #pragma unroll
-                for (int k = 0; k < P; ++k) s = fma(-lr[k], yw[k], s);
-                const double y = s * lr[P];
+                for (int k = 0; k < P; ++k) y = fma(-fr[k], yw[k], y);
                 xl[(long long)r * inner] = y;
 #pragma unroll
                 for (int k = 0; k + 1 < P; ++k) yw[k] = yw[k + 1];
@@ -171,8 +200,8 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
         for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
 
-    // backward: x_r = (y_r - sum_{k=1..P} L(r+k, r) x_{r+k}) / L(r, r); the zero rows
-    // after the table make the terms beyond the line vanish
+    // backward: x_r = y_r d_r - sum_{k=1..P} B(r, k-1) x_{r+k}; the zero rows after the
+    // table make the terms beyond the line vanish
     double xw[P];   // xw[k-1] = x_{r+k}
 #pragma unroll
     for (int k = 0; k < P; ++k) xw[k] = 0.0;
@@ -185,10 +214,10 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
         for (int u = 0; u < U; ++u) {
             const int r = r0 - u;
             if (r >= 0) {
-                double s = cur[u];
+                const double* br = B + (size_t)r * FR;
+                double v = cur[u] * br[P];
 #pragma unroll
-                for (int k = P; k >= 1; --k) s = fma(-L[(size_t)(r + k) * FR + P - k], xw[k - 1], s);
-                const double v = s * L[(size_t)r * FR + P];
+                for (int k = P; k >= 1; --k) v = fma(-br[k - 1], xw[k - 1], v);
                 xl[(long long)r * inner] = v;
 #pragma unroll
                 for (int k = P - 1; k >= 1; --k) xw[k] = xw[k - 1];
@@ -197,6 +226,149 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// The same family of solves with every line held on chip, for lines of at most
+// kSegMaxWaves * kSeg rows.  A workgroup owns 64 consecutive lines (one per lane); its
+// wave w holds rows [w * kSeg, (w+1) * kSeg) of them in registers, all loaded at once at
+// the start, so memory sees one read and one write per value.  The recurrences then run
+// wave after wave: forward from wave 0 up, each wave handing the last P values of its
+// lines to the next through LDS, backward from the last wave down, each wave handing its
+// first P values down and storing its rows.  Lanes past the last line repeat the last
+// line and store nothing.
+// Addressing: a buffer resource based at the wave's first element, one 32-bit lane
+// offset, and the row stride in the scalar offset, so that no per-row address is kept
+// (the host checks that every offset fits 32 bits).  The factor rows of a wave's kSeg
+// rows are loaded with the values, lane s holding row r0 + s, and each step of the
+// recurrences takes its row from lane s with a register read: no memory latency per row.
+// ---------------------------------------------------------------------------------
+constexpr int kSeg = 48;
+constexpr int kSegMaxWaves = 16;
+static_assert(kFactorPad >= kSeg + 3, "zero rows must cover a padded segment and the band");
+
+__device__ __forceinline__ unsigned opaque_val(unsigned v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Lane l's value of v (a register move to a scalar register; l is a constant).
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int P>
+__global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double* __restrict__ F,
+                                                                     const double* __restrict__ B, int n,
+                                                                     long long lines, long long inner,
+                                                                     const double* b, double* x)
+{
+    constexpr int FR = P + 1, S = kSeg;
+    __shared__ double hand[P][64];
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const long long t0 = (long long)blockIdx.x * 64;
+    const long long t = t0 + lane;
+    const bool live = t < lines;
+    const long long tl = live ? t : lines - 1;
+    const long long o = tl / inner, i = tl - o * inner;
+    const long long o0 = t0 / inner, i0 = t0 - o0 * inner;
+    const int r0 = w * S;
+    // wave base: row r0 of line t0; lane offset in bytes; row stride in bytes
+    const long long wbase = (o0 * (long long)n + r0) * inner + i0;
+    const long long total = lines * (long long)n;
+    const unsigned voff = (unsigned)(((o - o0) * (long long)n * inner + (i - i0)) * 8);
+    const unsigned rstride = (unsigned)(inner * 8);
+    const long long left = (total - wbase) * 8;
+    const int nrec = (int)(left > 0xffffffffll ? 0xffffffffll : left);
+    const auto rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(b + wbase), (short)0, nrec, 0x00020000);
+    const auto rx = __builtin_amdgcn_make_buffer_rsrc(x + wbase, (short)0, nrec, 0x00020000);
+    const int last = n - 1 - r0;   // rows s > last of this wave lie past the end of the lines
+
+    // factor rows of this wave's segment, lane s holding row r0 + s (zero rows past n)
+    double fl[FR], bl[FR];
+    {
+        const size_t rl = (size_t)(r0 + min(lane, S - 1)) * FR;
+#pragma unroll
+        for (int k = 0; k < FR; ++k) {
+            fl[k] = F[rl + k];
+            bl[k] = B[rl + k];
+        }
+    }
+    double v[S];
+    {
+        unsigned so = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            v[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, (int)voff, (int)so, 0));
+            so = opaque_val(s + 1 <= last ? so + rstride : so);
+        }
+    }
+
+    // forward: y_r = b_r d_r - sum_k F(r, k) y_{r-P+k}
+    for (int k = 0; k < nw; ++k) {
+        if (w == k) {
+            double yw[P];
+#pragma unroll
+            for (int j = 0; j < P; ++j) yw[j] = k > 0 ? hand[j][lane] : 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {   // rows past the end meet zero factor rows: y = 0
+                double fc[FR];
+#pragma unroll
+                for (int j = 0; j <= P; ++j) fc[j] = lane_value(fl[j], s);
+                double y = v[s] * fc[P];
+#pragma unroll
+                for (int j = 0; j < P; ++j) y = fma(-fc[j], yw[j], y);
+                v[s] = y;
+#pragma unroll
+                for (int j = 0; j + 1 < P; ++j) yw[j] = yw[j + 1];
+                yw[P - 1] = y;
+            }
+#pragma unroll
+            for (int j = 0; j < P; ++j) hand[j][lane] = yw[j];
+        }
+        __syncthreads();
+    }
+    // backward: x_r = y_r d_r - sum_{j=1..P} B(r, j-1) x_{r+j}
+    for (int k = nw - 1; k >= 0; --k) {
+        if (w == k) {
+            double xw[P];   // xw[j-1] = x_{r+j}
+#pragma unroll
+            for (int j = 0; j < P; ++j) xw[j] = k < nw - 1 ? hand[j][lane] : 0.0;
+#pragma unroll
+            for (int s = S - 1; s >= 0; --s) {   // padded rows meet zero rows: x = 0
+                double bc[FR];
+#pragma unroll
+                for (int j = 0; j <= P; ++j) bc[j] = lane_value(bl[j], s);
+                double xv = v[s] * bc[P];
+#pragma unroll
+                for (int j = P; j >= 1; --j) xv = fma(-bc[j - 1], xw[j - 1], xv);
+                v[s] = xv;
+#pragma unroll
+                for (int j = P - 1; j >= 1; --j) xw[j] = xw[j - 1];
+                xw[0] = xv;
+            }
+#pragma unroll
+            for (int j = 0; j < P; ++j) hand[j][lane] = xw[j];
+            if (live) {
+                // offsets recomputed here rather than kept from the loads
+                unsigned so = 0;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    if (s <= last)
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[s]), rx, (int)voff,
+                                                              (int)so, 0);
+                    so = opaque_val(so + rstride);
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 

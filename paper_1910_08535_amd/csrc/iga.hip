@@ -697,17 +697,26 @@ int ensure_factors(iga_ctx* c)
     for (int a = 0; a < c->dim; ++a) {
         if (c->chol[a]) continue;
         const int N = c->N[a], p = c->p;
+        const size_t tab = (size_t)(N + iga::kFactorPad) * (p + 1);   // doubles per table
         void* mem = nullptr;
-        IGA_TRY(dalloc(c, &mem, (size_t)(N + p) * (p + 1) * sizeof(double)));
+        IGA_TRY(dalloc(c, &mem, 3 * tab * sizeof(double)));   // L, F, B
         c->chol[a] = (double*)mem;
+        double* F = c->chol[a] + tab;
+        double* B = F + tab;
+        const unsigned g = (unsigned)((N + iga::kFactorPad + 255) / 256);
         // rows with identical mass bands: B_i and its neighbours clear of the end knots
         const int ilo = 2 * p, ihi = c->ne[a] - 1 - p;
-        if (p == 2)
+        if (p == 2) {
             hipLaunchKernelGGL(iga::chol_band_kernel<2>, dim3(1), dim3(256), 0, c->stream,
                                (const double*)c->t[a].gm, N, ilo, ihi, c->chol[a]);
-        else
+            hipLaunchKernelGGL(iga::scaled_factor_kernel<2>, dim3(g), dim3(256), 0, c->stream,
+                               (const double*)c->chol[a], N, F, B);
+        } else {
             hipLaunchKernelGGL(iga::chol_band_kernel<3>, dim3(1), dim3(256), 0, c->stream,
                                (const double*)c->t[a].gm, N, ilo, ihi, c->chol[a]);
+            hipLaunchKernelGGL(iga::scaled_factor_kernel<3>, dim3(g), dim3(256), 0, c->stream,
+                               (const double*)c->chol[a], N, F, B);
+        }
         IGA_HIP(hipGetLastError());
     }
     return IGA_OK;
@@ -721,13 +730,34 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s)
     const long long lines[3] = {Ny * Nz, Nx * Nz, Nx * Ny};
     for (int a = 0; a < c->dim; ++a) {
         const double* src = a == 0 ? b : x;
+        const int n = c->N[a];
+        const size_t tab = (size_t)(n + iga::kFactorPad) * (c->p + 1);
+        const double* F = c->chol[a] + tab;
+        const double* B = F + tab;
+        // the segment kernel addresses a wave's values with 32-bit offsets from the
+        // element of its first lane: at most (dO n + 1) inner + (kSeg - 1) inner
+        // elements away, dO the number of line groups its 64 lanes cross
+        const long long dO = std::min(lines[a] / inner[a] - 1, (63 + inner[a] - 1) / inner[a]);
+        const long long span = (dO * n + 1) * inner[a] + (long long)(iga::kSeg - 1) * inner[a];
+        if (n <= iga::kSeg * iga::kSegMaxWaves && span * 8 < 0xffffffffLL) {   // lines on chip
+            const unsigned grid = (unsigned)((lines[a] + 63) / 64);
+            const unsigned threads = 64u * (unsigned)((n + iga::kSeg - 1) / iga::kSeg);
+            if (c->p == 2)
+                hipLaunchKernelGGL(iga::ads_seg_kernel<2>, dim3(grid), dim3(threads), 0, s, F, B, n,
+                                   lines[a], inner[a], src, x);
+            else
+                hipLaunchKernelGGL(iga::ads_seg_kernel<3>, dim3(grid), dim3(threads), 0, s, F, B, n,
+                                   lines[a], inner[a], src, x);
+            IGA_HIP(hipGetLastError());
+            continue;
+        }
         const unsigned grid = (unsigned)((lines[a] + iga::kAdsBlock - 1) / iga::kAdsBlock);
         if (c->p == 2)
-            hipLaunchKernelGGL(iga::ads_sweep_kernel<2>, dim3(grid), dim3(iga::kAdsBlock), 0, s,
-                               (const double*)c->chol[a], c->N[a], lines[a], inner[a], src, x);
+            hipLaunchKernelGGL(iga::ads_sweep_kernel<2>, dim3(grid), dim3(iga::kAdsBlock), 0, s, F, B,
+                               n, lines[a], inner[a], src, x);
         else
-            hipLaunchKernelGGL(iga::ads_sweep_kernel<3>, dim3(grid), dim3(iga::kAdsBlock), 0, s,
-                               (const double*)c->chol[a], c->N[a], lines[a], inner[a], src, x);
+            hipLaunchKernelGGL(iga::ads_sweep_kernel<3>, dim3(grid), dim3(iga::kAdsBlock), 0, s, F, B,
+                               n, lines[a], inner[a], src, x);
         IGA_HIP(hipGetLastError());
     }
     return IGA_OK;
