@@ -12,6 +12,8 @@
 namespace iga {
 
 typedef int iv2s __attribute__((ext_vector_type(2)));
+typedef int iv4s __attribute__((ext_vector_type(4)));
+typedef double dv2s __attribute__((ext_vector_type(2)));
 
 // Factor tables of one axis, P+1 doubles per row, kFactorPad rows of zeros after the
 // last row (rows past the end of a line then solve to 0 and couple to nothing, so the
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
 // rows are loaded with the values, lane s holding row r0 + s, and each step of the
 // recurrences takes its row from lane s with a register read: no memory latency per row.
 // ---------------------------------------------------------------------------------
-constexpr int kSeg = 48;
+constexpr int kSeg = 48;   // even: the contiguous variant reads rows in pairs
 constexpr int kSegMaxWaves = 16;
 static_assert(kFactorPad >= kSeg + 3, "zero rows must cover a padded segment and the band");
 
@@ -263,7 +265,7 @@ __device__ __forceinline__ double lane_value(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-template <int P>
+template <int P, bool CONTIG>
 __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double* __restrict__ F,
                                                                      const double* __restrict__ B, int n,
                                                                      long long lines, long long inner,
@@ -302,7 +304,24 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
         }
     }
     double v[S];
-    {
+    if constexpr (CONTIG) {
+        // x-lines (inner = 1): a lane's rows are contiguous, read as 16-byte pairs (a single
+        // value at an odd end; nothing past the end of the line)
+#pragma unroll
+        for (int q = 0; q < S / 2; ++q) {
+            if (2 * q + 1 <= last) {
+                const auto pr = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)(voff + 16u * q), 0, 0);
+                const dv2s d = __builtin_bit_cast(dv2s, pr);
+                v[2 * q] = d.x;
+                v[2 * q + 1] = d.y;
+            } else {
+                v[2 * q] = 2 * q <= last ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                                        rb, (int)(voff + 16u * q), 0, 0))
+                                         : 0.0;
+                v[2 * q + 1] = 0.0;
+            }
+        }
+    } else {
         unsigned so = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -310,6 +329,10 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
             so = opaque_val(s + 1 <= last ? so + rstride : so);
         }
     }
+    // rows past the end of the lines start from 0 (their factor rows are 0 too), whatever
+    // was read for them
+#pragma unroll
+    for (int s = 0; s < S; ++s) v[s] = s <= last ? v[s] : 0.0;
 
     // forward: y_r = b_r d_r - sum_k F(r, k) y_{r-P+k}
     for (int k = 0; k < nw; ++k) {
@@ -357,14 +380,30 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
 #pragma unroll
             for (int j = 0; j < P; ++j) hand[j][lane] = xw[j];
             if (live) {
-                // offsets recomputed here rather than kept from the loads
-                unsigned so = 0;
+                if constexpr (CONTIG) {
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    if (s <= last)
-                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[s]), rx, (int)voff,
-                                                              (int)so, 0);
-                    so = opaque_val(so + rstride);
+                    for (int q = 0; q < S / 2; ++q) {
+                        if (2 * q + 1 <= last) {
+                            dv2s d;
+                            d.x = v[2 * q];
+                            d.y = v[2 * q + 1];
+                            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4s, d), rx,
+                                                                   (int)(voff + 16u * q), 0, 0);
+                        } else if (2 * q <= last) {
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[2 * q]), rx,
+                                                                  (int)(voff + 16u * q), 0, 0);
+                        }
+                    }
+                } else {
+                    // offsets recomputed here rather than kept from the loads
+                    unsigned so = 0;
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        if (s <= last)
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[s]), rx,
+                                                                  (int)voff, (int)so, 0);
+                        so = opaque_val(so + rstride);
+                    }
                 }
             }
         }

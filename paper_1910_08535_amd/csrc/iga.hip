@@ -743,11 +743,19 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s)
             const unsigned grid = (unsigned)((lines[a] + 63) / 64);
             const unsigned threads = 64u * (unsigned)((n + iga::kSeg - 1) / iga::kSeg);
             if (c->p == 2)
-                hipLaunchKernelGGL(iga::ads_seg_kernel<2>, dim3(grid), dim3(threads), 0, s, F, B, n,
-                                   lines[a], inner[a], src, x);
+                if (a == 0)
+                    hipLaunchKernelGGL((iga::ads_seg_kernel<2, true>), dim3(grid), dim3(threads), 0, s, F,
+                                       B, n, lines[a], inner[a], src, x);
+                else
+                    hipLaunchKernelGGL((iga::ads_seg_kernel<2, false>), dim3(grid), dim3(threads), 0, s, F,
+                                       B, n, lines[a], inner[a], src, x);
             else
-                hipLaunchKernelGGL(iga::ads_seg_kernel<3>, dim3(grid), dim3(threads), 0, s, F, B, n,
-                                   lines[a], inner[a], src, x);
+                if (a == 0)
+                    hipLaunchKernelGGL((iga::ads_seg_kernel<3, true>), dim3(grid), dim3(threads), 0, s, F,
+                                       B, n, lines[a], inner[a], src, x);
+                else
+                    hipLaunchKernelGGL((iga::ads_seg_kernel<3, false>), dim3(grid), dim3(threads), 0, s, F,
+                                       B, n, lines[a], inner[a], src, x);
             IGA_HIP(hipGetLastError());
             continue;
         }
