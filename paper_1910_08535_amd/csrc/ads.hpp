@@ -126,6 +126,15 @@ __global__ __launch_bounds__(256) void chol_band_kernel(const double* __restrict
     }
 }
 
+// Lane l's value of v (a register move to a scalar register; l is a constant).
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // F and B from L, one thread per row (pad rows included).
 template <int P>
 __global__ void scaled_factor_kernel(const double* __restrict__ L, int N, double* __restrict__ F,
@@ -154,12 +163,15 @@ __global__ void scaled_factor_kernel(const double* __restrict__ L, int N, double
 // the line sits at o * n * inner + r * inner + i.  So inner = 1 walks x-lines (rows of
 // the array), inner = N_x walks y-lines and inner = N_x N_y walks z-lines; consecutive
 // threads take consecutive i, which makes the y and z families' accesses coalesced.
-// One thread per line: the forward substitution writes y over x, the backward one
-// reads it back in reverse.  Each direction keeps the next U values of its line in
-// flight (double-buffered), so that the recurrence waits on memory once per block.
+// One thread per line (one wave per workgroup): the forward substitution writes y over
+// x, the backward one reads it back in reverse.  Each direction keeps the next U = 64
+// values of its line in flight (double-buffered), and the factor rows of those 64 rows
+// one per lane (read with register moves), so that the recurrence waits on memory once
+// per 64 rows: this path serves lines too long to stay on chip, and there are few of
+// them.  Lanes past the last line repeat it and store nothing.
 // x may equal b.  L rows are uniform across a wave (scalar loads).
 // ---------------------------------------------------------------------------------
-constexpr int kAdsBlock = 256;
+constexpr int kAdsBlock = 64;   // few lines take this path: one wave per CU
 
 template <int P>
 __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __restrict__ F,
@@ -167,10 +179,13 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
                                                               long long lines, long long inner,
                                                               const double* b, double* x)
 {
-    constexpr int FR = P + 1, U = 16;
-    const long long t = (long long)blockIdx.x * kAdsBlock + threadIdx.x;
-    if (t >= lines) return;
-    const long long o = t / inner, i = t - o * inner;
+    constexpr int FR = P + 1, U = 64;
+    static_assert(U == 64, "lane u holds the factor row of step u of a block");
+    const int lane = threadIdx.x;
+    const long long t = (long long)blockIdx.x * kAdsBlock + lane;
+    const bool live = t < lines;
+    const long long tl = live ? t : lines - 1;
+    const long long o = tl / inner, i = tl - o * inner;
     const double* bl = b + o * (long long)n * inner + i;
     double* xl = x + o * (long long)n * inner + i;
 
@@ -178,21 +193,27 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
     double yw[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) yw[k] = 0.0;
-    double cur[U], nxt[U];
+    double cur[U], nxt[U], fc[FR], fn[FR];
 #pragma unroll
     for (int u = 0; u < U; ++u) cur[u] = bl[(long long)min(u, n - 1) * inner];
+#pragma unroll
+    for (int k = 0; k < FR; ++k) fc[k] = F[(size_t)min(lane, n - 1) * FR + k];
     for (int r0 = 0; r0 < n; r0 += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) nxt[u] = bl[(long long)min(r0 + U + u, n - 1) * inner];
 #pragma unroll
+        for (int k = 0; k < FR; ++k) fn[k] = F[(size_t)min(r0 + U + lane, n - 1) * FR + k];
+#pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = r0 + u;
             if (r < n) {
-                const double* fr = F + (size_t)r * FR;
-                double y = cur[u] * fr[P];
+                double f[FR];
 #pragma unroll
-                for (int k = 0; k < P; ++k) y = fma(-fr[k], yw[k], y);
-                xl[(long long)r * inner] = y;
+                for (int k = 0; k < FR; ++k) f[k] = lane_value(fc[k], u);
+                double y = cur[u] * f[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) y = fma(-f[k], yw[k], y);
+                if (live) xl[(long long)r * inner] = y;
 #pragma unroll
                 for (int k = 0; k + 1 < P; ++k) yw[k] = yw[k + 1];
                 yw[P - 1] = y;
@@ -200,6 +221,8 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+#pragma unroll
+        for (int k = 0; k < FR; ++k) fc[k] = fn[k];
     }
 
     // backward: x_r = y_r d_r - sum_{k=1..P} B(r, k-1) x_{r+k}; the zero rows after the
@@ -209,18 +232,24 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
     for (int k = 0; k < P; ++k) xw[k] = 0.0;
 #pragma unroll
     for (int u = 0; u < U; ++u) cur[u] = xl[(long long)max(n - 1 - u, 0) * inner];
+#pragma unroll
+    for (int k = 0; k < FR; ++k) fc[k] = B[(size_t)max(n - 1 - lane, 0) * FR + k];
     for (int r0 = n - 1; r0 >= 0; r0 -= U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) nxt[u] = xl[(long long)max(r0 - U - u, 0) * inner];
 #pragma unroll
+        for (int k = 0; k < FR; ++k) fn[k] = B[(size_t)max(r0 - U - lane, 0) * FR + k];
+#pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = r0 - u;
             if (r >= 0) {
-                const double* br = B + (size_t)r * FR;
-                double v = cur[u] * br[P];
+                double f[FR];
 #pragma unroll
-                for (int k = P; k >= 1; --k) v = fma(-br[k - 1], xw[k - 1], v);
-                xl[(long long)r * inner] = v;
+                for (int k = 0; k < FR; ++k) f[k] = lane_value(fc[k], u);
+                double v = cur[u] * f[P];
+#pragma unroll
+                for (int k = P; k >= 1; --k) v = fma(-f[k - 1], xw[k - 1], v);
+                if (live) xl[(long long)r * inner] = v;
 #pragma unroll
                 for (int k = P - 1; k >= 1; --k) xw[k] = xw[k - 1];
                 xw[0] = v;
@@ -228,6 +257,8 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+#pragma unroll
+        for (int k = 0; k < FR; ++k) fc[k] = fn[k];
     }
 }
 
@@ -256,14 +287,6 @@ __device__ __forceinline__ unsigned opaque_val(unsigned v)
     return v;
 }
 
-// Lane l's value of v (a register move to a scalar register; l is a constant).
-__device__ __forceinline__ double lane_value(double v, int l)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 template <int P, bool CONTIG>
 __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double* __restrict__ F,
