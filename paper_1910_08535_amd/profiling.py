@@ -28,6 +28,7 @@ KERNEL_SOURCES = {
     "apply2d": ("apply.hpp", "common.hpp"),
     "apply3d": ("apply3d.hpp", "apply.hpp", "common.hpp"),
     "batch2d": ("batch.hpp", "apply.hpp", "common.hpp"),
+    "ads_seg": ("ads.hpp", "common.hpp"),
 }
 
 
