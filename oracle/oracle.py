@@ -287,3 +287,90 @@ def galerkin_step(pb: Problem, u: np.ndarray, dt: float, form: int = GALERKIN_LA
         b = rhs(pb, form, v, 1.0, dt, dt, f_table, sin_amp)
         v = ads_solve(pb, b)
     return v
+
+
+def boundary_terms(pb: Problem, form: int, sides, u: Optional[np.ndarray] = None,
+                   alpha: float = 0.0, beta: float = 0.0) -> np.ndarray:
+    """Boundary rows of the problem with Neumann conditions (Section 4.3):
+
+        b_r = sum over the listed sides G of  int_G T_r (alpha du_h/dn + beta G) dS,
+
+    T_r = B_r (Galerkin forms) or the indicator of the span S_r (PG), n the outward
+    normal.  ``sides`` lists dicts {"axis": a, "hi": bool, "g_table": array or None,
+    "g_const": float}; a side's table holds G at its Gauss points, tangential axes in
+    increasing order with the first fastest (numpy shape reversed).  Evaluated point by
+    point: the side's Gauss points, the basis at each of them and at the side's
+    coordinate, and the test function's value there."""
+    dim, p = pb.dim, pb.p
+    shape = pb.shape(form)
+    out = np.zeros(shape)
+    if u is not None:
+        u = np.asarray(u, dtype=np.float64)
+        assert u.shape == pb.coef_shape()
+    for sd in sides:
+        a, hi = int(sd["axis"]), bool(sd["hi"])
+        xs = pb.hi[a] if hi else pb.lo[a]
+        nrm = 1.0 if hi else -1.0
+        Ba = basis_eval(p, pb.ne[a], xs, pb.lo[a], pb.hi[a], nder=1)
+        # normal factor of each row: PG = does the span reach the side; Galerkin = B_r(side)
+        if form == PG:
+            f, l = pb._spans[a]
+            wa = ((l == pb.ne[a] - 1) if hi else (f == 0)).astype(np.float64)
+        else:
+            wa = Ba[0].copy()
+        tang = [b for b in range(dim) if b != a]
+        # Gauss points of the side, per tangential axis: weights, elements, basis values
+        Tb, Bb = [], []
+        for b in tang:
+            xi, w = gauss_legendre(pb.nq[b])
+            hb = (pb.hi[b] - pb.lo[b]) / pb.ne[b]
+            e = np.repeat(np.arange(pb.ne[b]), pb.nq[b])
+            xq = pb.lo[b] + hb * (e + (np.tile(xi, pb.ne[b]) + 1.0) / 2.0)
+            wq = np.tile(w, pb.ne[b]) * hb / 2.0
+            vals = np.stack([basis_eval(p, pb.ne[b], x, pb.lo[b], pb.hi[b], nder=0)[0] for x in xq])
+            Bb.append(vals)                                     # (points, N_b)
+            if form == PG:
+                fb, lb = pb._spans[b]
+                ind = (e[None, :] >= fb[:, None]) & (e[None, :] <= lb[:, None])
+                Tb.append(ind * wq[None, :])                    # (R_b, points)
+            else:
+                Tb.append(vals.T * wq[None, :])                 # (N_b, points)
+        # integrand at the side's points (numpy order: tangential axes reversed)
+        val = np.zeros(tuple(len(B) for B in reversed(Bb)))
+        if u is not None and alpha != 0.0:
+            dn = np.moveaxis(u, dim - 1 - a, 0)
+            dn = nrm * np.tensordot(Ba[1], dn, axes=(0, 0))     # tangential coefficients
+            for k, B in enumerate(reversed(Bb)):                # numpy axis k <-> tang[-1-k]
+                dn = np.moveaxis(np.tensordot(B, dn, axes=(1, k)), 0, k)
+            val = val + alpha * dn
+        if beta != 0.0:
+            g = np.full(val.shape, float(sd.get("g_const", 0.0)))
+            if sd.get("g_table") is not None:
+                g = g + np.asarray(sd["g_table"], dtype=np.float64).reshape(val.shape)
+            val = val + beta * g
+        rows = val
+        for k, T in enumerate(reversed(Tb)):
+            rows = np.moveaxis(np.tensordot(T, rows, axes=(1, k)), 0, k)
+        full = np.multiply.outer(wa, rows)                      # normal axis first
+        out += np.moveaxis(full, 0, dim - 1 - a)
+    return out
+
+
+def dirichlet_rows(pb: Problem, side_mask: int, rows: np.ndarray,
+                   u: Optional[np.ndarray] = None) -> np.ndarray:
+    """Row replacement for zero Dirichlet conditions (Section 4.3): the rows of the
+    B-splines that do not vanish on a listed side (bit 2a: lower end of axis a, bit
+    2a+1: upper end; B_0 and B_{N-1} of that axis under open knots) become identity
+    rows, so rows[r] = u_r (operator applied to u), or 0 without u (right-hand side).
+    Square systems only (rows indexed like the coefficients)."""
+    out = np.array(rows, dtype=np.float64, copy=True)
+    assert out.shape == pb.coef_shape()
+    src = np.zeros_like(out) if u is None else np.asarray(u, dtype=np.float64)
+    for a in range(pb.dim):
+        ax = pb.dim - 1 - a
+        for hi in (0, 1):
+            if side_mask & (1 << (2 * a + hi)):
+                idx = [slice(None)] * pb.dim
+                idx[ax] = -1 if hi else 0
+                out[tuple(idx)] = src[tuple(idx)]
+    return out
