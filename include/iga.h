@@ -193,6 +193,38 @@ int iga_solve(iga_ctx *ctx, int32_t form, const double *b, double *x);
 int iga_galerkin_step(iga_ctx *ctx, int32_t form, double *u, double dt, const iga_source *f,
                       int32_t nsteps);
 
+/* A side of the domain for boundary conditions: side = 2a is the lower end of axis a,
+   2a + 1 its upper end.  The Neumann datum G on the side is g_const plus, when g_table
+   is given (device), one value per Gauss point of the side: the side's elements and
+   Gauss points along its tangential axes, taken in increasing axis order with the first
+   fastest (1D: one value). */
+typedef struct {
+    int32_t side;
+    const double *g_table;
+    double g_const;
+} iga_side;
+
+/* Boundary terms of the Laplace problem with mixed conditions (Section 4.3): after the
+   Laplacian is integrated back by parts, a Neumann side G carries
+     b_r += alpha int_G T_r du_h/dn dS + beta int_G T_r G dS
+   with T_r = B_r (Galerkin forms) or the indicator of the span S_r (PG), n the outward
+   normal, for every listed side, added to b (device rows, as written by iga_rhs).
+   With the Laplacian form the system of the problem -Lap u = f, du/dn = G on the
+   Neumann sides reads  -iga_apply(lap) + (alpha = 1 term) = iga_rhs(f) + (beta = 1 term)
+   (the by-parts form already carries the boundary integral of every side).
+   sides: host array of nsides entries; u: device coefficients (needed when alpha != 0);
+   b must not alias u or a table.  Errors: IGA_E_INVAL. */
+int iga_boundary_terms(iga_ctx *ctx, int32_t form, int32_t nsides, const iga_side *sides,
+                       const double *u, double alpha, double beta, double *b);
+
+/* Zero Dirichlet conditions by row replacement (Section 4.3): the rows of the B-splines
+   that do not vanish on a listed side (bit 2a of side_mask: lower end of axis a, bit
+   2a + 1: upper end; under open knots B_0 and B_{N-1} of that axis) become identity rows:
+   rows[r] = u[r] (the operator applied to u), or 0 when u is NULL (the right-hand side).
+   Square systems only: Galerkin forms, or PG with support spans.
+   Errors: IGA_E_INVAL. */
+int iga_dirichlet_rows(iga_ctx *ctx, int32_t form, int32_t side_mask, const double *u, double *rows);
+
 /* Tile configuration of the context's kernels (what the autotuner varies).  A setting
    fixes the order of every sum, so results are reproducible for a given setting; other
    settings differ from it by round-off only.  Keys:

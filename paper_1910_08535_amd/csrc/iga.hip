@@ -16,6 +16,7 @@
 #include "iga.h"
 
 #include "ads.hpp"
+#include "boundary.hpp"
 #include "apply.hpp"
 #include "apply3d.hpp"
 #include "common.hpp"
@@ -1143,6 +1144,108 @@ int iga_galerkin_step(iga_ctx* c, int32_t form, double* u, double dt, const iga_
         IGA_TRY(launch_apply(c, g, c->stream, amp != 0.0));
         IGA_TRY(launch_solve(c, c->work, u, c->stream));
     }
+    return IGA_OK;
+}
+
+int iga_boundary_terms(iga_ctx* c, int32_t form, int32_t nsides, const iga_side* sides, const double* u,
+                       double alpha, double beta, double* b)
+{
+    if (!c || !b || !valid_form(form) || nsides < 0 || (nsides > 0 && !sides)) return IGA_E_INVAL;
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return IGA_E_INVAL;
+    if (alpha != 0.0 && !u) return IGA_E_INVAL;
+    if (u && (const double*)b == u) return IGA_E_INVAL;
+    for (int i = 0; i < nsides; ++i) {
+        if (sides[i].side < 0 || sides[i].side >= 2 * c->dim) return IGA_E_INVAL;
+        if (!std::isfinite(sides[i].g_const)) return IGA_E_INVAL;
+        if (sides[i].g_table && sides[i].g_table == (const double*)b) return IGA_E_INVAL;
+    }
+    const bool pg = form == IGA_PG;
+    for (int i = 0; i < nsides; ++i) {
+        iga::SideArgs sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.dim = c->dim;
+        sa.a = sides[i].side / 2;
+        sa.hi = sides[i].side & 1;
+        sa.p = c->p;
+        sa.pg = pg ? 1 : 0;
+        for (int k = 0; k < 3; ++k) {
+            sa.N[k] = k < c->dim ? c->N[k] : 1;
+            sa.R[k] = k < c->dim ? rows_of(c, form, k) : 1;
+        }
+        const AxisTables& ta = c->t[sa.a];
+        sa.ne_a = ta.ne;
+        sa.inv_h_a = (double)ta.ne / (ta.hi - ta.lo);
+        sa.first_a = ta.first;
+        sa.last_a = ta.last;
+        for (int k = 0; k < 2; ++k) {   // unused tangential slots: unit tables
+            iga::SrcAxis& x = sa.src[k];
+            x.ne = x.nq = x.np1 = x.R = 1;
+            x.gw = x.cls = c->unit;
+            x.first = x.last = c->zero;
+            sa.M[k] = c->unit;
+        }
+        for (int b2 = 0; b2 < c->dim; ++b2) {
+            if (b2 == sa.a) continue;
+            const int k = sa.nt++;
+            sa.tb[k] = b2;
+            const AxisTables& t = c->t[b2];
+            sa.M[k] = pg ? t.pm : t.gm;
+            iga::SrcAxis& x = sa.src[k];
+            x.ne = t.ne;
+            x.nq = t.nq;
+            x.np1 = t.p + 1;
+            x.p = t.p;
+            x.R = pg ? t.R : t.N;
+            x.gw = t.gw;
+            x.cls = t.cls;
+            x.first = t.first;
+            x.last = t.last;
+        }
+        // normal rows whose test function can reach the side
+        const int e = sa.hi ? ta.ne - 1 : 0;
+        if (!pg) {
+            sa.rlo = e;
+            sa.rhi = e + c->p;
+        } else if (c->spans == IGA_SPANS_SUPPORT) {
+            sa.rlo = sa.hi ? ta.ne - 1 : 0;
+            sa.rhi = sa.hi ? ta.R - 1 : c->p;
+        } else if (c->spans == IGA_SPANS_ELEMENT) {
+            sa.rlo = sa.rhi = e;
+        } else {
+            sa.rlo = 0;
+            sa.rhi = ta.R - 1;
+        }
+        sa.u = u;
+        sa.g = sides[i].g_table;
+        sa.g_const = sides[i].g_const;
+        sa.alpha = alpha;
+        sa.beta = beta;
+        sa.b = b;
+        long long n = 1;
+        for (int k = 0; k < sa.nt; ++k) n *= sa.R[sa.tb[k]];
+        hipLaunchKernelGGL(iga::boundary_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, sa);
+        IGA_HIP(hipGetLastError());
+    }
+    return IGA_OK;
+}
+
+int iga_dirichlet_rows(iga_ctx* c, int32_t form, int32_t side_mask, const double* u, double* rows)
+{
+    if (!c || !rows || !valid_form(form)) return IGA_E_INVAL;
+    if (side_mask < 0 || side_mask >= (1 << (2 * c->dim))) return IGA_E_INVAL;
+    for (int a = 0; a < c->dim; ++a)
+        if (rows_of(c, form, a) != c->N[a]) return IGA_E_INVAL;   // square systems only
+    const int3 N = make_int3(c->N[0], c->dim > 1 ? c->N[1] : 1, c->dim > 2 ? c->N[2] : 1);
+    for (int a = 0; a < c->dim; ++a)
+        for (int hi = 0; hi < 2; ++hi) {
+            if (!(side_mask & (1 << (2 * a + hi)))) continue;
+            long long n = 1;
+            for (int k = 0; k < c->dim; ++k)
+                if (k != a) n *= c->N[k];
+            hipLaunchKernelGGL(iga::dirichlet_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                               a, hi, N, u, rows);
+            IGA_HIP(hipGetLastError());
+        }
     return IGA_OK;
 }
 

@@ -39,6 +39,10 @@ class Source(C.Structure):
     _fields_ = [("table", C.c_void_p), ("sin_amp", C.c_double)]
 
 
+class Side(C.Structure):
+    _fields_ = [("side", C.c_int32), ("g_table", C.c_void_p), ("g_const", C.c_double)]
+
+
 class Job(C.Structure):
     _fields_ = [("p", C.c_int32), ("ne", C.c_int64 * 2), ("u", C.c_void_p),
                 ("mass_out", C.c_void_p), ("lap_out", C.c_void_p)]
@@ -72,6 +76,9 @@ _SIGS = {
     "iga_apply": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "iga_explicit_step": [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Source), C.c_int32],
     "iga_solve": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "iga_boundary_terms": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Side), C.c_void_p, C.c_double,
+                           C.c_double, C.c_void_p],
+    "iga_dirichlet_rows": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
     "iga_galerkin_step": [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.POINTER(Source),
                           C.c_int32],
     "iga_strerror": [C.c_int],
@@ -167,6 +174,17 @@ def iga_explicit_step(h, u_ptr: int, dt: float, src: Optional[Source], nsteps: i
     _check(lib().iga_explicit_step(h, C.c_void_p(u_ptr), dt,
                                    C.byref(src) if src is not None else None, nsteps),
            "iga_explicit_step")
+
+
+def iga_boundary_terms(h, form: int, sides, u_ptr: int, alpha: float, beta: float, b_ptr: int) -> None:
+    arr = (Side * max(1, len(sides)))(*sides)
+    _check(lib().iga_boundary_terms(h, form, len(sides), arr, C.c_void_p(u_ptr), alpha, beta,
+                                    C.c_void_p(b_ptr)), "iga_boundary_terms")
+
+
+def iga_dirichlet_rows(h, form: int, side_mask: int, u_ptr: int, rows_ptr: int) -> None:
+    _check(lib().iga_dirichlet_rows(h, form, side_mask, C.c_void_p(u_ptr), C.c_void_p(rows_ptr)),
+           "iga_dirichlet_rows")
 
 
 def iga_solve(h, form: int, b_ptr: int, x_ptr: int) -> None:
@@ -313,6 +331,20 @@ class Mesh:
         """Consistent-mass Euler steps in place on u (returned)."""
         iga_galerkin_step(self.h, form, _ptr(u), dt, self._src(f_table, sin_amp), nsteps)
         return u
+
+    def boundary_terms(self, form: int, sides, b, u=None, alpha: float = 0.0, beta: float = 0.0):
+        """b += sum over sides of int_side T_r (alpha du_h/dn + beta G); sides: list of
+        (side, g_table or None, g_const).  Returns b."""
+        recs = []
+        for sd, tab, c in sides:
+            recs.append(Side(int(sd), C.c_void_p(_ptr(tab)) if tab is not None else None, float(c)))
+        iga_boundary_terms(self.h, form, recs, _ptr(u) if u is not None else 0, alpha, beta, _ptr(b))
+        return b
+
+    def dirichlet_rows(self, form: int, side_mask: int, rows, u=None):
+        """Identity rows on the listed sides (rows[r] = u[r], or 0 without u).  Returns rows."""
+        iga_dirichlet_rows(self.h, form, side_mask, _ptr(u) if u is not None else 0, _ptr(rows))
+        return rows
 
     def assemble(self, form: int, op: int = OP_LAPLACE):
         """Banded factors, tensor of shape (dim, 2, Rmax, 2p+1)."""

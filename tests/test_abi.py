@@ -84,3 +84,5 @@ def test_null_arguments(iga):
     assert L.iga_explicit_step(None, None, 0.1, None, 1) == -1
     assert L.iga_solve(None, 1, None, None) == -1
     assert L.iga_galerkin_step(None, 1, None, 0.1, None, 1) == -1
+    assert L.iga_boundary_terms(None, 2, 0, None, None, 0.0, 0.0, None) == -1
+    assert L.iga_dirichlet_rows(None, 2, 1, None, None) == -1
