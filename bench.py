@@ -353,6 +353,84 @@ def run_ads(args) -> dict:
     return out
 
 
+def run_laplace(args) -> dict:
+    """The Laplace problem with mixed conditions in the PG form (quadratic C1, 3x3 Gauss,
+    unit square): -Lap u = f with f given at the Gauss points, u = 0 on x = 0 and
+    du/dn = G on the other sides (a table of Gauss-point values on x = 1, a constant on
+    y = 0, 1).  Times, per size, the right-hand side (domain rows, Neumann rows, Dirichlet
+    rows) and the operator application to u (Laplacian rows, flux rows, identity rows),
+    each sequence captured 20 times into a HIP graph and replayed (device time; the eager
+    calls, whose small launches are bound by the host's launch rate, are reported
+    beside).  HIP events on the mesh's stream.  The sizes are the largest of the paper's
+    2D Laplace table (256^2) and the headline 1024^2."""
+    import numpy as np
+    import torch
+    from paper_1910_08535_amd import iga, inputs
+
+    reps = max(1, args.ads_reps)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    out = {}
+    for n in (256, 1024):
+        mesh = iga.Mesh(2, 2, (n, n), (3, 3), stream=stream)
+        u = torch.from_numpy(inputs.normal_coefs((n, n), 2, 6)).cuda()
+        f = torch.from_numpy(inputs.uniform_table((3 * n, 3 * n), 7)).cuda()
+        g = torch.from_numpy(inputs.uniform_table((3 * n,), 8)).cuda()
+        neu = [(1, g, 0.0), (2, None, 0.5), (3, None, -0.5)]
+        b = torch.empty(mesh.shape(iga.PG), dtype=torch.float64, device="cuda")
+        au = torch.empty_like(b)
+
+        def rhs():
+            mesh.rhs(iga.PG, None, 0.0, 0.0, 1.0, f_table=f, out=b)
+            mesh.boundary_terms(iga.PG, neu, b, beta=1.0)
+            mesh.dirichlet_rows(iga.PG, 0b0001, b)
+
+        def apply():
+            mesh.apply(iga.PG, u, mass=False, out_lap=au)
+            au.neg_()
+            mesh.boundary_terms(iga.PG, neu, au, u=u, alpha=1.0)
+            mesh.dirichlet_rows(iga.PG, 0b0001, au, u=u)
+
+        t_rhs, t_apply = timed(rhs), timed(apply)
+        b_ref, au_ref = b.clone(), au.clone()
+
+        def graphed(fn, k=20):
+            # k calls captured once (scratch already sized by the calls above), replayed
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                for _ in range(k):
+                    fn()
+            graph.replay()
+            torch.cuda.synchronize()
+            e0.record(stream)
+            graph.replay()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e-3 / k
+
+        g_rhs, g_apply = graphed(rhs), graphed(apply)
+        # every replay recomputes the same rows as the eager calls
+        assert torch.equal(b, b_ref) and torch.equal(au, au_ref)
+        out[f"n{n}"] = {"dofs": (n + 2) ** 2, "us_rhs": g_rhs * 1e6, "us_apply": g_apply * 1e6,
+                        "GPs_rhs": 9 * n * n / g_rhs,
+                        "us_rhs_eager": t_rhs * 1e6, "us_apply_eager": t_apply * 1e6}
+        mesh.close()
+    return out
+
+
 def stage_requests(reqs) -> int:
     """Puts every request's coefficients (seeded N(0,1), as the request's seed draws them)
     and, for RHS requests, its two output arrays on the device, so that the timed serving
@@ -430,6 +508,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-ads", action="store_true", help="skip the Galerkin projection/solve leg")
     ap.add_argument("--ads-reps", type=int, default=10)
+    ap.add_argument("--no-laplace", action="store_true", help="skip the mixed Laplace leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter scaling)")
@@ -446,6 +525,8 @@ def main():
         out["heat3d"] = run_c3(args)
     if not args.no_ads:
         out["ads"] = run_ads(args)
+    if not args.no_laplace:
+        out["laplace2d"] = run_laplace(args)
     if not args.no_batched:
         out["batched"] = run_c4(args)
     if not args.no_serving:
