@@ -374,3 +374,105 @@ def dirichlet_rows(pb: Problem, side_mask: int, rows: np.ndarray,
                 idx[ax] = -1 if hi else 0
                 out[tuple(idx)] = src[tuple(idx)]
     return out
+
+
+# ---- refined test space (Section 2: more test elements than trial elements) ----------
+
+def refined_cells(p: int, ne: int, rho: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Row i of the refined-test-space system sums the refined test B-splines
+    Bhat_m, m in J_i = [a_i, b_i], of the open uniform knot vector with ne*rho elements:
+    T_i = sum_{m in J_i} Bhat_m is 1 on the refined elements [a_i, b_i - p] (its cell)
+    and ramps down over p refined elements on each side (none at the domain's ends).
+
+    The cells partition the axis at the midpoints of consecutive Greville abscissae
+    g_j = (t_{j+1} + ... + t_{j+p}) / p of the trial knots (element units), rounded to the
+    nearest refined element boundary: cut_i = floor((rho (G_i + G_{i+1}) + p) / (2p)),
+    G_j = p g_j, so that cell i sits at the centre of supp B_i (the reading of the
+    paper's requirement that the N selected test functions be linearly independent)."""
+    N = ne + p
+    t = np.clip(np.arange(N + p + 1) - p, 0, ne)          # trial knots, element units
+    G = np.array([int(t[j + 1:j + p + 1].sum()) for j in range(N)])
+    cuts = [0] + [(rho * (int(G[i]) + int(G[i + 1])) + p) // (2 * p) for i in range(N - 1)] + [ne * rho]
+    c = np.array(cuts, dtype=np.int64)
+    return c[:-1].copy(), c[1:] - 1 + p
+
+
+def _refined_axis(p: int, ne: int, rho: int, nq: int, lo: float, hi: float):
+    """Sub-element Gauss points of one axis with the refined test functions and the
+    trial basis (values and second derivatives) at each of them."""
+    a, b = refined_cells(p, ne, rho)
+    xi, w = gauss_legendre(nq)
+    ns = ne * rho
+    hs = (hi - lo) / ns
+    k = np.repeat(np.arange(ns), nq)
+    x = lo + hs * (k + (np.tile(xi, ns) + 1.0) / 2.0)
+    W = np.tile(w, ns) * hs / 2.0
+    N = ne + p
+    T = np.zeros((N, len(x)))
+    B = np.zeros((N, len(x)))
+    B2 = np.zeros((N, len(x)))
+    for q, xq in enumerate(x):
+        bt = basis_eval(p, ns, xq, lo, hi, nder=0)[0]          # refined test basis
+        tr = basis_eval(p, ne, xq, lo, hi, nder=2)             # trial basis
+        csum = np.concatenate([[0.0], np.cumsum(bt)])
+        T[:, q] = csum[b + 1] - csum[a]                        # sum of bt[a_i .. b_i]
+        B[:, q] = tr[0]
+        B2[:, q] = tr[2]
+    return x, W, T, B, B2
+
+
+def refined_matrix_1d(p: int, ne: int, rho: int, nq: int, kind: int, lo: float = 0.0,
+                      hi: float = 1.0) -> np.ndarray:
+    """M[i, j] = int T_i B_j (kind MAT_PG_MASS) or int T_i B_j'' (MAT_PG_LAP), with nq
+    Gauss points on every refined element."""
+    x, W, T, B, B2 = _refined_axis(p, ne, rho, nq, lo, hi)
+    trial = B if kind == MAT_PG_MASS else B2
+    return (T * W[None, :]) @ trial.T
+
+
+def refined_rhs(pb: Problem, rho: Sequence[int], u: Optional[np.ndarray], alpha: float = 0.0,
+                beta: float = 0.0, gamma: float = 0.0, sin_amp: float = 0.0) -> np.ndarray:
+    """b_r = int T_r (alpha u_h + beta Lap u_h + gamma sin_amp prod_a sin(pi x_a)) with the
+    tensor test functions T_r = prod_a T_{r_a}, evaluated at every point of the tensor
+    sub-element Gauss grid."""
+    dim = pb.dim
+    ax = [_refined_axis(pb.p, pb.ne[a], int(rho[a]), pb.nq[a], pb.lo[a], pb.hi[a]) for a in range(dim)]
+
+    def grid(mats):   # coefficient array (numpy order) -> values on the point grid
+        v = np.asarray(u, dtype=np.float64)
+        for k in range(dim):                                 # numpy axis k <-> mesh axis dim-1-k
+            v = np.moveaxis(np.tensordot(mats[dim - 1 - k].T, v, axes=(1, k)), 0, k)
+        return v
+
+    shape = tuple(len(ax[a][0]) for a in reversed(range(dim)))
+    f = np.zeros(shape)
+    if u is not None and alpha != 0.0:
+        f = f + alpha * grid([A[3] for A in ax])
+    if u is not None and beta != 0.0:
+        for t in range(dim):
+            f = f + beta * grid([ax[a][4] if a == t else ax[a][3] for a in range(dim)])
+    if gamma != 0.0 and sin_amp != 0.0:
+        s = np.ones(())
+        for a in reversed(range(dim)):
+            s = np.multiply.outer(s, np.sin(np.pi * ax[a][0]))
+        f = f + gamma * sin_amp * s
+    for k in range(dim):
+        a = dim - 1 - k
+        TW = ax[a][2] * ax[a][1][None, :]
+        f = np.moveaxis(np.tensordot(TW, f, axes=(1, k)), 0, k)
+    return f
+
+
+def refined_solve(pb: Problem, rho: Sequence[int], b: np.ndarray) -> np.ndarray:
+    """Solves (P_z (x) P_y (x) P_x) x = b with the square refined-test-space mass
+    matrices P_a = [int T_i B_j]: three families of 1D solves, x, then y, then z, each one
+    call of numpy.linalg.solve (the alternating-directions solver of Section 4.1 with the
+    Petrov-Galerkin matrices the refinement makes regular)."""
+    x = np.array(b, dtype=np.float64, copy=True)
+    for a in range(pb.dim):
+        M = refined_matrix_1d(pb.p, pb.ne[a], int(rho[a]), pb.nq[a], MAT_PG_MASS, pb.lo[a], pb.hi[a])
+        k = pb.dim - 1 - a
+        lines = np.moveaxis(x, k, 0)
+        sol = np.linalg.solve(M, lines.reshape(M.shape[0], -1))
+        x = np.moveaxis(sol.reshape(lines.shape), 0, k)
+    return np.ascontiguousarray(x)
