@@ -36,7 +36,16 @@
  *       IGA_SPANS_ELEMENT  S_e = {e} -- the single-element integrals (the rows of the
  *                          worked example of Section 2 where p+1 consecutive B-splines
  *                          sum to one);
- *       IGA_SPANS_CUSTOM   caller tables; each S_r must lie inside supp B_r.
+ *       IGA_SPANS_CUSTOM   caller tables; each S_r must lie inside supp B_r;
+ *       IGA_SPANS_REFINED  the refined test space (Section 2): every trial element of axis
+ *                          a is split into refine[a] elements, and row i sums the test
+ *                          B-splines of degree p on those refined open knots whose sum is
+ *                          1 on the row's cell and ramps over p refined elements on each
+ *                          side; the cells partition the axis at the midpoints of
+ *                          consecutive Greville abscissae (rounded to refined element
+ *                          boundaries).  The system is square (R_a = N_a) and regular, its
+ *                          rows are integrated with nq[a] Gauss points on every refined
+ *                          element, and iga_solve accepts it.
  *   - Gauss rule: nq[a] Gauss-Legendre points per element on axis a; weight times
  *     Jacobian W = w h / 2 per axis (Section 2, Section 4.1).
  *   - A source f is   sin_amp * prod_a sin(pi x_a)   plus an optional table with one
@@ -66,7 +75,9 @@ extern "C" {
 
 #define IGA_OK 0
 #define IGA_E_INVAL (-1)       /* bad argument (null pointer, size, range, span table) */
-#define IGA_E_UNSUPPORTED (-2) /* dim not in {1,2,3}, p not in {2,3}, nq not in [1,16] */
+#define IGA_E_UNSUPPORTED (-2) /* dim not in {1,2,3}, p not in {2,3}, nq not in [1,16];  */
+                               /* a Gauss-point table source or boundary terms with      */
+                               /* refined PG rows                                        */
 #define IGA_E_NOMEM (-3)       /* device allocation failed / batch over its memory budget */
 #define IGA_E_DEVICE (-4)      /* a HIP call failed */
 #define IGA_E_AGAIN (-5)       /* batch queue full: poll and submit again */
@@ -74,7 +85,7 @@ extern "C" {
 
 typedef enum { IGA_GALERKIN_BYPARTS = 0, IGA_GALERKIN_LAPLACIAN = 1, IGA_PG = 2 } iga_form;
 typedef enum { IGA_OP_MASS = 0, IGA_OP_LAPLACE = 1 } iga_op;
-typedef enum { IGA_SPANS_SUPPORT = 0, IGA_SPANS_ELEMENT = 1, IGA_SPANS_CUSTOM = 2 } iga_spans;
+typedef enum { IGA_SPANS_SUPPORT = 0, IGA_SPANS_ELEMENT = 1, IGA_SPANS_CUSTOM = 2, IGA_SPANS_REFINED = 3 } iga_spans;
 
 typedef struct {
     int32_t dim;        /* 1, 2 or 3                                                  */
@@ -91,6 +102,10 @@ typedef struct {
     int64_t nspan[3];
     const int64_t *span_first[3];
     const int64_t *span_last[3];
+    /* IGA_SPANS_REFINED only: refined elements per trial element, 1..64 per axis; the    */
+    /* cells must be non-empty and every row's columns within r-p .. r+p (refine >= 4     */
+    /* always qualifies for p = 2, 3)                                                     */
+    int32_t refine[3];
 } iga_mesh_desc;
 
 typedef struct {
@@ -178,8 +193,11 @@ int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, i
    b, x: device coefficient arrays (N_z, N_y, N_x); x may equal b (in place); b is not
    modified unless x == b.  form: IGA_GALERKIN_BYPARTS or IGA_GALERKIN_LAPLACIAN (one
    mass matrix for both).
-   Errors: IGA_E_INVAL, IGA_E_SINGULAR for IGA_PG (with spans made of whole elements the
-   PG mass matrix has rank at most prod_a ne[a] < prod_a N_a), IGA_E_NOMEM. */
+   With IGA_PG on a context with IGA_SPANS_REFINED spans the solve uses the square PG
+   mass factors [int T_i B_j] of the refined test space instead (banded LU without
+   pivoting, once per context).
+   Errors: IGA_E_INVAL, IGA_E_SINGULAR for IGA_PG with spans made of whole elements (the
+   PG mass matrix then has rank at most prod_a ne[a] < prod_a N_a), IGA_E_NOMEM. */
 int iga_solve(iga_ctx *ctx, int32_t form, const double *b, double *x);
 
 /* nsteps forward-Euler steps of u_t = Lap u + f (Section 4.2) in a Galerkin form with
@@ -187,9 +205,11 @@ int iga_solve(iga_ctx *ctx, int32_t form, const double *b, double *x);
      M u_{t+1} = int B_r (u_t + dt Lap u_t + dt f)   (Laplacian term by parts for
    IGA_GALERKIN_BYPARTS),
    the right-hand side generated as by iga_rhs and the mass system solved as by
-   iga_solve.  u: device coefficients, updated in place.  The scheme is stable only for
-   dt below 2 / lambda_max(M^{-1} K) (of order h^2).
-   Errors: IGA_E_INVAL, IGA_E_SINGULAR for IGA_PG, IGA_E_NOMEM. */
+   iga_solve.  With IGA_PG on a context with refined spans the same step is taken with
+   the refined test functions and their square mass.  u: device coefficients, updated in
+   place.  The scheme is stable only for dt below 2 / lambda_max(M^{-1} K) (of order h^2).
+   Errors: IGA_E_INVAL, IGA_E_SINGULAR for IGA_PG with spans of whole elements,
+   IGA_E_NOMEM. */
 int iga_galerkin_step(iga_ctx *ctx, int32_t form, double *u, double dt, const iga_source *f,
                       int32_t nsteps);
 

@@ -17,6 +17,7 @@
 
 #include "ads.hpp"
 #include "boundary.hpp"
+#include "refined.hpp"
 #include "apply.hpp"
 #include "apply3d.hpp"
 #include "common.hpp"
@@ -68,6 +69,10 @@ struct iga_ctx {
     size_t work_n = 0;
     // banded Cholesky factors of the Galerkin mass per axis (built at the first solve)
     double* chol[3] = {nullptr, nullptr, nullptr};
+    // refined test space: refined elements per trial element, and the sweep tables (F | B)
+    // of the LU factors of its square PG mass
+    int refine[3] = {1, 1, 1};
+    double* lu[3] = {nullptr, nullptr, nullptr};
     // cached explicit-step graph
     hipGraphExec_t gexec = nullptr;
     const double* g_u = nullptr;
@@ -186,7 +191,7 @@ ApplyArgs make_args(const iga_ctx* c, int form, bool step, bool sep_source)
             if (form == IGA_PG && c->spans == IGA_SPANS_ELEMENT) {
                 o.ilo = p;
                 o.ihi = ne - 1 - p;
-            } else if (form == IGA_PG && c->spans == IGA_SPANS_CUSTOM) {
+            } else if (form == IGA_PG && (c->spans == IGA_SPANS_CUSTOM || c->spans == IGA_SPANS_REFINED)) {
                 o.ilo = 1;
                 o.ihi = 0;
             } else {
@@ -441,8 +446,24 @@ int validate_desc(const iga_mesh_desc* d)
             return IGA_E_INVAL;
     }
     if (d->spans != IGA_SPANS_SUPPORT && d->spans != IGA_SPANS_ELEMENT &&
-        d->spans != IGA_SPANS_CUSTOM)
+        d->spans != IGA_SPANS_CUSTOM && d->spans != IGA_SPANS_REFINED)
         return IGA_E_INVAL;
+    if (d->spans == IGA_SPANS_REFINED) {
+        for (int a = 0; a < d->dim; ++a) {
+            const int rho = d->refine[a], p = d->p, ne = (int)d->ne[a];
+            if (rho < 1 || rho > 64) return IGA_E_INVAL;
+            if ((int64_t)ne * rho >= ((int64_t)1 << 31)) return IGA_E_INVAL;
+            // non-empty cells, and the support of every row's test function inside the
+            // trial elements of supp B_i (its columns then lie in i-p .. i+p)
+            for (int i = 0; i < ne + p; ++i) {
+                const long long c0 = iga::refined_cut(i, p, ne, rho), c1 = iga::refined_cut(i + 1, p, ne, rho);
+                if (c1 <= c0) return IGA_E_INVAL;
+                const long long lo = std::max<long long>(0, c0 - p);
+                const long long hi = std::min<long long>((long long)ne * rho - 1, c1 - 1 + p);
+                if (lo / rho < i - p || hi / rho > i) return IGA_E_INVAL;
+            }
+        }
+    }
     if (d->spans == IGA_SPANS_CUSTOM) {
         for (int a = 0; a < d->dim; ++a) {
             const int64_t N = d->ne[a] + d->p;
@@ -491,7 +512,9 @@ void axis_sizes(AxisTables& t, int p, int a, const iga_mesh_desc* d)
     t.W = 2 * t.p + 1;
     t.lo = d->lo[a];
     t.hi = d->hi[a];
-    t.R = d->spans == IGA_SPANS_SUPPORT ? t.N : (d->spans == IGA_SPANS_ELEMENT ? t.ne : (int)d->nspan[a]);
+    t.R = (d->spans == IGA_SPANS_SUPPORT || d->spans == IGA_SPANS_REFINED)
+              ? t.N
+              : (d->spans == IGA_SPANS_ELEMENT ? t.ne : (int)d->nspan[a]);
 }
 
 }  // namespace
@@ -723,8 +746,43 @@ int ensure_factors(iga_ctx* c)
     return IGA_OK;
 }
 
+// Sweep tables of the LU factors of the refined PG mass of every axis, once.
+int ensure_lu(iga_ctx* c)
+{
+    for (int a = 0; a < c->dim; ++a) {
+        if (c->lu[a]) continue;
+        const int N = c->N[a], p = c->p;
+        const size_t tab = (size_t)(N + iga::kFactorPad) * (p + 1);
+        void* mem = nullptr;
+        IGA_TRY(dalloc(c, &mem, 2 * tab * sizeof(double)));   // F, B
+        c->lu[a] = (double*)mem;
+        if (p == 2)
+            hipLaunchKernelGGL(iga::lu_band_kernel<2>, dim3(1), dim3(64), 0, c->stream, (const double*)c->t[a].pm,
+                               N, c->lu[a], c->lu[a] + tab);
+        else
+            hipLaunchKernelGGL(iga::lu_band_kernel<3>, dim3(1), dim3(64), 0, c->stream, (const double*)c->t[a].pm,
+                               N, c->lu[a], c->lu[a] + tab);
+        IGA_HIP(hipGetLastError());
+    }
+    return IGA_OK;
+}
+
+// Forward/backward tables of axis a: the Cholesky factors of the Galerkin mass, or the LU
+// factors of the refined PG mass.
+void sweep_tables(const iga_ctx* c, bool pg, int a, const double** F, const double** B)
+{
+    const size_t tab = (size_t)(c->N[a] + iga::kFactorPad) * (c->p + 1);
+    if (pg) {
+        *F = c->lu[a];
+        *B = c->lu[a] + tab;
+    } else {
+        *F = c->chol[a] + tab;
+        *B = *F + tab;
+    }
+}
+
 // x = (M_z (x) M_y (x) M_x)^{-1} b: the x family from b into x, then y and z in place.
-int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s)
+int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg = false)
 {
     const long long Nx = c->N[0], Ny = c->N[1], Nz = c->N[2];
     const long long inner[3] = {1, Nx, Nx * Ny};
@@ -732,9 +790,8 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s)
     for (int a = 0; a < c->dim; ++a) {
         const double* src = a == 0 ? b : x;
         const int n = c->N[a];
-        const size_t tab = (size_t)(n + iga::kFactorPad) * (c->p + 1);
-        const double* F = c->chol[a] + tab;
-        const double* B = F + tab;
+        const double *F = nullptr, *B = nullptr;
+        sweep_tables(c, pg, a, &F, &B);
         // the segment kernel addresses a wave's values with 32-bit offsets from the
         // element of its first lane: at most (dO n + 1) inner + (kSeg - 1) inner
         // elements away, dO the number of line groups its 64 lanes cross
@@ -803,6 +860,8 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
     c->W = 2 * desc->p + 1;
     c->spans = desc->spans;
     c->stream = (hipStream_t)hip_stream;
+    if (desc->spans == IGA_SPANS_REFINED)
+        for (int a = 0; a < desc->dim; ++a) c->refine[a] = desc->refine[a];
     int64_t nmax = 1;
     for (int a = 0; a < c->dim; ++a) {
         nmax = std::max<int64_t>(nmax, desc->ne[a] + desc->p);
@@ -821,7 +880,8 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
     std::memset(&set, 0, sizeof(set));
     AxisEntry* fresh[3] = {nullptr, nullptr, nullptr};
     int nbuild = 0;
-    if (rc == IGA_OK && desc->spans != IGA_SPANS_CUSTOM) {
+    const bool own = desc->spans == IGA_SPANS_CUSTOM || desc->spans == IGA_SPANS_REFINED;
+    if (rc == IGA_OK && !own) {
         for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
             bool built = false;
             rc = axis_acquire(c, a, desc, &c->shared[a], &built);
@@ -853,8 +913,15 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
             const AxisTables& t = c->t[a];
             std::vector<int> first(t.R), last(t.R);
             for (int r = 0; r < t.R; ++r) {
-                first[r] = (int)desc->span_first[a][r];
-                last[r] = (int)desc->span_last[a][r];
+                if (desc->spans == IGA_SPANS_CUSTOM) {
+                    first[r] = (int)desc->span_first[a][r];
+                    last[r] = (int)desc->span_last[a][r];
+                } else {   // refined: the trial elements under the row's test function
+                    const int rho = desc->refine[a], p = c->p;
+                    const long long c0 = iga::refined_cut(r, p, t.ne, rho), c1 = iga::refined_cut(r + 1, p, t.ne, rho);
+                    first[r] = (int)(std::max<long long>(0, c0 - p) / rho);
+                    last[r] = (int)(std::min<long long>((long long)t.ne * rho - 1, c1 - 1 + p) / rho);
+                }
             }
             // stream-ordered like the allocation; waited for, since the host vectors end here
             if (hipMemcpyAsync(t.first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -886,6 +953,9 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
                            0, c->stream, set);
         hipLaunchKernelGGL(iga::band_tables_kernel, dim3((nrmax + kBlock - 1) / kBlock, nbuild), dim3(kBlock),
                            lds, c->stream, set);
+        if (desc->spans == IGA_SPANS_REFINED)   // PG rows of the refined test space
+            hipLaunchKernelGGL(iga::refined_tables_kernel, dim3((nrmax + 63) / 64, nbuild), dim3(64), 0, c->stream,
+                               set, make_int3(c->refine[0], c->refine[1], c->refine[2]));
         if (hipGetLastError() != hipSuccess) rc = IGA_E_DEVICE;
         for (int a = 0; a < c->dim && rc == IGA_OK; ++a)
             if (fresh[a]) rc = axis_built(fresh[a], c->stream);
@@ -997,6 +1067,7 @@ int iga_rhs(iga_ctx* c, int32_t form, const double* u, double alpha, double beta
     const bool sep = amp != 0.0 && gamma != 0.0;
     if (!std::isfinite(amp)) return IGA_E_INVAL;
     if ((u && (const double*)b == u) || (tab && (const double*)b == f->table)) return IGA_E_INVAL;
+    if (tab && form == IGA_PG && c->spans == IGA_SPANS_REFINED) return IGA_E_UNSUPPORTED;
     ApplyArgs g = make_args(c, form, false, sep);
     g.u = u;
     g.out = b;
@@ -1113,7 +1184,11 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
 int iga_solve(iga_ctx* c, int32_t form, const double* b, double* x)
 {
     if (!c || !b || !x || !valid_form(form)) return IGA_E_INVAL;
-    if (form == IGA_PG) return IGA_E_SINGULAR;
+    if (form == IGA_PG) {
+        if (c->spans != IGA_SPANS_REFINED) return IGA_E_SINGULAR;
+        IGA_TRY(ensure_lu(c));
+        return launch_solve(c, b, x, c->stream, true);
+    }
     IGA_TRY(ensure_factors(c));
     return launch_solve(c, b, x, c->stream);
 }
@@ -1122,13 +1197,15 @@ int iga_galerkin_step(iga_ctx* c, int32_t form, double* u, double dt, const iga_
                       int32_t nsteps)
 {
     if (!c || !u || nsteps < 0 || !std::isfinite(dt) || !valid_form(form)) return IGA_E_INVAL;
-    if (form == IGA_PG) return IGA_E_SINGULAR;
+    const bool pg = form == IGA_PG;
+    if (pg && c->spans != IGA_SPANS_REFINED) return IGA_E_SINGULAR;
     const double amp = f ? f->sin_amp : 0.0;
     const double* table = f ? f->table : nullptr;
     if (!std::isfinite(amp)) return IGA_E_INVAL;
+    if (pg && table) return IGA_E_UNSUPPORTED;   // Gauss-point tables are on the trial grid
     if (nsteps == 0) return IGA_OK;
     IGA_TRY(scratch(c, &c->work, &c->work_n, prod3(c->N)));
-    IGA_TRY(ensure_factors(c));
+    IGA_TRY(pg ? ensure_lu(c) : ensure_factors(c));
     ApplyArgs g = make_args(c, form, false, amp != 0.0);
     g.alpha = 1.0;
     g.beta = dt;
@@ -1140,9 +1217,9 @@ int iga_galerkin_step(iga_ctx* c, int32_t form, double* u, double dt, const iga_
     }
     g.u = u;
     g.out = c->work;
-    for (int k = 0; k < nsteps; ++k) {   // b = int B (u + dt Lap u + dt f), then u = M^{-1} b
+    for (int k = 0; k < nsteps; ++k) {   // b = int T (u + dt Lap u + dt f), then u = M^{-1} b
         IGA_TRY(launch_apply(c, g, c->stream, amp != 0.0));
-        IGA_TRY(launch_solve(c, c->work, u, c->stream));
+        IGA_TRY(launch_solve(c, c->work, u, c->stream, pg));
     }
     return IGA_OK;
 }
@@ -1160,6 +1237,7 @@ int iga_boundary_terms(iga_ctx* c, int32_t form, int32_t nsides, const iga_side*
         if (sides[i].g_table && sides[i].g_table == (const double*)b) return IGA_E_INVAL;
     }
     const bool pg = form == IGA_PG;
+    if (pg && c->spans == IGA_SPANS_REFINED) return IGA_E_UNSUPPORTED;
     for (int i = 0; i < nsides; ++i) {
         iga::SideArgs sa;
         std::memset(&sa, 0, sizeof(sa));

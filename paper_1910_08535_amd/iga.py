@@ -21,7 +21,7 @@ IGA_OK, IGA_E_INVAL, IGA_E_UNSUPPORTED, IGA_E_NOMEM, IGA_E_DEVICE, IGA_E_AGAIN =
 IGA_E_SINGULAR = -6
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
-SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM = 0, 1, 2
+SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM, SPANS_REFINED = 0, 1, 2, 3
 TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_ROWS, TILE_2D_ORDER = 1, 2, 4, 5
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
@@ -32,7 +32,7 @@ class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("p", C.c_int32), ("ne", C.c_int64 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("nq", C.c_int32 * 3),
                 ("spans", C.c_int32), ("nspan", C.c_int64 * 3),
-                ("span_first", _P64 * 3), ("span_last", _P64 * 3)]
+                ("span_first", _P64 * 3), ("span_last", _P64 * 3), ("refine", C.c_int32 * 3)]
 
 
 class Source(C.Structure):
@@ -229,11 +229,12 @@ class Mesh:
     """One context: a tensor-product B-spline space with its Gauss rule and spans.
 
     ne, nq, lo, hi are per axis in (x, y, z) order.  ``spans`` is "support",
-    "element" or a list of per-axis (first, last) integer arrays (custom)."""
+    "element", "refined" (with ``refine``: refined elements per trial element, per
+    axis) or a list of per-axis (first, last) integer arrays (custom)."""
 
     def __init__(self, dim: int, p: int, ne: Sequence[int], nq: Sequence[int],
                  lo: Optional[Sequence[float]] = None, hi: Optional[Sequence[float]] = None,
-                 spans="support", stream=None):
+                 spans="support", stream=None, refine: Optional[Sequence[int]] = None):
         import numpy as np
         self.stream = stream
         d = MeshDesc()
@@ -248,7 +249,10 @@ class Mesh:
             d.lo[a] = float(lo[a]) if real else 0.0
             d.hi[a] = float(hi[a]) if real else 1.0
         if isinstance(spans, str):
-            d.spans = {"support": SPANS_SUPPORT, "element": SPANS_ELEMENT}[spans]
+            d.spans = {"support": SPANS_SUPPORT, "element": SPANS_ELEMENT, "refined": SPANS_REFINED}[spans]
+            if spans == "refined":
+                for a in range(dim):
+                    d.refine[a] = int(refine[a])
         else:
             d.spans = SPANS_CUSTOM
             for a in range(dim):

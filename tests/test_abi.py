@@ -46,6 +46,8 @@ def _desc(iga, **kw):
         d.nq[a] = kw.get("nq", (3, 3, 3))[a]
         d.lo[a], d.hi[a] = 0.0, kw.get("hi", 1.0)
     d.spans = kw.get("spans", 0)
+    for a in range(3):
+        d.refine[a] = kw.get("refine", (4, 4, 4))[a]
     return d
 
 
@@ -56,6 +58,10 @@ def _desc(iga, **kw):
     (dict(ne=(50000, 50000, 8)), -1),
     # 2D arrays and band tables must stay below 4 GiB (32-bit buffer offsets)
     (dict(ne=(23171, 23171, 1)), -1), (dict(p=3, ne=(76_700_000, 2, 1)), -1),
+    # refined test space: refinement 1..64, cells non-empty, rows inside the band
+    (dict(spans=3, refine=(0, 4, 4)), -1), (dict(spans=3, refine=(4, 65, 4)), -1),
+    (dict(spans=3, refine=(1, 4, 4)), -1), (dict(spans=3, refine=(2, 4, 4)), -1),
+    (dict(spans=3, p=3, refine=(4, 3, 4)), -1), (dict(spans=4), -1),
 ])
 def test_create_rejects_bad_descriptors(iga, kw, code):
     h = C.c_void_p()
