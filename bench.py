@@ -305,7 +305,8 @@ def run_ads(args) -> dict:
     (M_z (x) M_y (x) M_x) u = b in three families of 1D banded solves (factors computed
     once per mesh, outside the timed region).  Also one consistent-mass Galerkin Euler step
     of the 3D heat workload (128^3, p = 3; the step is unstable at dt = 1e-6, so only its
-    time is reported).  Every call is timed with HIP events on the mesh's stream over
+    time is reported), and the refined-test-space PG projection (256^3, p = 2, refine 4):
+    the sine rows and the solve with the LU factors of its square PG mass.  Every call is timed with HIP events on the mesh's stream over
     `reps` calls after two warm-up calls.  Algorithmic HBM bytes of a solve: each of the
     three families reads and writes every coefficient once, 48 B per coefficient."""
     import torch
@@ -339,6 +340,22 @@ def run_ads(args) -> dict:
         out[f"projection_256_p{p}"] = {
             "dofs": n, "us_rhs": t_rhs * 1e6, "us_solve": t_solve * 1e6,
             "us_projection": (t_rhs + t_solve) * 1e6,
+            "dofs_per_s_solve": n / t_solve,
+            "solve_hbm_frac": 48.0 * n / t_solve / (HBM_PEAK_GBS * 1e9)}
+        mesh.close()
+        del b, u
+    # the refined-test-space PG projection (refine 4, regular square system): rows of the
+    # sine source, then the solve with the LU factors of the PG mass
+    for p in (2,):
+        ne = (256, 256, 256)
+        mesh = iga.Mesh(3, p, ne, (p + 1,) * 3, stream=stream, spans="refined", refine=(4, 4, 4))
+        b = torch.empty(mesh.coef_shape(), dtype=torch.float64, device="cuda")
+        u = torch.empty_like(b)
+        n = b.numel()
+        t_rhs = timed(lambda: mesh.rhs(iga.PG, None, 0.0, 0.0, 1.0, sin_amp=1.0, out=b))
+        t_solve = timed(lambda: mesh.solve(b, form=iga.PG, out=u))
+        out[f"refined_pg_projection_256_p{p}"] = {
+            "dofs": n, "refine": 4, "us_rhs": t_rhs * 1e6, "us_solve": t_solve * 1e6,
             "dofs_per_s_solve": n / t_solve,
             "solve_hbm_frac": 48.0 * n / t_solve / (HBM_PEAK_GBS * 1e9)}
         mesh.close()
