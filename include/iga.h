@@ -254,12 +254,14 @@ int iga_dirichlet_rows(iga_ctx *ctx, int32_t form, int32_t side_mask, const doub
      IGA_TILE_3D_PLANES  output planes per 3D z-chunk: 1..32, 0 = automatic (default)
      IGA_TILE_3D_ROWS    output rows per 3D tile: even, 2..32, 0 = automatic (default;
                          fewer when the tile's footprint would not fit a workgroup)
+     IGA_TILE_3D_COLS    output columns per 3D tile: even, 8..96, 0 = automatic (default)
    Changing a setting drops the context's cached graph.
    Errors: IGA_E_INVAL (unknown key or value). */
 #define IGA_TILE_2D_ROWS 1
 #define IGA_TILE_3D_PLANES 2
 #define IGA_TILE_3D_ROWS 4
 #define IGA_TILE_2D_ORDER 5
+#define IGA_TILE_3D_COLS 6
 int iga_set_tile(iga_ctx *ctx, int32_t key, int32_t value);
 int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);
 

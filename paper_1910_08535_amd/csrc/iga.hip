@@ -89,6 +89,7 @@ struct iga_ctx {
     int order2d = 0;
     int tz3d = 0;   // 3D planes per z-chunk, 0 = automatic
     int ty3d = 0;   // 3D rows per tile, 0 = automatic
+    int tx3d = 0;   // 3D columns per tile, 0 = automatic
 };
 
 namespace {
@@ -236,7 +237,7 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     using namespace iga;
     const int P = c->p, Rx = g.ax[0].R, Ry = g.ax[1].R, Rz = g.ax[2].R;
     Plan3D pl;
-    pl.tx = std::max(1, (Rx + 32) / 66);
+    pl.tx = c->tx3d > 0 ? (Rx + c->tx3d - 1) / c->tx3d : std::max(1, (Rx + 32) / 66);
     pl.TX = (Rx + pl.tx - 1) / pl.tx;
     pl.TX += pl.TX & 1;
     pl.tx = (Rx + pl.TX - 1) / pl.TX;
@@ -1017,6 +1018,10 @@ int iga_set_tile(iga_ctx* c, int32_t key, int32_t value)
         if (value < 0 || value > 32 || (value & 1)) return IGA_E_INVAL;
         c->ty3d = value;
         break;
+    case IGA_TILE_3D_COLS:   // up to 96: a two-row tile's footprint then fits the ring slots
+        if (value != 0 && (value < 8 || value > 96 || (value & 1))) return IGA_E_INVAL;
+        c->tx3d = value;
+        break;
     default:
         return IGA_E_INVAL;
     }
@@ -1032,6 +1037,7 @@ int iga_get_tile(const iga_ctx* c, int32_t key, int32_t* value)
     case IGA_TILE_2D_ORDER: *value = c->order2d; break;
     case IGA_TILE_3D_PLANES: *value = c->tz3d; break;
     case IGA_TILE_3D_ROWS: *value = c->ty3d; break;
+    case IGA_TILE_3D_COLS: *value = c->tx3d; break;
     default: return IGA_E_INVAL;
     }
     return IGA_OK;

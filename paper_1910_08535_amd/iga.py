@@ -22,7 +22,7 @@ IGA_E_SINGULAR = -6
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM, SPANS_REFINED = 0, 1, 2, 3
-TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_ROWS, TILE_2D_ORDER = 1, 2, 4, 5
+TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_ROWS, TILE_2D_ORDER, TILE_3D_COLS = 1, 2, 4, 5, 6
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 _P64 = C.POINTER(C.c_int64)

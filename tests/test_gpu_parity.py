@@ -233,15 +233,21 @@ def test_3d_tile_settings(iga, orc, p):
     ud = cuda(u)
     rm = orc.rhs(pb, orc.PG, u, alpha=1.0)
     rl = orc.rhs(pb, orc.PG, u, beta=1.0)
-    for rows, planes in ((0, 0), (2, 1), (4, 3), (6, 32), (32, 5), (10, 7)):
+    for rows, planes, cols in ((0, 0, 0), (2, 1, 0), (4, 3, 0), (6, 32, 0), (32, 5, 0), (10, 7, 0),
+                               (0, 0, 8), (0, 0, 22), (12, 4, 44), (2, 0, 96), (0, 9, 70)):
         mesh.set_tile(iga.TILE_3D_ROWS, rows)
         mesh.set_tile(iga.TILE_3D_PLANES, planes)
+        mesh.set_tile(iga.TILE_3D_COLS, cols)
         assert mesh.get_tile(iga.TILE_3D_ROWS) == rows
+        assert mesh.get_tile(iga.TILE_3D_COLS) == cols
         m, l = mesh.apply(iga.PG, ud)
-        assert relerr(host(m), rm) <= TOL, (rows, planes)
-        assert relerr(host(l), rl) <= TOL, (rows, planes)
+        assert relerr(host(m), rm) <= TOL, (rows, planes, cols)
+        assert relerr(host(l), rl) <= TOL, (rows, planes, cols)
     with pytest.raises(iga.IGAError):
         mesh.set_tile(iga.TILE_3D_ROWS, 3)
+    for bad in (6, 98, 33):
+        with pytest.raises(iga.IGAError):
+            mesh.set_tile(iga.TILE_3D_COLS, bad)
 
 
 def test_shared_axis_tables_across_streams(iga, orc):
