@@ -52,6 +52,9 @@ CASES = [
     (2, 2, (19, 23), "support", 1),
     (3, 2, (9, 12, 7), "support", 2),
     (3, 3, (8, 6, 10), "support", 0),
+    (1, 2, (1,), "support", 1),                   # one element per axis
+    (2, 3, (1, 1), "element", 2),
+    (3, 2, (1, 3, 1), "support", 0),
 ]
 
 

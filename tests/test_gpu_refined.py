@@ -66,6 +66,8 @@ def test_refined_bands(orc, torch, iga, p, ne, rho):
     (2, 3, (21, 33), (8, 4)),
     (3, 2, (9, 12, 7), (4, 4, 6)),
     (3, 3, (8, 7, 10), (4, 5, 4)),
+    (1, 2, (1,), (4,)),                           # one trial element
+    (2, 3, (1, 3), (4, 64)),                      # the largest refinement
 ])
 def test_refined_rows(orc, torch, iga, dim, p, ne, rho):
     print(f"refined rows dim={dim} p={p} ne={ne} rho={rho}", flush=True)
@@ -94,6 +96,7 @@ def _kappa(orc, pb, rho):
     (2, 3, (30, 17), (4, 8)),
     (3, 2, (12, 9, 14), (4, 6, 4)),
     (3, 3, (10, 8, 9), (4, 4, 5)),
+    (2, 2, (1, 2), (3, 4)),                       # the smallest sizes and refinements
 ])
 def test_refined_solve(orc, torch, iga, dim, p, ne, rho):
     print(f"refined solve dim={dim} p={p} ne={ne} rho={rho}", flush=True)

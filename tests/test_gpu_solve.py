@@ -54,6 +54,11 @@ SOLVE_CASES = [
     (3, 3, (14, 19, 12), None, None),
     (3, 3, (130, 9, 7), None, None),               # repeated rows along x, 3D
     (3, 2, (6, 150, 11), None, None),              # repeated rows along y
+    (1, 2, (1,), None, None),                      # one element: N = p + 1
+    (2, 3, (1, 5), None, None),
+    (3, 2, (1, 1, 1), (0.0, 1.0, 2.0), (0.5, 3.0, 2.25)),
+    (2, 2, (800, 3), None, None),                  # x-lines longer than the on-chip limit
+    (3, 3, (1000, 20, 12), None, None),            # long x-lines beside short y and z lines
 ]
 
 
