@@ -385,6 +385,32 @@ __global__ void rows_only_kernel(ApplyArgs g, int dim, size_t nrows)
     finish_row<MODE>(g, idx, 0.0, 0.0, s, f);
 }
 
+// The same rows on a (x blocks, R_y, z groups of kRowsZ) grid: no index division per
+// row; axes beyond the dimension have one row and tables of ones.  Products in the order
+// of the kernel above, so both give the same bits.
+constexpr int kRowsZ = 8;
+
+template <int MODE>
+__global__ void rows_only_grid_kernel(ApplyArgs g)
+{
+    const AxisOp &X = g.ax[0], &Y = g.ax[1], &Z = g.ax[2];
+    const int ry = blockIdx.y;
+    const double ys = Y.S[ry], yf = Y.F[ry];
+    const int z1 = min(Z.R, (int)(blockIdx.z + 1) * kRowsZ);
+    for (int rz = blockIdx.z * kRowsZ; rz < z1; ++rz) {
+        const double zs = Z.S[rz], zf = Z.F[rz];
+        const size_t row0 = ((size_t)rz * Y.R + ry) * X.R;
+        for (int rx = blockIdx.x * blockDim.x + threadIdx.x; rx < X.R; rx += gridDim.x * blockDim.x) {
+            double s = X.S[rx], f = X.F[rx];
+            s *= ys;
+            f *= yf;
+            s *= zs;
+            f *= zf;
+            finish_row<MODE>(g, row0 + rx, 0.0, 0.0, s, f);
+        }
+    }
+}
+
 __global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__ src, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

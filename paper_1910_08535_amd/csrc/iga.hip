@@ -349,6 +349,21 @@ int launch_apply(const iga_ctx* c, const ApplyArgs& g, hipStream_t s, bool scale
 
 int launch_rows_only(const iga_ctx* c, const ApplyArgs& g, size_t n, hipStream_t s)
 {
+    const int Rx = g.ax[0].R, Ry = g.ax[1].R, Rz = g.ax[2].R;
+    // 3D: a grid over r_y and groups of kRowsZ z-rows (no index division per row; 61 -> 52 us
+    // at 258^3).  In 1D and 2D the flat kernel is faster (more groups in flight).
+    if (c->dim == 3 && Ry <= 65535 && (Rz + iga::kRowsZ - 1) / iga::kRowsZ <= 65535) {
+        // one-wave groups, at most 32 per x-line (a wave strides over the rest)
+        const dim3 grid((unsigned)std::min((Rx + 63) / 64, 32), (unsigned)Ry,
+                        (unsigned)((Rz + iga::kRowsZ - 1) / iga::kRowsZ));
+        if (g.farr)
+            hipLaunchKernelGGL(iga::rows_only_grid_kernel<iga::kOut | iga::kFarr | iga::kScaleSrc>, grid, dim3(64),
+                               0, s, g);
+        else
+            hipLaunchKernelGGL(iga::rows_only_grid_kernel<iga::kOut | iga::kScaleSrc>, grid, dim3(64), 0, s, g);
+        IGA_HIP(hipGetLastError());
+        return IGA_OK;
+    }
     const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
     if (g.farr)
         hipLaunchKernelGGL(iga::rows_only_kernel<iga::kOut | iga::kFarr | iga::kScaleSrc>, dim3(grid), dim3(kBlock), 0,
