@@ -24,7 +24,7 @@ typedef double dv2s __attribute__((ext_vector_type(2)));
 //   B: [L(r+1, r) d_r, ..., L(r+P, r) d_r, d_r]
 // With F and B the forward step is y_r = b_r d_r - sum_k F(r,k) y_{r-P+k} and the backward
 // step x_r = y_r d_r - sum_j B(r,j-1) x_{r+j}: the newest value enters one FMA only.
-constexpr int kFactorPad = 64;
+constexpr int kFactorPad = 128;
 
 // ---------------------------------------------------------------------------------
 // Banded Cholesky factor of one axis (one workgroup).
@@ -270,7 +270,10 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
 // wave after wave: forward from wave 0 up, each wave handing the last P values of its
 // lines to the next through LDS, backward from the last wave down, each wave handing its
 // first P values down and storing its rows.  Lanes past the last line repeat the last
-// line and store nothing.
+// line and store nothing.  With HALVES = 2 (lines of up to twice as many rows) a wave
+// holds two halves of 32 lines: lanes 0-31 rows [w kSeg, ...) of the first half of the
+// lines, lanes 32-63 rows [(nw + w) kSeg, ...) of the second; the recurrences then run
+// over 2 nw phases, and the factor rows held in lanes are reloaded for the other half.
 // Addressing: a buffer resource based at the wave's first element, one 32-bit lane
 // offset, and the row stride in the scalar offset, so that no per-row address is kept
 // (the host checks that every offset fits 32 bits).  The factor rows of a wave's kSeg
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
 // ---------------------------------------------------------------------------------
 constexpr int kSeg = 48;   // even: the contiguous variant reads rows in pairs
 constexpr int kSegMaxWaves = 16;
-static_assert(kFactorPad >= kSeg + 3, "zero rows must cover a padded segment and the band");
+static_assert(kFactorPad >= 2 * kSeg + 3, "zero rows must cover the padding of two halves and the band");
 
 __device__ __forceinline__ unsigned opaque_val(unsigned v)
 {
@@ -288,44 +291,51 @@ __device__ __forceinline__ unsigned opaque_val(unsigned v)
 }
 
 
-template <int P, bool CONTIG>
+template <int P, bool CONTIG, int HALVES>
 __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double* __restrict__ F,
                                                                      const double* __restrict__ B, int n,
                                                                      long long lines, long long inner,
                                                                      const double* b, double* x)
 {
-    constexpr int FR = P + 1, S = kSeg;
+    static_assert(HALVES == 1 || HALVES == 2, "one or two halves per wave");
+    constexpr int FR = P + 1, S = kSeg, LPW = 64 / HALVES;   // lines per workgroup
     __shared__ double hand[P][64];
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
-    const long long t0 = (long long)blockIdx.x * 64;
-    const long long t = t0 + lane;
+    const int h = HALVES == 2 ? lane >> 5 : 0;                                // half of the line
+    const int slot = lane % LPW;                                              // line of the group
+    const long long t0 = (long long)blockIdx.x * LPW;
+    const long long t = t0 + slot;
     const bool live = t < lines;
     const long long tl = live ? t : lines - 1;
     const long long o = tl / inner, i = tl - o * inner;
     const long long o0 = t0 / inner, i0 = t0 - o0 * inner;
-    const int r0 = w * S;
-    // wave base: row r0 of line t0; lane offset in bytes; row stride in bytes
-    const long long wbase = (o0 * (long long)n + r0) * inner + i0;
+    // rows of this lane: [r0, r0 + S); the wave's first half starts at rw
+    const int rw = w * S, r0 = (h * nw + w) * S;
+    // wave base: row rw of line t0; lane offset in bytes; row stride in bytes
+    const long long wbase = (o0 * (long long)n + rw) * inner + i0;
     const long long total = lines * (long long)n;
-    const unsigned voff = (unsigned)(((o - o0) * (long long)n * inner + (i - i0)) * 8);
+    const unsigned voff =
+        (unsigned)(((o - o0) * (long long)n * inner + (i - i0) + (long long)(r0 - rw) * inner) * 8);
     const unsigned rstride = (unsigned)(inner * 8);
     const long long left = (total - wbase) * 8;
     const int nrec = (int)(left > 0xffffffffll ? 0xffffffffll : left);
     const auto rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(b + wbase), (short)0, nrec, 0x00020000);
     const auto rx = __builtin_amdgcn_make_buffer_rsrc(x + wbase, (short)0, nrec, 0x00020000);
-    const int last = n - 1 - r0;   // rows s > last of this wave lie past the end of the lines
+    const int last = n - 1 - r0;   // rows s > last of this lane lie past the end of its line
 
-    // factor rows of this wave's segment, lane s holding row r0 + s (zero rows past n)
+    // factor rows of one half's segment of this wave, lane s holding row (half nw + w) S + s
+    // (zero rows past n)
     double fl[FR], bl[FR];
-    {
-        const size_t rl = (size_t)(r0 + min(lane, S - 1)) * FR;
+    auto load_factors = [&](int half) {
+        const size_t rl = (size_t)((half * nw + w) * S + min(lane, S - 1)) * FR;
 #pragma unroll
         for (int k = 0; k < FR; ++k) {
             fl[k] = F[rl + k];
             bl[k] = B[rl + k];
         }
-    }
+    };
+    load_factors(0);
     double v[S];
     if constexpr (CONTIG) {
         // x-lines (inner = 1): a lane's rows are contiguous, read as 16-byte pairs (a single
@@ -344,12 +354,24 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
                 v[2 * q + 1] = 0.0;
             }
         }
-    } else {
+    } else if constexpr (HALVES == 1) {
+        // the wave's rows end together: the row offset steps in a scalar register, clamped
+        // to the last row of the lines
         unsigned so = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             v[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, (int)voff, (int)so, 0));
             so = opaque_val(s + 1 <= last ? so + rstride : so);
+        }
+    } else {
+        // the halves end at different rows: a row past a lane's line is not read
+        unsigned so = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            v[s] = s <= last ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, (int)voff,
+                                                                                                   (int)so, 0))
+                             : 0.0;
+            so = opaque_val(so + rstride);
         }
     }
     // rows past the end of the lines start from 0 (their factor rows are 0 too), whatever
@@ -357,75 +379,84 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
 #pragma unroll
     for (int s = 0; s < S; ++s) v[s] = s <= last ? v[s] : 0.0;
 
-    // forward: y_r = b_r d_r - sum_k F(r, k) y_{r-P+k}
-    for (int k = 0; k < nw; ++k) {
-        if (w == k) {
-            double yw[P];
+    // forward: y_r = b_r d_r - sum_k F(r, k) y_{r-P+k}; phase k runs wave k % nw on half
+    // k / nw, handing the last P values of each line to the next phase through LDS
+    for (int k = 0; k < HALVES * nw; ++k) {
+        const int kw = k % nw, kh = k / nw;
+        if (w == kw) {
+            if (HALVES == 2 && kh == 1) load_factors(1);
+            if (h == kh) {
+                double yw[P];
 #pragma unroll
-            for (int j = 0; j < P; ++j) yw[j] = k > 0 ? hand[j][lane] : 0.0;
+                for (int j = 0; j < P; ++j) yw[j] = k > 0 ? hand[j][slot] : 0.0;
 #pragma unroll
-            for (int s = 0; s < S; ++s) {   // rows past the end meet zero factor rows: y = 0
-                double fc[FR];
+                for (int s = 0; s < S; ++s) {   // rows past the end meet zero factor rows: y = 0
+                    double fc[FR];
 #pragma unroll
-                for (int j = 0; j <= P; ++j) fc[j] = lane_value(fl[j], s);
-                double y = v[s] * fc[P];
+                    for (int j = 0; j <= P; ++j) fc[j] = lane_value(fl[j], s);
+                    double y = v[s] * fc[P];
 #pragma unroll
-                for (int j = 0; j < P; ++j) y = fma(-fc[j], yw[j], y);
-                v[s] = y;
+                    for (int j = 0; j < P; ++j) y = fma(-fc[j], yw[j], y);
+                    v[s] = y;
 #pragma unroll
-                for (int j = 0; j + 1 < P; ++j) yw[j] = yw[j + 1];
-                yw[P - 1] = y;
+                    for (int j = 0; j + 1 < P; ++j) yw[j] = yw[j + 1];
+                    yw[P - 1] = y;
+                }
+#pragma unroll
+                for (int j = 0; j < P; ++j) hand[j][slot] = yw[j];
             }
-#pragma unroll
-            for (int j = 0; j < P; ++j) hand[j][lane] = yw[j];
         }
         __syncthreads();
     }
-    // backward: x_r = y_r d_r - sum_{j=1..P} B(r, j-1) x_{r+j}
-    for (int k = nw - 1; k >= 0; --k) {
-        if (w == k) {
-            double xw[P];   // xw[j-1] = x_{r+j}
+    // backward: x_r = y_r d_r - sum_{j=1..P} B(r, j-1) x_{r+j}, phases in reverse order
+    for (int k = HALVES * nw - 1; k >= 0; --k) {
+        const int kw = k % nw, kh = k / nw;
+        if (w == kw) {
+            if (HALVES == 2 && kh == 0) load_factors(0);
+            if (h == kh) {
+                double xw[P];   // xw[j-1] = x_{r+j}
 #pragma unroll
-            for (int j = 0; j < P; ++j) xw[j] = k < nw - 1 ? hand[j][lane] : 0.0;
+                for (int j = 0; j < P; ++j) xw[j] = k < HALVES * nw - 1 ? hand[j][slot] : 0.0;
 #pragma unroll
-            for (int s = S - 1; s >= 0; --s) {   // padded rows meet zero rows: x = 0
-                double bc[FR];
+                for (int s = S - 1; s >= 0; --s) {   // padded rows meet zero rows: x = 0
+                    double bc[FR];
 #pragma unroll
-                for (int j = 0; j <= P; ++j) bc[j] = lane_value(bl[j], s);
-                double xv = v[s] * bc[P];
+                    for (int j = 0; j <= P; ++j) bc[j] = lane_value(bl[j], s);
+                    double xv = v[s] * bc[P];
 #pragma unroll
-                for (int j = P; j >= 1; --j) xv = fma(-bc[j - 1], xw[j - 1], xv);
-                v[s] = xv;
+                    for (int j = P; j >= 1; --j) xv = fma(-bc[j - 1], xw[j - 1], xv);
+                    v[s] = xv;
 #pragma unroll
-                for (int j = P - 1; j >= 1; --j) xw[j] = xw[j - 1];
-                xw[0] = xv;
-            }
+                    for (int j = P - 1; j >= 1; --j) xw[j] = xw[j - 1];
+                    xw[0] = xv;
+                }
 #pragma unroll
-            for (int j = 0; j < P; ++j) hand[j][lane] = xw[j];
-            if (live) {
-                if constexpr (CONTIG) {
+                for (int j = 0; j < P; ++j) hand[j][slot] = xw[j];
+                if (live) {
+                    if constexpr (CONTIG) {
 #pragma unroll
-                    for (int q = 0; q < S / 2; ++q) {
-                        if (2 * q + 1 <= last) {
-                            dv2s d;
-                            d.x = v[2 * q];
-                            d.y = v[2 * q + 1];
-                            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4s, d), rx,
-                                                                   (int)(voff + 16u * q), 0, 0);
-                        } else if (2 * q <= last) {
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[2 * q]), rx,
-                                                                  (int)(voff + 16u * q), 0, 0);
+                        for (int q = 0; q < S / 2; ++q) {
+                            if (2 * q + 1 <= last) {
+                                dv2s d;
+                                d.x = v[2 * q];
+                                d.y = v[2 * q + 1];
+                                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4s, d), rx,
+                                                                       (int)(voff + 16u * q), 0, 0);
+                            } else if (2 * q <= last) {
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[2 * q]), rx,
+                                                                      (int)(voff + 16u * q), 0, 0);
+                            }
                         }
-                    }
-                } else {
-                    // offsets recomputed here rather than kept from the loads
-                    unsigned so = 0;
+                    } else {
+                        // offsets recomputed here rather than kept from the loads
+                        unsigned so = 0;
 #pragma unroll
-                    for (int s = 0; s < S; ++s) {
-                        if (s <= last)
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[s]), rx,
-                                                                  (int)voff, (int)so, 0);
-                        so = opaque_val(so + rstride);
+                        for (int s = 0; s < S; ++s) {
+                            if (s <= last)
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[s]), rx,
+                                                                      (int)voff, (int)so, 0);
+                            so = opaque_val(so + rstride);
+                        }
                     }
                 }
             }

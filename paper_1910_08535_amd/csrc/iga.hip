@@ -808,28 +808,37 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
         const int n = c->N[a];
         const double *F = nullptr, *B = nullptr;
         sweep_tables(c, pg, a, &F, &B);
-        // the segment kernel addresses a wave's values with 32-bit offsets from the
-        // element of its first lane: at most (dO n + 1) inner + (kSeg - 1) inner
-        // elements away, dO the number of line groups its 64 lanes cross
-        const long long dO = std::min(lines[a] / inner[a] - 1, (63 + inner[a] - 1) / inner[a]);
-        const long long span = (dO * n + 1) * inner[a] + (long long)(iga::kSeg - 1) * inner[a];
-        if (n <= iga::kSeg * iga::kSegMaxWaves && span * 8 < 0xffffffffLL) {   // lines on chip
-            const unsigned grid = (unsigned)((lines[a] + 63) / 64);
-            const unsigned threads = 64u * (unsigned)((n + iga::kSeg - 1) / iga::kSeg);
-            if (c->p == 2)
-                if (a == 0)
-                    hipLaunchKernelGGL((iga::ads_seg_kernel<2, true>), dim3(grid), dim3(threads), 0, s, F,
-                                       B, n, lines[a], inner[a], src, x);
-                else
-                    hipLaunchKernelGGL((iga::ads_seg_kernel<2, false>), dim3(grid), dim3(threads), 0, s, F,
-                                       B, n, lines[a], inner[a], src, x);
-            else
-                if (a == 0)
-                    hipLaunchKernelGGL((iga::ads_seg_kernel<3, true>), dim3(grid), dim3(threads), 0, s, F,
-                                       B, n, lines[a], inner[a], src, x);
-                else
-                    hipLaunchKernelGGL((iga::ads_seg_kernel<3, false>), dim3(grid), dim3(threads), 0, s, F,
-                                       B, n, lines[a], inner[a], src, x);
+        // the segment kernel addresses a wave's values with 32-bit offsets from the element
+        // of its first lane: at most (dO n + 1) inner + ((H - 1) nw kSeg + kSeg - 1) inner
+        // elements away, dO the number of line groups its lanes cross, H the halves
+        const int cap = iga::kSeg * iga::kSegMaxWaves;
+        const int H = n <= cap ? 1 : 2;
+        const int lpw = 64 / H;
+        const int nw = (n + H * iga::kSeg - 1) / (H * iga::kSeg);
+        const long long dO = std::min(lines[a] / inner[a] - 1, (lpw - 1 + inner[a] - 1) / inner[a]);
+        const long long span =
+            (dO * n + 1) * inner[a] + ((long long)(H - 1) * nw * iga::kSeg + iga::kSeg - 1) * inner[a];
+        if (n <= 2 * cap && span * 8 < 0xffffffffLL) {   // lines on chip
+            const unsigned grid = (unsigned)((lines[a] + lpw - 1) / lpw);
+            const unsigned threads = 64u * (unsigned)nw;
+            const bool contig = a == 0;
+#define IGA_SEG(PP, CC, HH)                                                                            \
+    hipLaunchKernelGGL((iga::ads_seg_kernel<PP, CC, HH>), dim3(grid), dim3(threads), 0, s, F, B, n, lines[a], \
+                       inner[a], src, x)
+            if (c->p == 2) {
+                if (H == 1) {
+                    if (contig) IGA_SEG(2, true, 1); else IGA_SEG(2, false, 1);
+                } else {
+                    if (contig) IGA_SEG(2, true, 2); else IGA_SEG(2, false, 2);
+                }
+            } else {
+                if (H == 1) {
+                    if (contig) IGA_SEG(3, true, 1); else IGA_SEG(3, false, 1);
+                } else {
+                    if (contig) IGA_SEG(3, true, 2); else IGA_SEG(3, false, 2);
+                }
+            }
+#undef IGA_SEG
             IGA_HIP(hipGetLastError());
             continue;
         }
