@@ -279,15 +279,51 @@ __global__ __launch_bounds__(kAdsBlock) void ads_sweep_kernel(const double* __re
 // (the host checks that every offset fits 32 bits).  The factor rows of a wave's kSeg
 // rows are loaded with the values, lane s holding row r0 + s, and each step of the
 // recurrences takes its row from lane s with a register read: no memory latency per row.
+//
+// x-lines (CONTIG) are contiguous, so a lane's rows lie one line length away from the
+// next lane's and lane-per-line accesses touch 64 cache lines per instruction.  Their
+// values instead pass through a per-wave LDS stage, kStageRows rows of the wave's 64
+// segments at a time: the loads go straight into LDS (buffer loads with the LDS flag),
+// eight lanes covering the 128 contiguous bytes of one segment, and each lane then reads
+// its own rows back; the stores take the reverse route.
 // ---------------------------------------------------------------------------------
-constexpr int kSeg = 48;   // even: the contiguous variant reads rows in pairs
+constexpr int kSeg = 48;   // even: the contiguous variant moves rows in pairs
 constexpr int kSegMaxWaves = 16;
+constexpr int kStageRows = 16;                     // rows of a segment per stage pass
+constexpr int kStageBytes = 64 * kStageRows * 8;   // stage of one wave
+static_assert(kSeg % kStageRows == 0 && kStageRows == 16, "a stage pass moves 8 pairs per segment");
 static_assert(kFactorPad >= 2 * kSeg + 3, "zero rows must cover the padding of two halves and the band");
 
 __device__ __forceinline__ unsigned opaque_val(unsigned v)
 {
     asm volatile("" : "+s"(v));
     return v;
+}
+
+// Orders the LDS accesses of one wave around it (the wave's LDS operations execute in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Waits for every outstanding vector memory operation (s_waitcnt vmcnt(0)): loads into
+// LDS are not tracked by the compiler's waits.
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// Waits for every outstanding LDS operation (s_waitcnt lgkmcnt(0)).
+__device__ __forceinline__ void wait_lds_all() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// Byte position in a wave's stage of pair 0 (rows 0, 1 of the pass) of segment L; pair j
+// sits at stage_pos(L) ^ 16 j.  Transfer instruction q moves segments 8q .. 8q+7, its lane
+// 8a + b pair b ^ a of segment 8q + a, to bytes 16 (64 q + lane): contiguous for the loads
+// into LDS, and the XOR puts the eight segments a lane group reads back at one pair index
+// in distinct banks.
+__device__ __forceinline__ unsigned stage_pos(int L)
+{
+    const int a = L & 7;
+    return 16u * (unsigned)(64 * (L >> 3) + 9 * a);
 }
 
 
@@ -300,6 +336,7 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
     static_assert(HALVES == 1 || HALVES == 2, "one or two halves per wave");
     constexpr int FR = P + 1, S = kSeg, LPW = 64 / HALVES;   // lines per workgroup
     __shared__ double hand[P][64];
+    extern __shared__ __attribute__((aligned(16))) char ads_stage[];   // CONTIG: nw * kStageBytes
     const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
     const int h = HALVES == 2 ? lane >> 5 : 0;                                // half of the line
@@ -336,23 +373,36 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
         }
     };
     load_factors(0);
+    // CONTIG staging: this wave's stage; segment L (the rows of lane L) starts seg_off(L)
+    // bytes after the wave base, and lane 8a + b of a transfer moves pair b ^ a
+    char* const stg = ads_stage + (size_t)w * kStageBytes;
+    const int ga = lane >> 3, gj = (lane & 7) ^ (lane >> 3);
+    const unsigned own = stage_pos(lane);
+    auto seg_off = [&](int L) -> unsigned {
+        return (unsigned)(((L % LPW) * n + (L / LPW) * nw * S) * 8);
+    };
     double v[S];
     if constexpr (CONTIG) {
-        // x-lines (inner = 1): a lane's rows are contiguous, read as 16-byte pairs (a single
-        // value at an odd end; nothing past the end of the line)
+        // x-lines (inner = 1).  Rows past the end of a line are read too (the next line's,
+        // or zeros past the end of the buffer) and cleared below; lines past the last are
+        // read the same way and never stored.
 #pragma unroll
-        for (int q = 0; q < S / 2; ++q) {
-            if (2 * q + 1 <= last) {
-                const auto pr = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)(voff + 16u * q), 0, 0);
-                const dv2s d = __builtin_bit_cast(dv2s, pr);
-                v[2 * q] = d.x;
-                v[2 * q + 1] = d.y;
-            } else {
-                v[2 * q] = 2 * q <= last ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                                        rb, (int)(voff + 16u * q), 0, 0))
-                                         : 0.0;
-                v[2 * q + 1] = 0.0;
+        for (int c = 0; c < S / kStageRows; ++c) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rb, (__attribute__((address_space(3))) void*)(stg + 1024 * q), 16,
+                    (int)(seg_off(8 * q + ga) + 16u * gj), c * kStageRows * 8, 0, 0);
+            wait_vm_all();
+            wave_lds_order();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const dv2s d = *reinterpret_cast<const dv2s*>(stg + (own ^ (16u * j)));
+                v[c * kStageRows + 2 * j] = d.x;
+                v[c * kStageRows + 2 * j + 1] = d.y;
             }
+            wait_lds_all();
+            wave_lds_order();
         }
     } else if constexpr (HALVES == 1) {
         // the wave's rows end together: the row offset steps in a scalar register, clamped
@@ -432,22 +482,8 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
                 }
 #pragma unroll
                 for (int j = 0; j < P; ++j) hand[j][slot] = xw[j];
-                if (live) {
-                    if constexpr (CONTIG) {
-#pragma unroll
-                        for (int q = 0; q < S / 2; ++q) {
-                            if (2 * q + 1 <= last) {
-                                dv2s d;
-                                d.x = v[2 * q];
-                                d.y = v[2 * q + 1];
-                                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4s, d), rx,
-                                                                       (int)(voff + 16u * q), 0, 0);
-                            } else if (2 * q <= last) {
-                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, v[2 * q]), rx,
-                                                                      (int)(voff + 16u * q), 0, 0);
-                            }
-                        }
-                    } else {
+                if constexpr (!CONTIG) {
+                    if (live) {
                         // offsets recomputed here rather than kept from the loads
                         unsigned so = 0;
 #pragma unroll
@@ -457,6 +493,46 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
                                                                       (int)voff, (int)so, 0);
                             so = opaque_val(so + rstride);
                         }
+                    }
+                }
+            }
+            if constexpr (CONTIG) {
+                // once both halves of the wave are final (the first half's phase comes
+                // last), every lane stages its rows and the wave stores them segment-wise.
+                // The transfer lanes' segment, pair and stage position come from the lane
+                // index anew rather than being kept live from the loads.
+                if (kh == 0) {
+                    unsigned ln = threadIdx.x;
+                    asm volatile("" : "+v"(ln));
+                    ln &= 63u;
+                    const unsigned sa = ln >> 3, sj = (ln & 7u) ^ sa, sown = stage_pos((int)ln);
+#pragma unroll
+                    for (int c = 0; c < S / kStageRows; ++c) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            dv2s d;
+                            d.x = v[c * kStageRows + 2 * j];
+                            d.y = v[c * kStageRows + 2 * j + 1];
+                            *reinterpret_cast<dv2s*>(stg + (sown ^ (16u * j))) = d;
+                        }
+                        wave_lds_order();
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const dv2s d = *reinterpret_cast<const dv2s*>(stg + 16 * (64 * q + ln));
+                            const unsigned L = 8u * q + sa;
+                            const int s = c * kStageRows + 2 * (int)sj;
+                            const int lastL = n - 1 - ((int)(L / LPW) * nw + w) * S;
+                            const bool liveL = t0 + (long long)(L % LPW) < lines;
+                            const int off = (int)(seg_off((int)L) + 16u * sj);
+                            if (liveL && s + 1 <= lastL)
+                                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(iv4s, d), rx, off,
+                                                                       c * kStageRows * 8, 0);
+                            if (liveL && s == lastL)
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iv2s, d.x), rx, off,
+                                                                      c * kStageRows * 8, 0);
+                        }
+                        wait_lds_all();
+                        wave_lds_order();
                     }
                 }
             }

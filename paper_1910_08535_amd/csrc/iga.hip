@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -798,6 +799,41 @@ void sweep_tables(const iga_ctx* c, bool pg, int a, const double** F, const doub
 }
 
 // x = (M_z (x) M_y (x) M_x)^{-1} b: the x family from b into x, then y and z in place.
+// Largest LDS allocation of one workgroup on the current device (0 if unknown).
+int max_lds_per_block()
+{
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    cached[dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+
+// Lets one instantiation of the segment kernel take `bytes` of dynamic LDS (above 64 KiB
+// the function attribute has to allow it), once per device and size.
+template <int PP, bool CC, int HH>
+void seg_allow_lds(size_t bytes)
+{
+    static std::atomic<size_t> granted[64];
+    int dev = 0;
+    if (bytes <= 65536 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    if (bytes <= granted[dev].load(std::memory_order_relaxed)) return;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&iga::ads_seg_kernel<PP, CC, HH>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        granted[dev].store(bytes, std::memory_order_relaxed);
+    else
+        (void)hipGetLastError();
+}
+
 int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg = false)
 {
     const long long Nx = c->N[0], Ny = c->N[1], Nz = c->N[2];
@@ -818,13 +854,20 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
         const long long dO = std::min(lines[a] / inner[a] - 1, (lpw - 1 + inner[a] - 1) / inner[a]);
         const long long span =
             (dO * n + 1) * inner[a] + ((long long)(H - 1) * nw * iga::kSeg + iga::kSeg - 1) * inner[a];
-        if (n <= 2 * cap && span * 8 < 0xffffffffLL) {   // lines on chip
+        // x-lines pass through a per-wave LDS stage, which has to fit one workgroup
+        const bool contig = a == 0;
+        const size_t stage = contig ? (size_t)nw * iga::kStageBytes : 0;
+        const size_t lds_static = (size_t)c->p * 64 * sizeof(double);
+        const bool lds_ok = stage == 0 || stage + lds_static <= (size_t)max_lds_per_block();
+        if (n <= 2 * cap && span * 8 < 0xffffffffLL && lds_ok) {   // lines on chip
             const unsigned grid = (unsigned)((lines[a] + lpw - 1) / lpw);
             const unsigned threads = 64u * (unsigned)nw;
-            const bool contig = a == 0;
 #define IGA_SEG(PP, CC, HH)                                                                            \
-    hipLaunchKernelGGL((iga::ads_seg_kernel<PP, CC, HH>), dim3(grid), dim3(threads), 0, s, F, B, n, lines[a], \
-                       inner[a], src, x)
+    do {                                                                                               \
+        seg_allow_lds<PP, CC, HH>(stage + lds_static);                                                 \
+        hipLaunchKernelGGL((iga::ads_seg_kernel<PP, CC, HH>), dim3(grid), dim3(threads), stage, s, F, B, \
+                           n, lines[a], inner[a], src, x);                                             \
+    } while (0)
             if (c->p == 2) {
                 if (H == 1) {
                     if (contig) IGA_SEG(2, true, 1); else IGA_SEG(2, false, 1);
