@@ -26,6 +26,59 @@ typedef double dv2s __attribute__((ext_vector_type(2)));
 // step x_r = y_r d_r - sum_j B(r,j-1) x_{r+j}: the newest value enters one FMA only.
 constexpr int kFactorPad = 128;
 
+// Banded LU without pivoting of rows r0 .. r1-1 of a banded matrix A (rows of 2P+1
+// doubles, A[r (2P+1) + c - r + P] = A(r, c)) taken on its own: columns outside [r0, r1)
+// are dropped.  A = L U with L unit lower and U upper, both of bandwidth P; rows r0 .. r1-1
+// of the sweep tables get F[r] = [L(r, r-P), ..., L(r, r-1), 1] and
+// B[r] = [U(r, r+1) d_r, ..., U(r, r+P) d_r, d_r], d_r = 1 / U(r, r) (entries of columns
+// outside the range 0), so the substitutions are those of the Cholesky tables.  One thread.
+template <int P>
+__device__ void lu_rows(const double* __restrict__ A, int r0, int r1, double* __restrict__ F,
+                        double* __restrict__ B)
+{
+    constexpr int W = 2 * P + 1, FR = P + 1;
+    double ur[P][P + 1];   // rows r-P .. r-1 of U: ur[j][k] = U(r-P+j, r-P+j+k)
+    for (int j = 0; j < P; ++j)
+        for (int k = 0; k <= P; ++k) ur[j][k] = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        const double* ar = A + (size_t)r * W;   // ar[c - r + P] = A(r, c)
+        double l[P];
+        for (int k = 0; k < P; ++k) {           // column c = r - P + k < r
+            const int c = r - P + k;
+            if (c < r0) {
+                l[k] = 0.0;
+                continue;
+            }
+            double s = ar[k];
+            for (int m = 0; m < k; ++m) {       // rows r - P + m < c with U(., c) in band
+                const int row = r - P + m;
+                if (row < r0 || c - row > P) continue;
+                s = fma(-l[m], ur[m][c - row], s);
+            }
+            l[k] = s / ur[k][0];
+        }
+        double u[P + 1];
+        for (int k = 0; k <= P; ++k) {          // column c = r + k
+            const int c = r + k;
+            double s = ar[P + k];
+            for (int m = 0; m < P; ++m) {
+                const int row = r - P + m;
+                if (row < r0 || c - row > P) continue;
+                s = fma(-l[m], ur[m][c - row], s);
+            }
+            u[k] = c < r1 ? s : 0.0;
+        }
+        const double d = 1.0 / u[0];
+        for (int k = 0; k < P; ++k) F[(size_t)r * FR + k] = l[k];
+        F[(size_t)r * FR + P] = 1.0;
+        for (int j = 1; j <= P; ++j) B[(size_t)r * FR + j - 1] = u[j] * d;
+        B[(size_t)r * FR + P] = d;
+        for (int j = 0; j + 1 < P; ++j)
+            for (int k = 0; k <= P; ++k) ur[j][k] = ur[j + 1][k];
+        for (int k = 0; k <= P; ++k) ur[P - 1][k] = u[k];
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Banded Cholesky factor of one axis (one workgroup).
 //   M: band rows of M_a, W = 2P+1 slots per row, slot k <-> column r + k - P.
@@ -327,9 +380,16 @@ __device__ __forceinline__ unsigned stage_pos(int L)
 }
 
 
+//
+// Chunks: with K > 1 the lines are solved in K independent chunks of rows
+// [floor(k n / K), floor((k+1) n / K)), chunk k by the workgroups of grid row k, with
+// tables whose rows couple nothing across a chunk's end (the chunk factors of the
+// partitioned solve).  Rows past the end of a chunk then read the next chunk's factor
+// rows; they compute values that are never stored and, since the chunk's last rows have
+// no coupling beyond it, never reach a stored row.
 template <int P, bool CONTIG, int HALVES>
 __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double* __restrict__ F,
-                                                                     const double* __restrict__ B, int n,
+                                                                     const double* __restrict__ B, int n, int K,
                                                                      long long lines, long long inner,
                                                                      const double* b, double* x)
 {
@@ -347,10 +407,15 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
     const long long tl = live ? t : lines - 1;
     const long long o = tl / inner, i = tl - o * inner;
     const long long o0 = t0 / inner, i0 = t0 - o0 * inner;
+    // rows [cb, cb + len) of the lines (the whole lines when K = 1)
+    const int cb = (int)(((long long)blockIdx.y * n) / K);
+    const int len = (int)(((long long)(blockIdx.y + 1) * n) / K) - cb;
+    F += (size_t)cb * FR;
+    B += (size_t)cb * FR;
     // rows of this lane: [r0, r0 + S); the wave's first half starts at rw
     const int rw = w * S, r0 = (h * nw + w) * S;
     // wave base: row rw of line t0; lane offset in bytes; row stride in bytes
-    const long long wbase = (o0 * (long long)n + rw) * inner + i0;
+    const long long wbase = (o0 * (long long)n + cb + rw) * inner + i0;
     const long long total = lines * (long long)n;
     const unsigned voff =
         (unsigned)(((o - o0) * (long long)n * inner + (i - i0) + (long long)(r0 - rw) * inner) * 8);
@@ -359,7 +424,7 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
     const int nrec = (int)(left > 0xffffffffll ? 0xffffffffll : left);
     const auto rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(b + wbase), (short)0, nrec, 0x00020000);
     const auto rx = __builtin_amdgcn_make_buffer_rsrc(x + wbase, (short)0, nrec, 0x00020000);
-    const int last = n - 1 - r0;   // rows s > last of this lane lie past the end of its line
+    const int last = len - 1 - r0;   // rows s > last of this lane lie past the end of its line
 
     // factor rows of one half's segment of this wave, lane s holding row (half nw + w) S + s
     // (zero rows past n)
@@ -521,7 +586,7 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
                             const dv2s d = *reinterpret_cast<const dv2s*>(stg + 16 * (64 * q + ln));
                             const unsigned L = 8u * q + sa;
                             const int s = c * kStageRows + 2 * (int)sj;
-                            const int lastL = n - 1 - ((int)(L / LPW) * nw + w) * S;
+                            const int lastL = len - 1 - ((int)(L / LPW) * nw + w) * S;
                             const bool liveL = t0 + (long long)(L % LPW) < lines;
                             const int off = (int)(seg_off((int)L) + 16u * sj);
                             if (liveL && s + 1 <= lastL)

@@ -1,0 +1,465 @@
+// Partitioned solve of one family of lines of the alternating-directions solve
+// (Section 4.1), for families with few lines (1D, and 2D up to a few thousand lines per
+// family), where one recurrence per line leaves most of the GPU idle.
+//
+// The 1D matrix A (n x n, bandwidth P, the same for every line of the family) is cut into
+// K chunks of rows [s_k, e_k), s_k = floor(k n / K), e_k = s_{k+1}, of at least 64 >= 2P
+// rows each.  With D the block diagonal of the chunks' own blocks A_kk,
+// A = D (I + S), and the spikes of S are line-independent:
+//     V_k = A_kk^{-1} A(chunk k, first P columns of chunk k+1)     (e_k - s_k) x P
+//     W_k = A_kk^{-1} A(chunk k, last P columns of chunk k-1)      (e_k - s_k) x P
+// A line's solve is then
+//   1. g = D^{-1} b: independent solves of every chunk of every line (LU factors of the
+//      chunks, in the sweep-table format of the other solves, so that the segment kernel
+//      runs them, one chunk per workgroup row, when there are lines enough to fill its
+//      lanes);
+//   2. the reduced system in zeta_k = (u_k, t_{k+1}), u_k the last P values of chunk k and
+//      t_{k+1} the first P of chunk k+1 (k = 0 .. K-2):
+//          u_k + V_k^B t_{k+1} + W_k^B u_{k-1} = g_k^B,
+//          t_{k+1} + W_{k+1}^T u_k + V_{k+1}^T t_{k+2} = g_{k+1}^T
+//      (^T: first P rows of a spike, ^B: last P rows), block tridiagonal with 2P x 2P
+//      blocks D_k = [I, V_k^B; W_{k+1}^T, I], E_k = [W_k^B, 0; 0, 0] below and
+//      F_k = [0, 0; 0, V_{k+1}^T] above the diagonal.  Its block LU is line-independent:
+//      Delta_0 = D_0, Gamma_k = E_k Delta_{k-1}^{-1}, Delta_k = D_k - Gamma_k F_{k-1}; per
+//      line a forward sweep y_k = h_k - Gamma_k y_{k-1} (h_k = (g_k^B, g_{k+1}^T)) and a
+//      backward sweep zeta_k = Delta_k^{-1} (y_k - F_k zeta_{k+1});
+//   3. x = g - V_k t_{k+1} - W_k u_{k-1} on every row of chunk k.
+// This is exact (no truncation of the spikes), so it agrees with the sequential solve to
+// rounding.  The spikes decay fast away from the chunk ends (for the mass matrices of
+// this method Gamma is below 1e-16 for chunks of 64 rows), so the reduced system is well
+// conditioned.
+#pragma once
+#include "ads.hpp"
+#include "common.hpp"
+
+namespace iga {
+
+// First row of chunk k (k = K: n).
+__host__ __device__ inline int part_start(int k, int n, int K)
+{
+    return (int)(((long long)k * n) / K);
+}
+
+// Chunk LU factors: thread k factorizes rows [s_k, e_k) of A on their own; thread 0 also
+// writes the kFactorPad zero rows after row n that the segment kernel reads past the end.
+template <int P>
+__global__ void part_factor_kernel(const double* __restrict__ A, int n, int K, double* __restrict__ F,
+                                   double* __restrict__ B)
+{
+    constexpr int FR = P + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    if (k == 0)
+        for (int i = 0; i < kFactorPad * FR; ++i) F[(size_t)n * FR + i] = B[(size_t)n * FR + i] = 0.0;
+    lu_rows<P>(A, part_start(k, n, K), part_start(k + 1, n, K), F, B);
+}
+
+// Spikes: thread (k, side, j) solves A_kk v = column j of the coupling block (side 0: V_k,
+// nonzero right-hand side in the last P rows; side 1: W_k, in the first P rows) into
+// rows [s_k, e_k) of V or Wt (P doubles per row).  Spikes that do not exist (V of the last
+// chunk, W of the first) are written as zeros.
+template <int P>
+__global__ void part_spike_kernel(const double* __restrict__ A, int n, int K,
+                                  const double* __restrict__ F, const double* __restrict__ B,
+                                  double* __restrict__ V, double* __restrict__ Wt)
+{
+    constexpr int W = 2 * P + 1, FR = P + 1;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= K * 2 * P) return;
+    const int j = id % P, side = (id / P) % 2, k = id / (2 * P);
+    const int s = part_start(k, n, K), e = part_start(k + 1, n, K);
+    double* out = side == 0 ? V : Wt;
+    const bool exists = side == 0 ? k < K - 1 : k > 0;
+    double yw[P];
+    for (int q = 0; q < P; ++q) yw[q] = 0.0;
+    for (int r = s; r < e; ++r) {
+        double rhs = 0.0;
+        if (exists) {
+            const int c = side == 0 ? e + j : s - P + j;
+            const bool row_in = side == 0 ? r >= e - P : r < s + P;
+            const int kk = c - r + P;
+            if (row_in && kk >= 0 && kk <= 2 * P) rhs = A[(size_t)r * W + kk];
+        }
+        double y = rhs * F[(size_t)r * FR + P];
+        for (int q = 0; q < P; ++q) y = fma(-F[(size_t)r * FR + q], yw[q], y);
+        out[(size_t)r * P + j] = y;
+        for (int q = 0; q + 1 < P; ++q) yw[q] = yw[q + 1];
+        yw[P - 1] = y;
+    }
+    double xw[P];   // xw[q-1] = x_{r+q}
+    for (int q = 0; q < P; ++q) xw[q] = 0.0;
+    for (int r = e - 1; r >= s; --r) {
+        double x = out[(size_t)r * P + j] * B[(size_t)r * FR + P];
+        for (int q = P; q >= 1; --q) x = fma(-B[(size_t)r * FR + q - 1], xw[q - 1], x);
+        out[(size_t)r * P + j] = x;
+        for (int q = P - 1; q >= 1; --q) xw[q] = xw[q - 1];
+        xw[0] = x;
+    }
+}
+
+// In-place inverse of a Q x Q matrix by Gauss-Jordan elimination with partial pivoting.
+template <int Q>
+__device__ void small_inverse(double (&a)[Q][Q], double (&inv)[Q][Q])
+{
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) inv[i][j] = i == j ? 1.0 : 0.0;
+    for (int c = 0; c < Q; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < Q; ++r)
+            if (fabs(a[r][c]) > fabs(a[pr][c])) pr = r;
+        if (pr != c)
+            for (int j = 0; j < Q; ++j) {
+                double t = a[c][j];
+                a[c][j] = a[pr][j];
+                a[pr][j] = t;
+                t = inv[c][j];
+                inv[c][j] = inv[pr][j];
+                inv[pr][j] = t;
+            }
+        const double d = 1.0 / a[c][c];
+        for (int j = 0; j < Q; ++j) {
+            a[c][j] *= d;
+            inv[c][j] *= d;
+        }
+        for (int r = 0; r < Q; ++r) {
+            if (r == c) continue;
+            const double f = a[r][c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < Q; ++j) {
+                a[r][j] = fma(-f, a[c][j], a[r][j]);
+                inv[r][j] = fma(-f, inv[c][j], inv[r][j]);
+            }
+        }
+    }
+}
+
+// Block LU of the reduced system (one thread): Gamma_k (k >= 1; Gamma_0 = 0) and
+// Delta_k^{-1} for k = 0 .. K-2, 2P x 2P each, row-major.
+template <int P>
+__global__ void part_reduce_setup_kernel(const double* __restrict__ V, const double* __restrict__ Wt, int n,
+                                         int K, double* __restrict__ G, double* __restrict__ Dinv)
+{
+    constexpr int Q = 2 * P;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double prev[Q][Q];   // Delta_{k-1}^{-1}
+    for (int k = 0; k + 1 < K; ++k) {
+        const int s = part_start(k, n, K), e = part_start(k + 1, n, K);
+        double D[Q][Q];
+        for (int i = 0; i < Q; ++i)
+            for (int j = 0; j < Q; ++j) D[i][j] = i == j ? 1.0 : 0.0;
+        for (int i = 0; i < P; ++i)
+            for (int j = 0; j < P; ++j) {
+                D[i][P + j] = V[(size_t)(e - P + i) * P + j];    // V_k^B
+                D[P + i][j] = Wt[(size_t)(e + i) * P + j];       // W_{k+1}^T
+            }
+        double Gk[Q][Q];
+        for (int i = 0; i < Q; ++i)
+            for (int j = 0; j < Q; ++j) Gk[i][j] = 0.0;
+        if (k >= 1) {
+            // Gamma_k = E_k Delta_{k-1}^{-1}: rows 0 .. P-1 are W_k^B times rows 0 .. P-1
+            for (int i = 0; i < P; ++i)
+                for (int j = 0; j < Q; ++j) {
+                    double acc = 0.0;
+                    for (int q = 0; q < P; ++q) acc = fma(Wt[(size_t)(e - P + i) * P + q], prev[q][j], acc);
+                    Gk[i][j] = acc;
+                }
+            // Delta_k = D_k - Gamma_k F_{k-1}, F_{k-1} = [0, 0; 0, V_k^T]
+            for (int i = 0; i < Q; ++i)
+                for (int j = 0; j < P; ++j) {
+                    double acc = 0.0;
+                    for (int q = 0; q < P; ++q) acc = fma(Gk[i][P + q], V[(size_t)(s + q) * P + j], acc);
+                    D[i][P + j] -= acc;
+                }
+        }
+        double inv[Q][Q];
+        small_inverse<Q>(D, inv);
+        for (int i = 0; i < Q; ++i)
+            for (int j = 0; j < Q; ++j) {
+                G[((size_t)k * Q + i) * Q + j] = Gk[i][j];
+                Dinv[((size_t)k * Q + i) * Q + j] = inv[i][j];
+                prev[i][j] = inv[i][j];
+            }
+    }
+}
+
+// Step 1 for families of fewer lines than a wave has lanes (1D): one thread per
+// (line, chunk), lines fastest; a line's row r at (o n + r) inner + i for line
+// t = o inner + i.  Rows are read eight at a time ahead of the recurrence.  dst may be src.
+template <int P>
+__global__ __launch_bounds__(256) void part_local_kernel(const double* __restrict__ F,
+                                                         const double* __restrict__ B, int n, int K,
+                                                         int lines, int inner, const double* src, double* dst)
+{
+    constexpr int FR = P + 1, U = 8;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= lines * K) return;
+    const int t = id % lines, k = id / lines;
+    const int o = t / inner, i = t - o * inner;
+    const size_t base = (size_t)o * n * inner + i;
+    const int s = part_start(k, n, K), e = part_start(k + 1, n, K);
+    double yw[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) yw[q] = 0.0;
+    for (int r0 = s; r0 < e; r0 += U) {
+        double bv[U], f[U][FR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = min(r0 + u, e - 1);
+            bv[u] = src[base + (size_t)r * inner];
+#pragma unroll
+            for (int q = 0; q < FR; ++q) f[u][q] = F[(size_t)r * FR + q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r0 + u < e) {
+                double y = bv[u] * f[u][P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) y = fma(-f[u][q], yw[q], y);
+                dst[base + (size_t)(r0 + u) * inner] = y;
+#pragma unroll
+                for (int q = 0; q + 1 < P; ++q) yw[q] = yw[q + 1];
+                yw[P - 1] = y;
+            }
+        }
+    }
+    double xw[P];   // xw[q-1] = x_{r+q}
+#pragma unroll
+    for (int q = 0; q < P; ++q) xw[q] = 0.0;
+    for (int r0 = e - 1; r0 >= s; r0 -= U) {
+        double yv[U], bt[U][FR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = max(r0 - u, s);
+            yv[u] = dst[base + (size_t)r * inner];
+#pragma unroll
+            for (int q = 0; q < FR; ++q) bt[u][q] = B[(size_t)r * FR + q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r0 - u >= s) {
+                double x = yv[u] * bt[u][P];
+#pragma unroll
+                for (int q = P; q >= 1; --q) x = fma(-bt[u][q - 1], xw[q - 1], x);
+                dst[base + (size_t)(r0 - u) * inner] = x;
+#pragma unroll
+                for (int q = P - 1; q >= 1; --q) xw[q] = xw[q - 1];
+                xw[0] = x;
+            }
+        }
+    }
+}
+
+// Step 2: one thread per line, T lines per workgroup.  With `staged` the workgroup first
+// copies the block tables (Gamma_k, Delta_k^{-1} and V_{k+1}^T for every k) into LDS, so
+// that the sweeps wait on no memory; otherwise they read them from memory a step ahead.
+// Each thread then reads all its h_k = x rows e_k - P .. e_k + P - 1 (k = 0 .. K-2) into
+// LDS, sixteen steps' loads at once, runs the forward sweep there (y_k replaces h_k) and the
+// backward sweep, which writes zeta_k to Z (entry (k, q) of line t at
+// Z[(k 2P + q) lines + t]).  LDS: [tables: (K-1) (2 (2P)^2 + P^2) if staged | T (K-1) 2P].
+template <int P>
+__host__ __device__ constexpr int part_table_doubles(int K)
+{
+    return (K - 1) * (2 * 4 * P * P + P * P);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restrict__ G,
+                                                         const double* __restrict__ Dinv,
+                                                         const double* __restrict__ V, int n, int K,
+                                                         int lines, int inner, int staged,
+                                                         const double* __restrict__ x, double* __restrict__ Z)
+{
+    constexpr int Q = 2 * P;
+    extern __shared__ double part_y[];
+    const int T = blockDim.x, tid = threadIdx.x;
+    double* const tabs = part_y;
+    if (staged) {
+        // eight entries per thread in flight at a time: [Gamma | Delta^-1 | V^T]
+        const int nq = (K - 1) * Q * Q, nt = 2 * nq + (K - 1) * P * P;
+        for (int j0 = 0; j0 < nt; j0 += 8 * T) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = min(j0 + u * T + tid, nt - 1);
+                if (j < nq) {
+                    v[u] = G[j];
+                } else if (j < 2 * nq) {
+                    v[u] = Dinv[j - nq];
+                } else {
+                    const int jj = j - 2 * nq, k = jj / (P * P), a = (jj / P) % P, b = jj % P;
+                    v[u] = V[(size_t)(part_start(k + 1, n, K) + a) * P + b];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j0 + u * T + tid < nt) tabs[j0 + u * T + tid] = v[u];
+        }
+        __syncthreads();
+    }
+    const int t = blockIdx.x * T + tid;
+    if (t >= lines) return;   // no barrier below: each thread uses its own LDS column
+    const int o = t / inner, i = t - o * inner;
+    const size_t base = (size_t)o * n * inner + i;
+    double* yl = part_y + (staged ? part_table_doubles<P>(K) : 0) + tid;
+    // block tables, from LDS or memory (the same for every thread; read through vector
+    // registers, a zero the compiler cannot see through, as scalar registers do not hold
+    // them)
+    int vz;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+    const double* Gp = staged ? tabs + vz : G + vz;
+    const double* Dp = staged ? tabs + (K - 1) * Q * Q + vz : Dinv + vz;
+    const double* VTs = tabs + 2 * (K - 1) * Q * Q + vz;
+    V += vz;
+    constexpr int KB = 16;   // steps whose h is loaded together
+    for (int k0 = 0; k0 + 1 < K; k0 += KB) {
+        double hb[KB][Q];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+            const int e = part_start(min(k0 + kk, K - 2) + 1, n, K);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
+        }
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk)
+            if (k0 + kk + 1 < K) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) yl[(size_t)((k0 + kk) * Q + q) * T] = hb[kk][q];
+            }
+    }
+    // forward: y_k = h_k - Gamma_k y_{k-1}
+    double y[Q], g[Q * Q], gn[Q * Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) y[q] = yl[(size_t)q * T];
+#pragma unroll
+    for (int q = 0; q < Q * Q; ++q) gn[q] = K > 2 ? Gp[(size_t)Q * Q + q] : 0.0;
+    for (int k = 1; k + 1 < K; ++k) {
+#pragma unroll
+        for (int q = 0; q < Q * Q; ++q) g[q] = gn[q];
+        const int kn = k + 2 < K ? k + 1 : k;
+#pragma unroll
+        for (int q = 0; q < Q * Q; ++q) gn[q] = Gp[(size_t)kn * Q * Q + q];
+        double h[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            double acc = yl[(size_t)(k * Q + a) * T];
+#pragma unroll
+            for (int b = 0; b < Q; ++b) acc = fma(-g[a * Q + b], y[b], acc);
+            h[a] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            y[q] = h[q];
+            yl[(size_t)(k * Q + q) * T] = h[q];
+        }
+    }
+    // backward: zeta_k = Delta_k^{-1} (y_k - F_k zeta_{k+1})
+    double zn[Q], d[Q * Q], dn[Q * Q], vt[P * P], vn[P * P];
+#pragma unroll
+    for (int q = 0; q < Q * Q; ++q) dn[q] = Dp[(size_t)(K - 2) * Q * Q + q];
+#pragma unroll
+    for (int q = 0; q < P * P; ++q) vn[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) zn[q] = 0.0;
+    for (int k = K - 2; k >= 0; --k) {
+#pragma unroll
+        for (int q = 0; q < Q * Q; ++q) d[q] = dn[q];
+#pragma unroll
+        for (int q = 0; q < P * P; ++q) vt[q] = vn[q];   // V_{k+1}^T (0 for k = K-2)
+        const int kn = k > 0 ? k - 1 : k;
+#pragma unroll
+        for (int q = 0; q < Q * Q; ++q) dn[q] = Dp[(size_t)kn * Q * Q + q];
+        if (staged) {
+#pragma unroll
+            for (int q = 0; q < P * P; ++q) vn[q] = VTs[(size_t)kn * P * P + q];
+        } else {
+            const int s1 = part_start(kn + 1, n, K);   // first row of chunk kn + 1
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) vn[a * P + b] = V[(size_t)(s1 + a) * P + b];
+        }
+        double rhs[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rhs[q] = yl[(size_t)(k * Q + q) * T];
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+            double acc = rhs[P + a];
+#pragma unroll
+            for (int b = 0; b < P; ++b) acc = fma(-vt[a * P + b], zn[P + b], acc);
+            rhs[P + a] = acc;
+        }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < Q; ++b) acc = fma(d[a * Q + b], rhs[b], acc);
+            zn[a] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Z[((size_t)k * Q + q) * lines + t] = zn[q];
+    }
+}
+
+// Step 3: x -= V[r] t_{k+1} + Wt[r] u_{k-1} on every value.  x-lines (inner = 1): a
+// workgroup per (chunk, line) = (blockIdx.x, blockIdx.y), its threads over the chunk's
+// rows.  Other families: a workgroup per (kCorrRows rows of line groups, inner block) =
+// (blockIdx.x, blockIdx.y), its threads over the inner index, each thread taking those
+// rows.  The chunk of a row is uniform across the workgroup, so no thread divides.
+constexpr int kCorrRows = 4;
+template <int P>
+__global__ __launch_bounds__(256) void part_correct_kernel(const double* __restrict__ V,
+                                                           const double* __restrict__ Wt, int n, int K,
+                                                           int lines, int inner, int rows,
+                                                           const double* __restrict__ Z, double* __restrict__ x)
+{
+    constexpr int Q = 2 * P;
+    if (inner == 1) {
+        const int k = blockIdx.x, o = blockIdx.y;
+        double zt[P], zu[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            zt[j] = k < K - 1 ? Z[((size_t)k * Q + P + j) * lines + o] : 0.0;
+            zu[j] = k > 0 ? Z[((size_t)(k - 1) * Q + j) * lines + o] : 0.0;
+        }
+        const int r1 = part_start(k + 1, n, K);
+        for (int r = part_start(k, n, K) + threadIdx.x; r < r1; r += blockDim.x) {
+            const size_t idx = (size_t)o * n + r;
+            double v = x[idx];
+#pragma unroll
+            for (int j = 0; j < P; ++j) v = fma(-V[(size_t)r * P + j], zt[j], v);
+#pragma unroll
+            for (int j = 0; j < P; ++j) v = fma(-Wt[(size_t)r * P + j], zu[j], v);
+            x[idx] = v;
+        }
+        return;
+    }
+    const int i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= inner) return;
+    double xv[kCorrRows];
+#pragma unroll
+    for (int u = 0; u < kCorrRows; ++u) {
+        const int g = min(blockIdx.x * kCorrRows + u, rows - 1), o = g / n, r = g - o * n;
+        xv[u] = x[((size_t)o * n + r) * inner + i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCorrRows; ++u) {
+        const int g = blockIdx.x * kCorrRows + u;
+        if (g >= rows) break;
+        const int o = g / n, r = g - o * n;
+        const int k = (int)(((long long)(r + 1) * K + n - 1) / n) - 1;   // s_k <= r < e_k
+        const int t = o * inner + i;
+        double v = xv[u];
+        if (k < K - 1) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) v = fma(-V[(size_t)r * P + j], Z[((size_t)k * Q + P + j) * lines + t], v);
+        }
+        if (k > 0) {
+#pragma unroll
+            for (int j = 0; j < P; ++j)
+                v = fma(-Wt[(size_t)r * P + j], Z[((size_t)(k - 1) * Q + j) * lines + t], v);
+        }
+        x[((size_t)o * n + r) * inner + i] = v;
+    }
+}
+
+}  // namespace iga

@@ -17,6 +17,7 @@
 #include "iga.h"
 
 #include "ads.hpp"
+#include "ads_part.hpp"
 #include "boundary.hpp"
 #include "refined.hpp"
 #include "apply.hpp"
@@ -74,6 +75,12 @@ struct iga_ctx {
     // of the LU factors of its square PG mass
     int refine[3] = {1, 1, 1};
     double* lu[3] = {nullptr, nullptr, nullptr};
+    // partitioned solve of the Galerkin mass along axes with few lines: chunk length and
+    // count, the tables F | B | V | Wt | Gamma | Delta^-1 per axis, and per-line scratch
+    int part_m[3] = {0, 0, 0}, part_K[3] = {0, 0, 0};
+    double* part[3] = {nullptr, nullptr, nullptr};
+    double* part_z = nullptr;
+    size_t part_z_n = 0;
     // cached explicit-step graph
     hipGraphExec_t gexec = nullptr;
     const double* g_u = nullptr;
@@ -798,7 +805,6 @@ void sweep_tables(const iga_ctx* c, bool pg, int a, const double** F, const doub
     }
 }
 
-// x = (M_z (x) M_y (x) M_x)^{-1} b: the x family from b into x, then y and z in place.
 // Largest LDS allocation of one workgroup on the current device (0 if unknown).
 int max_lds_per_block()
 {
@@ -834,6 +840,187 @@ void seg_allow_lds(size_t bytes)
         (void)hipGetLastError();
 }
 
+// Chunk count K of the partitioned solve of a family of `lines` lines of n rows, or 0 when
+// the family keeps one recurrence per line: that is when its lines fill at least 128
+// workgroups of 64 lines (half the compute units), or when a chunk would have fewer than
+// 64 rows.  With lines enough for the lanes of a wave the chunks are solved by the
+// segment kernel, at most 96 rows (two waves) each.  Fewer lines (1D) take one thread
+// per chunk, of about sqrt(3 n) rows: a chunk's two substitutions then cost about as much
+// as a line's reduced sweeps (2 n / m steps of a 2P x 2P block).
+int part_chunks(int n, long long lines)
+{
+    const long long total = lines * n;
+    if (total >= (1LL << 31) || (lines + 63) / 64 >= 128) return 0;
+    int K;
+    if (lines >= 64) {
+        K = (n + 95) / 96;
+    } else {
+        int m = 64;
+        while ((long long)m * m < 3LL * n && m < 8192) m *= 2;
+        K = n / m;
+    }
+    // grid rows of the chunks, and the reduced sweeps of one line in at most 64 KiB of LDS
+    if (K < 2 || n / K < 64 || K > 65535 || (long long)(K - 1) * 6 * 8 > 65536) return 0;
+    return K;
+}
+
+// Tables of the partitioned solve along axis a in K chunks (built once per context), and
+// scratch for `lines` lines.  The chunk factors F, B have kFactorPad zero rows after row n,
+// as the segment kernel reads them.
+int ensure_part(iga_ctx* c, int a, int K, long long lines)
+{
+    const int n = c->N[a], p = c->p, Q = 2 * p;
+    const size_t tab = (size_t)(n + iga::kFactorPad) * (p + 1);
+    if (!c->part[a] || c->part_K[a] != K) {
+        const size_t doubles = 2 * tab + 2 * (size_t)n * p + 2 * (size_t)(K - 1) * Q * Q;
+        void* mem = nullptr;
+        IGA_TRY(dalloc(c, &mem, doubles * sizeof(double)));
+        double* F = (double*)mem;
+        double* B = F + tab;
+        double* V = B + tab;
+        double* Wt = V + (size_t)n * p;
+        double* G = Wt + (size_t)n * p;
+        double* Dinv = G + (size_t)(K - 1) * Q * Q;
+        const double* A = c->t[a].gm;
+        const unsigned gk = (unsigned)((K + 63) / 64), gs = (unsigned)((K * 2 * p + 63) / 64);
+        if (p == 2) {
+            hipLaunchKernelGGL(iga::part_factor_kernel<2>, dim3(gk), dim3(64), 0, c->stream, A, n, K, F, B);
+            hipLaunchKernelGGL(iga::part_spike_kernel<2>, dim3(gs), dim3(64), 0, c->stream, A, n, K,
+                               (const double*)F, (const double*)B, V, Wt);
+            hipLaunchKernelGGL(iga::part_reduce_setup_kernel<2>, dim3(1), dim3(64), 0, c->stream,
+                               (const double*)V, (const double*)Wt, n, K, G, Dinv);
+        } else {
+            hipLaunchKernelGGL(iga::part_factor_kernel<3>, dim3(gk), dim3(64), 0, c->stream, A, n, K, F, B);
+            hipLaunchKernelGGL(iga::part_spike_kernel<3>, dim3(gs), dim3(64), 0, c->stream, A, n, K,
+                               (const double*)F, (const double*)B, V, Wt);
+            hipLaunchKernelGGL(iga::part_reduce_setup_kernel<3>, dim3(1), dim3(64), 0, c->stream,
+                               (const double*)V, (const double*)Wt, n, K, G, Dinv);
+        }
+        IGA_HIP(hipGetLastError());
+        c->part[a] = F;
+        c->part_K[a] = K;
+    }
+    const size_t zn = (size_t)lines * (K - 1) * Q;
+    if (c->part_z_n < zn) {
+        void* mem = nullptr;
+        IGA_TRY(dalloc(c, &mem, zn * sizeof(double)));   // the old scratch stays with the context
+        c->part_z = (double*)mem;
+        c->part_z_n = zn;
+    }
+    return IGA_OK;
+}
+
+int launch_seg(iga_ctx* c, const double* F, const double* B, int n, int K, long long lines, long long inner,
+               bool contig, const double* src, double* x, hipStream_t s);
+
+// One family by the partitioned solve: chunk solves from src into x, the reduced sweeps
+// per line, the spike correction.
+int launch_part(iga_ctx* c, int a, int K, int lines, int inner, const double* src, double* x, hipStream_t s)
+{
+    IGA_TRY(ensure_part(c, a, K, lines));
+    const int n = c->N[a], p = c->p;
+    const size_t tab = (size_t)(n + iga::kFactorPad) * (p + 1);
+    const double* F = c->part[a];
+    const double* B = F + tab;
+    const double* V = B + tab;
+    const double* Wt = V + (size_t)n * p;
+    const double* G = Wt + (size_t)n * p;
+    const double* Dinv = G + (size_t)(K - 1) * 4 * p * p;
+    const unsigned g1 = (unsigned)(((size_t)lines * K + 255) / 256);
+    // reduced sweeps: T lines per workgroup, (K-1) 2P doubles of LDS each, and the block
+    // tables beside them when they take at most 32 KiB; at most 64 KiB in all
+    const size_t per_line = (size_t)(K - 1) * 2 * p * sizeof(double);
+    const size_t tabs = (size_t)(p == 2 ? iga::part_table_doubles<2>(K) : iga::part_table_doubles<3>(K)) *
+                        sizeof(double);
+    const int staged = tabs <= 32768 && per_line + tabs <= 65536 ? 1 : 0;
+    const unsigned T = (unsigned)std::max<size_t>(1, std::min<size_t>(64, (65536 - (staged ? tabs : 0)) / per_line));
+    const unsigned g2 = (unsigned)((lines + T - 1) / T);
+    const size_t lds2 = T * per_line + (staged ? tabs : 0);
+    // correction
+    dim3 g3, b3;
+    const int rows = (lines / inner) * n;   // rows of the line groups (inner > 1)
+    if (inner == 1) {
+        const int longest = (n + K - 1) / K;
+        g3 = dim3((unsigned)K, (unsigned)lines);
+        b3 = dim3((unsigned)std::min(256, (longest + 63) / 64 * 64));
+    } else {
+        g3 = dim3((unsigned)((rows + iga::kCorrRows - 1) / iga::kCorrRows), (unsigned)((inner + 255) / 256));
+        b3 = dim3(256);
+    }
+    bool local_done = false;
+    if (lines >= 64) {
+        const int rc = launch_seg(c, F, B, n, K, lines, inner, a == 0, src, x, s);
+        if (rc != 1) {   // 1: the chunks do not fit the segment kernel
+            IGA_TRY(rc);
+            local_done = true;
+        }
+    }
+    if (p == 2) {
+        if (!local_done)
+            hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, n, K, lines, inner, src, x);
+        hipLaunchKernelGGL(iga::part_reduce_kernel<2>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K, lines, inner,
+                           staged, (const double*)x, c->part_z);
+        hipLaunchKernelGGL(iga::part_correct_kernel<2>, g3, b3, 0, s, V, Wt, n, K, lines, inner, rows,
+                           (const double*)c->part_z, x);
+    } else {
+        if (!local_done)
+            hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, n, K, lines, inner, src, x);
+        hipLaunchKernelGGL(iga::part_reduce_kernel<3>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K, lines, inner,
+                           staged, (const double*)x, c->part_z);
+        hipLaunchKernelGGL(iga::part_correct_kernel<3>, g3, b3, 0, s, V, Wt, n, K, lines, inner, rows,
+                           (const double*)c->part_z, x);
+    }
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
+// One family of lines (or of K chunks of lines) by the segment kernel; returns 1 without
+// launching when the lines do not fit it (too long, 32-bit offsets, LDS).
+int launch_seg(iga_ctx* c, const double* F, const double* B, int n, int K, long long lines, long long inner,
+               bool contig, const double* src, double* x, hipStream_t s)
+{
+    const int len = (int)(((long long)n + K - 1) / K);   // longest chunk
+    // the segment kernel addresses a wave's values with 32-bit offsets from the element
+    // of its first lane: at most (dO n + 1) inner + ((H - 1) nw kSeg + kSeg - 1) inner
+    // elements away, dO the number of line groups its lanes cross, H the halves
+    const int cap = iga::kSeg * iga::kSegMaxWaves;
+    const int H = len <= cap ? 1 : 2;
+    const int lpw = 64 / H;
+    const int nw = (len + H * iga::kSeg - 1) / (H * iga::kSeg);
+    const long long dO = std::min(lines / inner - 1, (lpw - 1 + inner - 1) / inner);
+    const long long span = (dO * n + 1) * inner + ((long long)(H - 1) * nw * iga::kSeg + iga::kSeg - 1) * inner;
+    // x-lines pass through a per-wave LDS stage, which has to fit one workgroup
+    const size_t stage = contig ? (size_t)nw * iga::kStageBytes : 0;
+    const size_t lds_static = (size_t)c->p * 64 * sizeof(double);
+    const bool lds_ok = stage == 0 || stage + lds_static <= (size_t)max_lds_per_block();
+    if (!(len <= 2 * cap && span * 8 < 0xffffffffLL && lds_ok)) return 1;
+    const dim3 grid((unsigned)((lines + lpw - 1) / lpw), (unsigned)K);
+    const unsigned threads = 64u * (unsigned)nw;
+#define IGA_SEG(PP, CC, HH)                                                                            \
+    do {                                                                                               \
+        seg_allow_lds<PP, CC, HH>(stage + lds_static);                                                 \
+        hipLaunchKernelGGL((iga::ads_seg_kernel<PP, CC, HH>), grid, dim3(threads), stage, s, F, B, n, K, \
+                           lines, inner, src, x);                                                      \
+    } while (0)
+    if (c->p == 2) {
+        if (H == 1) {
+            if (contig) IGA_SEG(2, true, 1); else IGA_SEG(2, false, 1);
+        } else {
+            if (contig) IGA_SEG(2, true, 2); else IGA_SEG(2, false, 2);
+        }
+    } else {
+        if (H == 1) {
+            if (contig) IGA_SEG(3, true, 1); else IGA_SEG(3, false, 1);
+        } else {
+            if (contig) IGA_SEG(3, true, 2); else IGA_SEG(3, false, 2);
+        }
+    }
+#undef IGA_SEG
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
+// x = (M_z (x) M_y (x) M_x)^{-1} b: the x family from b into x, then y and z in place.
 int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg = false)
 {
     const long long Nx = c->N[0], Ny = c->N[1], Nz = c->N[2];
@@ -842,47 +1029,18 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
     for (int a = 0; a < c->dim; ++a) {
         const double* src = a == 0 ? b : x;
         const int n = c->N[a];
+        if (!pg) {
+            const int K = part_chunks(n, lines[a]);
+            if (K > 0) {
+                IGA_TRY(launch_part(c, a, K, (int)lines[a], (int)inner[a], src, x, s));
+                continue;
+            }
+        }
         const double *F = nullptr, *B = nullptr;
         sweep_tables(c, pg, a, &F, &B);
-        // the segment kernel addresses a wave's values with 32-bit offsets from the element
-        // of its first lane: at most (dO n + 1) inner + ((H - 1) nw kSeg + kSeg - 1) inner
-        // elements away, dO the number of line groups its lanes cross, H the halves
-        const int cap = iga::kSeg * iga::kSegMaxWaves;
-        const int H = n <= cap ? 1 : 2;
-        const int lpw = 64 / H;
-        const int nw = (n + H * iga::kSeg - 1) / (H * iga::kSeg);
-        const long long dO = std::min(lines[a] / inner[a] - 1, (lpw - 1 + inner[a] - 1) / inner[a]);
-        const long long span =
-            (dO * n + 1) * inner[a] + ((long long)(H - 1) * nw * iga::kSeg + iga::kSeg - 1) * inner[a];
-        // x-lines pass through a per-wave LDS stage, which has to fit one workgroup
-        const bool contig = a == 0;
-        const size_t stage = contig ? (size_t)nw * iga::kStageBytes : 0;
-        const size_t lds_static = (size_t)c->p * 64 * sizeof(double);
-        const bool lds_ok = stage == 0 || stage + lds_static <= (size_t)max_lds_per_block();
-        if (n <= 2 * cap && span * 8 < 0xffffffffLL && lds_ok) {   // lines on chip
-            const unsigned grid = (unsigned)((lines[a] + lpw - 1) / lpw);
-            const unsigned threads = 64u * (unsigned)nw;
-#define IGA_SEG(PP, CC, HH)                                                                            \
-    do {                                                                                               \
-        seg_allow_lds<PP, CC, HH>(stage + lds_static);                                                 \
-        hipLaunchKernelGGL((iga::ads_seg_kernel<PP, CC, HH>), dim3(grid), dim3(threads), stage, s, F, B, \
-                           n, lines[a], inner[a], src, x);                                             \
-    } while (0)
-            if (c->p == 2) {
-                if (H == 1) {
-                    if (contig) IGA_SEG(2, true, 1); else IGA_SEG(2, false, 1);
-                } else {
-                    if (contig) IGA_SEG(2, true, 2); else IGA_SEG(2, false, 2);
-                }
-            } else {
-                if (H == 1) {
-                    if (contig) IGA_SEG(3, true, 1); else IGA_SEG(3, false, 1);
-                } else {
-                    if (contig) IGA_SEG(3, true, 2); else IGA_SEG(3, false, 2);
-                }
-            }
-#undef IGA_SEG
-            IGA_HIP(hipGetLastError());
+        const int rc = launch_seg(c, F, B, n, 1, lines[a], inner[a], a == 0, src, x, s);
+        if (rc != 1) {
+            IGA_TRY(rc);
             continue;
         }
         const unsigned grid = (unsigned)((lines[a] + iga::kAdsBlock - 1) / iga::kAdsBlock);

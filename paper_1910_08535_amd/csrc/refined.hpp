@@ -92,55 +92,16 @@ __global__ void refined_tables_kernel(AxisSet set, int3 rho3)
 }
 
 // Banded LU (no pivoting) of one axis' PG mass factor, one thread: A = L U with L unit
-// lower and U upper, both of bandwidth P.  Writes the sweep tables of the solve:
-//   F[r] = [L(r, r-P), ..., L(r, r-1), 1],   B[r] = [U(r, r+1) d_r, ..., U(r, r+P) d_r, d_r],
-// d_r = 1 / U(r, r), and kFactorPad zero rows after each.
+// lower and U upper, both of bandwidth P, into the sweep tables of the solve
+// (F[r] = [L(r, r-P), ..., L(r, r-1), 1], B[r] = [U(r, r+1) d_r, ..., U(r, r+P) d_r, d_r],
+// d_r = 1 / U(r, r)), and kFactorPad zero rows after each.
 template <int P>
 __global__ void lu_band_kernel(const double* __restrict__ A, int N, double* __restrict__ F,
                                double* __restrict__ B)
 {
-    constexpr int W = 2 * P + 1, FR = P + 1;
+    constexpr int FR = P + 1;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double ur[P][P + 1];   // rows r-P .. r-1 of U: ur[j][k] = U(r-P+j, r-P+j+k)
-    for (int j = 0; j < P; ++j)
-        for (int k = 0; k <= P; ++k) ur[j][k] = 0.0;
-    for (int r = 0; r < N; ++r) {
-        const double* ar = A + (size_t)r * W;   // ar[c - r + P] = A(r, c)
-        double l[P];
-        for (int k = 0; k < P; ++k) {           // column c = r - P + k < r
-            const int c = r - P + k;
-            if (c < 0) {
-                l[k] = 0.0;
-                continue;
-            }
-            double s = ar[k];
-            for (int m = 0; m < k; ++m) {       // rows r - P + m < c with U(., c) in band
-                const int row = r - P + m;
-                if (row < 0 || c - row > P) continue;
-                s = fma(-l[m], ur[m][c - row], s);
-            }
-            l[k] = s / ur[k][0];
-        }
-        double u[P + 1];
-        for (int k = 0; k <= P; ++k) {          // column c = r + k
-            const int c = r + k;
-            double s = ar[P + k];
-            for (int m = 0; m < P; ++m) {
-                const int row = r - P + m;
-                if (row < 0 || c - row > P) continue;
-                s = fma(-l[m], ur[m][c - row], s);
-            }
-            u[k] = c < N ? s : 0.0;
-        }
-        const double d = 1.0 / u[0];
-        for (int k = 0; k < P; ++k) F[(size_t)r * FR + k] = l[k];
-        F[(size_t)r * FR + P] = 1.0;
-        for (int j = 1; j <= P; ++j) B[(size_t)r * FR + j - 1] = u[j] * d;
-        B[(size_t)r * FR + P] = d;
-        for (int j = 0; j + 1 < P; ++j)
-            for (int k = 0; k <= P; ++k) ur[j][k] = ur[j + 1][k];
-        for (int k = 0; k <= P; ++k) ur[P - 1][k] = u[k];
-    }
+    lu_rows<P>(A, 0, N, F, B);
     for (int i = 0; i < kFactorPad * FR; ++i) F[(size_t)N * FR + i] = B[(size_t)N * FR + i] = 0.0;
 }
 

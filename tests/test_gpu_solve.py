@@ -61,6 +61,10 @@ SOLVE_CASES = [
     (3, 3, (1000, 20, 12), None, None),            # long x-lines beside short y and z lines
     (2, 2, (1024, 1024), None, None),              # lines of two halves in both families
     (2, 3, (1300, 50), (0.0, 0.0), (2.0, 1.0)),
+    (1, 2, (5000,), (0.0,), (2.0,)),               # one line: partitioned into chunks
+    (1, 3, (128,), None, None),                    # two chunks, the second longer
+    (2, 3, (4, 300), None, None),                  # y-lines partitioned, x-lines not
+    (2, 3, (70, 500), (0.0, -1.0), (1.0, 1.0)),    # y-lines in chunks of the segment kernel
 ]
 
 
@@ -164,4 +168,20 @@ def test_galerkin_step_quadratic_full_size(torch, iga, dim, p, ne):
     mesh.galerkin_step(u, dt, form=iga.GALERKIN_LAPLACIAN, nsteps=2)
     d = u.cpu().numpy() - u0
     assert np.max(np.abs(d - 2 * 2 * dim * dt)) < 1e-11
+    mesh.close()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_solve_1d_long_undoes_mass(torch, iga, p):
+    """10^6 elements in 1D (one line of 10^6 + p rows, solved in chunks): the solve of the
+    GPU mass rows of u gives u back."""
+    ne = (1000000,)
+    print(f"solve 1D long p={p}", flush=True)
+    mesh = _mesh(iga, 1, p, ne)
+    u = torch.randn(mesh.coef_shape(), dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(25))
+    m, _ = mesh.apply(iga.GALERKIN_LAPLACIAN, u, lap=False)
+    back = mesh.solve(m)
+    err = ((back - u).norm() / u.norm()).item()
+    assert err < TOL, err
     mesh.close()
