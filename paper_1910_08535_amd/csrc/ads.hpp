@@ -448,16 +448,21 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
     };
     double v[S];
     if constexpr (CONTIG) {
-        // x-lines (inner = 1).  Rows past the end of a line are read too (the next line's,
-        // or zeros past the end of the buffer) and cleared below; lines past the last are
-        // read the same way and never stored.
+        // x-lines (inner = 1).  Pairs that start past the end of a line, and lines past the
+        // last, are not read (their stage slots keep stale values, cleared below or never
+        // stored); the second row of a pair that ends a line is read and cleared.
 #pragma unroll
         for (int c = 0; c < S / kStageRows; ++c) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rb, (__attribute__((address_space(3))) void*)(stg + 1024 * q), 16,
-                    (int)(seg_off(8 * q + ga) + 16u * gj), c * kStageRows * 8, 0, 0);
+            for (int q = 0; q < 8; ++q) {
+                const int L = 8 * q + ga;
+                const bool rd = t0 + L % LPW < lines &&
+                                c * kStageRows + 2 * gj <= len - 1 - ((L / LPW) * nw + w) * S;
+                if (rd)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rb, (__attribute__((address_space(3))) void*)(stg + 1024 * q), 16,
+                        (int)(seg_off(L) + 16u * gj), c * kStageRows * 8, 0, 0);
+            }
             wait_vm_all();
             wave_lds_order();
 #pragma unroll
