@@ -407,9 +407,10 @@ __global__ __launch_bounds__(64 * kSegMaxWaves) void ads_seg_kernel(const double
     const long long tl = live ? t : lines - 1;
     const long long o = tl / inner, i = tl - o * inner;
     const long long o0 = t0 / inner, i0 = t0 - o0 * inner;
-    // rows [cb, cb + len) of the lines (the whole lines when K = 1)
-    const int cb = (int)(((long long)blockIdx.y * n) / K);
-    const int len = (int)(((long long)(blockIdx.y + 1) * n) / K) - cb;
+    // rows [cb, cb + len) of the lines (the whole lines when K = 1; the host keeps
+    // (K + 1) n below 2^32)
+    const int cb = (int)(blockIdx.y * (unsigned)n / (unsigned)K);
+    const int len = (int)((blockIdx.y + 1u) * (unsigned)n / (unsigned)K) - cb;
     F += (size_t)cb * FR;
     B += (size_t)cb * FR;
     // rows of this lane: [r0, r0 + S); the wave's first half starts at rw

@@ -34,10 +34,11 @@
 
 namespace iga {
 
-// First row of chunk k (k = K: n).
+// First row of chunk k (k = K: n), in 32-bit arithmetic: the host keeps (K + 1) n below
+// 2^32.
 __host__ __device__ inline int part_start(int k, int n, int K)
 {
-    return (int)(((long long)k * n) / K);
+    return (int)((unsigned)k * (unsigned)n / (unsigned)K);
 }
 
 // Chunk LU factors: thread k factorizes rows [s_k, e_k) of A on their own; thread 0 also
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restr
         const int g = blockIdx.x * kCorrRows + u;
         if (g >= rows) break;
         const int o = g / n, r = g - o * n;
-        const int k = (int)(((long long)(r + 1) * K + n - 1) / n) - 1;   // s_k <= r < e_k
+        const int k = (int)(((unsigned)(r + 1) * (unsigned)K + (unsigned)n - 1u) / (unsigned)n) - 1;   // s_k <= r < e_k
         const int t = o * inner + i;
         double v = xv[u];
         if (k < K - 1) {

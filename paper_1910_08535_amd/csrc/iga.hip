@@ -859,8 +859,11 @@ int part_chunks(int n, long long lines)
         while ((long long)m * m < 3LL * n && m < 8192) m *= 2;
         K = n / m;
     }
-    // grid rows of the chunks, and the reduced sweeps of one line in at most 64 KiB of LDS
-    if (K < 2 || n / K < 64 || K > 65535 || (long long)(K - 1) * 6 * 8 > 65536) return 0;
+    // grid rows of the chunks, the reduced sweeps of one line in at most 64 KiB of LDS, and
+    // the kernels' 32-bit chunk arithmetic
+    if (K < 2 || n / K < 64 || K > 65535 || (long long)(K - 1) * 6 * 8 > 65536 ||
+        (long long)(K + 1) * n >= (1LL << 32))
+        return 0;
     return K;
 }
 
