@@ -80,9 +80,55 @@ def cpu_baseline(args) -> dict:
         orc.rhs(pb, orc.PG, u, beta=1.0)
         dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
-    return {"value": GP_C2 / best, "unit": "GP/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": "full 1024x1024 p=2 workload (mass and Laplacian PG rows), best of 3 runs, "
-                      f"{best:.3f} s each"}
+    out = {"value": GP_C2 / best, "unit": "GP/s", "cores": orc.num_threads(), "kind": "oracle",
+           "sample": "full 1024x1024 p=2 workload (mass and Laplacian PG rows), best of 3 runs, "
+                     f"{best:.3f} s each"}
+    if not args.no_cpu_others:
+        out["other_workloads"] = cpu_others()
+    return out
+
+
+def cpu_others() -> dict:
+    """The oracle on bounded samples of the other workloads, in Gauss points per second
+    (each about a few seconds on the host cores): the 1D Laplace rows (all forms), one
+    explicit step of the 3D heat problem at 64^3 (the 128^3 step takes 20-50 s), and the
+    first 8 problems of the batched draw."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_1910_08535_amd import inputs
+    res = {}
+    c1 = inputs.Laplace1D()
+    pb = orc.Problem(dim=1, p=c1.p, ne=(c1.ne,), nq=(c1.nq,))
+    u = np.random.default_rng(c1.seed).standard_normal(pb.coef_shape())
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for form in (orc.GALERKIN_BYPARTS, orc.GALERKIN_LAPLACIAN, orc.PG):
+            orc.rhs(pb, form, u, alpha=1.0)
+    dt = time.perf_counter() - t0
+    res["c1_laplace_1d"] = {"GPs": 3 * reps * c1.ne * c1.nq / dt,
+                            "sample": f"64 elements, p=2: RHS rows of the three forms x {reps}"}
+    c3 = inputs.Heat3D()
+    ne = (64, 64, 64)
+    pb = orc.Problem(dim=3, p=c3.p, ne=ne, nq=c3.nq)
+    u = inputs.normal_coefs(ne, c3.p, c3.seed)
+    t0 = time.perf_counter()
+    orc.explicit_step(pb, u, c3.dt, sin_amp=c3.sin_amp, nsteps=1)
+    dt = time.perf_counter() - t0
+    res["c3_heat_3d"] = {"GPs": 64 ** 3 * 4 ** 3 / dt,
+                         "sample": f"one explicit step at 64^3, p=3, 4^3 Gauss: {dt:.2f} s"}
+    jobs, coefs = inputs.batch_jobs()
+    gp, t0 = 0, time.perf_counter()
+    for job, cf in zip(jobs[:8], coefs[:8]):
+        pb = orc.Problem(dim=2, p=job.p, ne=job.ne, nq=(job.p + 1, job.p + 1))
+        orc.rhs(pb, orc.PG, cf, alpha=1.0)
+        orc.rhs(pb, orc.PG, cf, beta=1.0)
+        gp += job.ne[0] * job.ne[1] * (job.p + 1) ** 2
+    dt = time.perf_counter() - t0
+    res["c4_batched"] = {"GPs": gp / dt,
+                         "sample": f"first 8 of the 256 problems, mass and Laplacian rows each: {dt:.2f} s"}
+    return res
 
 
 def run_c2(args):
@@ -518,6 +564,8 @@ def main():
     ap.add_argument("--rotate-mb", type=int, default=600,
                     help="distinct buffer bytes cycled through (defeats the Infinity Cache)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-others", action="store_true",
+                    help="time the oracle on the C2 workload only")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batched leg")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--no-heat3d", action="store_true", help="skip the 3D explicit-step leg")
