@@ -263,18 +263,19 @@ __host__ __device__ constexpr int part_table_doubles(int K)
     return (K - 1) * (2 * 4 * P * P + P * P);
 }
 
-template <int P>
+template <int P, bool STAGED>
 __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restrict__ G,
                                                          const double* __restrict__ Dinv,
                                                          const double* __restrict__ V, int n, int K,
-                                                         int lines, int inner, int staged,
+                                                         int lines, int inner,
                                                          const double* __restrict__ x, double* __restrict__ Z)
 {
+    constexpr bool staged = STAGED;
     constexpr int Q = 2 * P;
     extern __shared__ double part_y[];
     const int T = blockDim.x, tid = threadIdx.x;
     double* const tabs = part_y;
-    if (staged) {
+    if constexpr (staged) {
         // eight entries per thread in flight at a time: [Gamma | Delta^-1 | V^T]
         const int nq = (K - 1) * Q * Q, nt = 2 * nq + (K - 1) * P * P;
         for (int j0 = 0; j0 < nt; j0 += 8 * T) {
@@ -302,14 +303,21 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
     const int o = t / inner, i = t - o * inner;
     const size_t base = (size_t)o * n * inner + i;
     double* yl = part_y + (staged ? part_table_doubles<P>(K) : 0) + tid;
-    // block tables, from LDS or memory (the same for every thread; read through vector
-    // registers, a zero the compiler cannot see through, as scalar registers do not hold
-    // them)
+    // block tables, from LDS (a pointer known to be LDS, so the reads are LDS reads) or
+    // from memory (the same for every thread; read through vector registers, a zero the
+    // compiler cannot see through, as scalar registers do not hold them)
     int vz;
     asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
-    const double* Gp = staged ? tabs + vz : G + vz;
-    const double* Dp = staged ? tabs + (K - 1) * Q * Q + vz : Dinv + vz;
-    const double* VTs = tabs + 2 * (K - 1) * Q * Q + vz;
+    const double* Gp;
+    const double* Dp;
+    if constexpr (staged) {
+        Gp = tabs;
+        Dp = tabs + (K - 1) * Q * Q;
+    } else {
+        Gp = G + vz;
+        Dp = Dinv + vz;
+    }
+    const double* VTs = tabs + 2 * (K - 1) * Q * Q;
     V += vz;
     constexpr int KB = 16;   // steps whose h is loaded together
     for (int k0 = 0; k0 + 1 < K; k0 += KB) {
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
         const int kn = k > 0 ? k - 1 : k;
 #pragma unroll
         for (int q = 0; q < Q * Q; ++q) dn[q] = Dp[(size_t)kn * Q * Q + q];
-        if (staged) {
+        if constexpr (staged) {
 #pragma unroll
             for (int q = 0; q < P * P; ++q) vn[q] = VTs[(size_t)kn * P * P + q];
         } else {

@@ -961,15 +961,23 @@ int launch_part(iga_ctx* c, int a, int K, int lines, int inner, const double* sr
     if (p == 2) {
         if (!local_done)
             hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, n, K, lines, inner, src, x);
-        hipLaunchKernelGGL(iga::part_reduce_kernel<2>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K, lines, inner,
-                           staged, (const double*)x, c->part_z);
+        if (staged)
+            hipLaunchKernelGGL((iga::part_reduce_kernel<2, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+                               lines, inner, (const double*)x, c->part_z);
+        else
+            hipLaunchKernelGGL((iga::part_reduce_kernel<2, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+                               lines, inner, (const double*)x, c->part_z);
         hipLaunchKernelGGL(iga::part_correct_kernel<2>, g3, b3, 0, s, V, Wt, n, K, lines, inner, rows,
                            (const double*)c->part_z, x);
     } else {
         if (!local_done)
             hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, n, K, lines, inner, src, x);
-        hipLaunchKernelGGL(iga::part_reduce_kernel<3>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K, lines, inner,
-                           staged, (const double*)x, c->part_z);
+        if (staged)
+            hipLaunchKernelGGL((iga::part_reduce_kernel<3, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+                               lines, inner, (const double*)x, c->part_z);
+        else
+            hipLaunchKernelGGL((iga::part_reduce_kernel<3, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+                               lines, inner, (const double*)x, c->part_z);
         hipLaunchKernelGGL(iga::part_correct_kernel<3>, g3, b3, 0, s, V, Wt, n, K, lines, inner, rows,
                            (const double*)c->part_z, x);
     }
