@@ -409,12 +409,13 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
     }
 }
 
-// Step 3: x -= V[r] t_{k+1} + Wt[r] u_{k-1} on every value.  x-lines (inner = 1): a
-// workgroup per (chunk, line) = (blockIdx.x, blockIdx.y), its threads over the chunk's
-// rows.  Other families: a workgroup per (kCorrRows rows of line groups, inner block) =
-// (blockIdx.x, blockIdx.y), its threads over the inner index, each thread taking those
-// rows.  The chunk of a row is uniform across the workgroup, so no thread divides.
-constexpr int kCorrRows = 4;
+// Step 3: x -= V[r] t_{k+1} + Wt[r] u_{k-1} on every value, kCorr values per thread with
+// every load issued before the first is used.  x-lines (inner = 1): a workgroup per
+// (chunk, kCorr lines) = (blockIdx.x, blockIdx.y), its threads over the chunk's rows.
+// Other families: a workgroup per (kCorr rows of line groups, inner block) =
+// (blockIdx.x, blockIdx.y), its threads over the inner index.  The chunk of a row is
+// uniform across the workgroup, so no thread divides.
+constexpr int kCorr = 4;
 template <int P>
 __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restrict__ V,
                                                            const double* __restrict__ Wt, int n, int K,
@@ -423,51 +424,66 @@ __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restr
 {
     constexpr int Q = 2 * P;
     if (inner == 1) {
-        const int k = blockIdx.x, o = blockIdx.y;
-        double zt[P], zu[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            zt[j] = k < K - 1 ? Z[((size_t)k * Q + P + j) * lines + o] : 0.0;
-            zu[j] = k > 0 ? Z[((size_t)(k - 1) * Q + j) * lines + o] : 0.0;
-        }
+        const int k = blockIdx.x, o0 = blockIdx.y * kCorr;
         const int r1 = part_start(k + 1, n, K);
+        double zt[kCorr][P], zu[kCorr][P];
+#pragma unroll
+        for (int u = 0; u < kCorr; ++u) {
+            const int o = min(o0 + u, lines - 1);
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                zt[u][j] = k < K - 1 ? Z[((size_t)k * Q + P + j) * lines + o] : 0.0;
+                zu[u][j] = k > 0 ? Z[((size_t)(k - 1) * Q + j) * lines + o] : 0.0;
+            }
+        }
         for (int r = part_start(k, n, K) + threadIdx.x; r < r1; r += blockDim.x) {
-            const size_t idx = (size_t)o * n + r;
-            double v = x[idx];
+            double vr[P], wr[P], xv[kCorr];
 #pragma unroll
-            for (int j = 0; j < P; ++j) v = fma(-V[(size_t)r * P + j], zt[j], v);
+            for (int j = 0; j < P; ++j) {
+                vr[j] = V[(size_t)r * P + j];
+                wr[j] = Wt[(size_t)r * P + j];
+            }
 #pragma unroll
-            for (int j = 0; j < P; ++j) v = fma(-Wt[(size_t)r * P + j], zu[j], v);
-            x[idx] = v;
+            for (int u = 0; u < kCorr; ++u) xv[u] = x[(size_t)min(o0 + u, lines - 1) * n + r];
+#pragma unroll
+            for (int u = 0; u < kCorr; ++u) {
+                double v = xv[u];
+#pragma unroll
+                for (int j = 0; j < P; ++j) v = fma(-vr[j], zt[u][j], v);
+#pragma unroll
+                for (int j = 0; j < P; ++j) v = fma(-wr[j], zu[u][j], v);
+                if (o0 + u < lines) x[(size_t)(o0 + u) * n + r] = v;
+            }
         }
         return;
     }
     const int i = blockIdx.y * blockDim.x + threadIdx.x;
     if (i >= inner) return;
-    double xv[kCorrRows];
+    double xv[kCorr], zt[kCorr][P], zu[kCorr][P], vr[kCorr][P], wr[kCorr][P];
+    size_t idx[kCorr];
 #pragma unroll
-    for (int u = 0; u < kCorrRows; ++u) {
-        const int g = min(blockIdx.x * kCorrRows + u, rows - 1), o = g / n, r = g - o * n;
-        xv[u] = x[((size_t)o * n + r) * inner + i];
-    }
-#pragma unroll
-    for (int u = 0; u < kCorrRows; ++u) {
-        const int g = blockIdx.x * kCorrRows + u;
-        if (g >= rows) break;
-        const int o = g / n, r = g - o * n;
+    for (int u = 0; u < kCorr; ++u) {
+        const int g = min(blockIdx.x * kCorr + u, rows - 1), o = g / n, r = g - o * n;
         const int k = (int)(((unsigned)(r + 1) * (unsigned)K + (unsigned)n - 1u) / (unsigned)n) - 1;   // s_k <= r < e_k
         const int t = o * inner + i;
+        idx[u] = ((size_t)o * n + r) * inner + i;
+        xv[u] = x[idx[u]];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            zt[u][j] = k < K - 1 ? Z[((size_t)k * Q + P + j) * lines + t] : 0.0;
+            zu[u][j] = k > 0 ? Z[((size_t)(k - 1) * Q + j) * lines + t] : 0.0;
+            vr[u][j] = V[(size_t)r * P + j];
+            wr[u][j] = Wt[(size_t)r * P + j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kCorr; ++u) {
         double v = xv[u];
-        if (k < K - 1) {
 #pragma unroll
-            for (int j = 0; j < P; ++j) v = fma(-V[(size_t)r * P + j], Z[((size_t)k * Q + P + j) * lines + t], v);
-        }
-        if (k > 0) {
+        for (int j = 0; j < P; ++j) v = fma(-vr[u][j], zt[u][j], v);
 #pragma unroll
-            for (int j = 0; j < P; ++j)
-                v = fma(-Wt[(size_t)r * P + j], Z[((size_t)(k - 1) * Q + j) * lines + t], v);
-        }
-        x[((size_t)o * n + r) * inner + i] = v;
+        for (int j = 0; j < P; ++j) v = fma(-wr[u][j], zu[u][j], v);
+        if (blockIdx.x * kCorr + u < (unsigned)rows) x[idx[u]] = v;
     }
 }
 

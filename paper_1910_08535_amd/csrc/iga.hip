@@ -944,10 +944,10 @@ int launch_part(iga_ctx* c, int a, int K, int lines, int inner, const double* sr
     const int rows = (lines / inner) * n;   // rows of the line groups (inner > 1)
     if (inner == 1) {
         const int longest = (n + K - 1) / K;
-        g3 = dim3((unsigned)K, (unsigned)lines);
+        g3 = dim3((unsigned)K, (unsigned)((lines + iga::kCorr - 1) / iga::kCorr));
         b3 = dim3((unsigned)std::min(256, (longest + 63) / 64 * 64));
     } else {
-        g3 = dim3((unsigned)((rows + iga::kCorrRows - 1) / iga::kCorrRows), (unsigned)((inner + 255) / 256));
+        g3 = dim3((unsigned)((rows + iga::kCorr - 1) / iga::kCorr), (unsigned)((inner + 255) / 256));
         b3 = dim3(256);
     }
     bool local_done = false;
