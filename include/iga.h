@@ -189,7 +189,10 @@ int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, i
    (y, z) line, then along y, then along z.  Each M_a (bandwidth p, symmetric positive
    definite) is factorized once, M_a = L_a L_a^T, at the context's first solve (kernels
    on its stream; the factors stay with the context), and every solve runs a forward and
-   a backward substitution along every line.
+   a backward substitution along every line.  Axes with few lines (1D, and 2D up to a
+   few thousand lines) are solved in chunks instead: the chunks' own factors, the
+   coupling between neighbouring chunks and a small block system per line, all built
+   once per context, give the same solution to rounding.
    b, x: device coefficient arrays (N_z, N_y, N_x); x may equal b (in place); b is not
    modified unless x == b.  form: IGA_GALERKIN_BYPARTS or IGA_GALERKIN_LAPLACIAN (one
    mass matrix for both).
