@@ -253,10 +253,11 @@ __global__ __launch_bounds__(256) void part_local_kernel(const double* __restric
 // Step 2: one thread per line, T lines per workgroup.  With `staged` the workgroup first
 // copies the block tables (Gamma_k, Delta_k^{-1} and V_{k+1}^T for every k) into LDS, so
 // that the sweeps wait on no memory; otherwise they read them from memory a step ahead.
-// Each thread then reads all its h_k = x rows e_k - P .. e_k + P - 1 (k = 0 .. K-2) into
-// LDS, sixteen steps' loads at once, runs the forward sweep there (y_k replaces h_k) and the
-// backward sweep, which writes zeta_k to Z (entry (k, q) of line t at
-// Z[(k 2P + q) lines + t]).  LDS: [tables: (K-1) (2 (2P)^2 + P^2) if staged | T (K-1) 2P].
+// Each thread reads all its h_k = x rows e_k - P .. e_k + P - 1 (k = 0 .. K-2) into LDS,
+// sixteen steps' loads at once (the first sixteen beside the table loads), runs the
+// forward sweep there (y_k replaces h_k) and the backward sweep, which writes zeta_k to Z
+// (entry (k, q) of line t at Z[(k 2P + q) lines + t]).
+// LDS: [tables: (K-1) (2 (2P)^2 + P^2) if staged | T (K-1) 2P].
 template <int P>
 __host__ __device__ constexpr int part_table_doubles(int K)
 {
@@ -275,6 +276,19 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
     extern __shared__ double part_y[];
     const int T = blockDim.x, tid = threadIdx.x;
     double* const tabs = part_y;
+    const int t = blockIdx.x * T + tid;
+    const int tc = min(t, lines - 1);   // lines past the last load the last one's values
+    const int o = tc / inner, i = tc - o * inner;
+    const size_t base = (size_t)o * n * inner + i;
+    constexpr int KB = 16;   // steps whose h is loaded together
+    // h of the first KB steps, in flight together with the table loads below
+    double hb[KB][Q];
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+        const int e = part_start(min(kk, K - 2) + 1, n, K);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
+    }
     if constexpr (staged) {
         // eight entries per thread in flight at a time: [Gamma | Delta^-1 | V^T]
         const int nq = (K - 1) * Q * Q, nt = 2 * nq + (K - 1) * P * P;
@@ -298,10 +312,7 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
         }
         __syncthreads();
     }
-    const int t = blockIdx.x * T + tid;
     if (t >= lines) return;   // no barrier below: each thread uses its own LDS column
-    const int o = t / inner, i = t - o * inner;
-    const size_t base = (size_t)o * n * inner + i;
     double* yl = part_y + (staged ? part_table_doubles<P>(K) : 0) + tid;
     // block tables, from LDS (a pointer known to be LDS, so the reads are LDS reads) or
     // from memory (the same for every thread; read through vector registers, a zero the
@@ -319,14 +330,14 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
     }
     const double* VTs = tabs + 2 * (K - 1) * Q * Q;
     V += vz;
-    constexpr int KB = 16;   // steps whose h is loaded together
     for (int k0 = 0; k0 + 1 < K; k0 += KB) {
-        double hb[KB][Q];
+        if (k0 > 0) {
 #pragma unroll
-        for (int kk = 0; kk < KB; ++kk) {
-            const int e = part_start(min(k0 + kk, K - 2) + 1, n, K);
+            for (int kk = 0; kk < KB; ++kk) {
+                const int e = part_start(min(k0 + kk, K - 2) + 1, n, K);
 #pragma unroll
-            for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
+                for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
+            }
         }
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk)
