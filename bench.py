@@ -352,9 +352,11 @@ def run_ads(args) -> dict:
     once per mesh, outside the timed region).  Also one consistent-mass Galerkin Euler step
     of the 3D heat workload (128^3, p = 3; the step is unstable at dt = 1e-6, so only its
     time is reported), and the refined-test-space PG projection (256^3, p = 2, refine 4):
-    the sine rows and the solve with the LU factors of its square PG mass.  Every call is timed with HIP events on the mesh's stream over
-    `reps` calls after two warm-up calls.  Algorithmic HBM bytes of a solve: each of the
-    three families reads and writes every coefficient once, 48 B per coefficient."""
+    the sine rows and the solve with the LU factors of its square PG mass.  The solve of
+    families with few lines, partitioned into chunks, at 2D 1024^2 and 1D 10^6 elements
+    (p = 2; b = N(0,1), seed 21).  Every call is timed with HIP events on the mesh's
+    stream over `reps` calls after two warm-up calls.  Algorithmic HBM bytes of a solve:
+    each family reads and writes every coefficient once, 16 B per coefficient and axis."""
     import torch
     from paper_1910_08535_amd import iga
 
@@ -406,13 +408,27 @@ def run_ads(args) -> dict:
             "solve_hbm_frac": 48.0 * n / t_solve / (HBM_PEAK_GBS * 1e9)}
         mesh.close()
         del b, u
+    # families with few lines: the partitioned solve
+    for dim, ne in ((2, (1024, 1024)), (1, (1000000,))):
+        mesh = iga.Mesh(dim, 2, ne, (3,) * dim, stream=stream)
+        g = torch.Generator(device="cuda").manual_seed(21)
+        b = torch.randn(mesh.coef_shape(), dtype=torch.float64, device="cuda", generator=g)
+        u = torch.empty_like(b)
+        n = b.numel()
+        t_solve = timed(lambda: mesh.solve(b, out=u))
+        key = f"solve_{dim}d_{ne[0]}_p2"
+        out[key] = {"dofs": n, "us_solve": t_solve * 1e6, "dofs_per_s_solve": n / t_solve,
+                    "solve_hbm_frac": 16.0 * dim * n / t_solve / (HBM_PEAK_GBS * 1e9)}
+        mesh.close()
+        del b, u
     mesh = iga.Mesh(3, 3, (128, 128, 128), (4, 4, 4), stream=stream)
     u = torch.zeros(mesh.coef_shape(), dtype=torch.float64, device="cuda")
     t_step = timed(lambda: mesh.galerkin_step(u, 1e-6, iga.GALERKIN_LAPLACIAN, sin_amp=1.0))
     out["galerkin_step_128_p3"] = {"us_per_step": t_step * 1e6,
                                    "GPs": 128 ** 3 * 64 / t_step}
     mesh.close()
-    out["kernel"] = "iga::ads_seg_kernel<P> (one launch per axis)"
+    out["kernel"] = ("iga::ads_seg_kernel<P> (one launch per axis); families with few lines: "
+                     "chunk solves, iga::part_reduce_kernel, iga::part_correct_kernel")
     return out
 
 
