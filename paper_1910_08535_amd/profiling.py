@@ -59,10 +59,11 @@ def stats_markdown(stats_csv: str, out_md: str, command: str) -> None:
         fh.write("\n".join(lines) + "\n")
 
 
-def _per_dispatch(csv_path: str, counter: str):
+def _per_dispatch(csv_path: str, counter: str, grid: str = ""):
+    """Counter values per kernel name, of the dispatches with that grid size if given."""
     vals = {}
     for r in csv.DictReader(open(csv_path)):
-        if r["Counter_Name"] != counter:
+        if r["Counter_Name"] != counter or (grid and r["Grid_Size"] != grid):
             continue
         vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return vals
@@ -77,8 +78,13 @@ def _family(kernel: str) -> str:
 
 def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, workload: str,
             commands: str) -> dict:
-    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
-    write = _per_dispatch(write_csv, "WRITE_SIZE")
+    """HBM bytes per launch of `kernel` ("name" or "name@grid size", the grid size in
+    threads picking one launch shape of a kernel that runs at several)."""
+    kernel, _, grid = kernel.partition("@")
+    fetch_all = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write_all = _per_dispatch(write_csv, "WRITE_SIZE")
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE", grid)
+    write = _per_dispatch(write_csv, "WRITE_SIZE", grid)
 
     def pick(vals, needle):
         keys = [k for k in vals if needle in k]
@@ -88,15 +94,15 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, worklo
 
     copy_bytes = copy_mib * 2**20
     # the copy kernel is the largest-traffic elementwise kernel of the probe
-    cf = max(v for k, vs in fetch.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
-    cw = max(v for k, vs in write.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
+    cf = max(v for k, vs in fetch_all.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
+    cw = max(v for k, vs in write_all.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
     f_scale = copy_bytes / (cf * 1024.0)
     w_scale = copy_bytes / (cw * 1024.0)
     kf, fv = pick(fetch, kernel)
     kw, wv = pick(write, kernel)
     fb = statistics.median(fv) * 1024.0 * f_scale
     wb = statistics.median(wv) * 1024.0 * w_scale
-    rec = {"workload": workload, "kernel": kf, "dispatches": [len(fv), len(wv)],
+    rec = {"workload": workload, "kernel": kf, "grid_size": grid or None, "dispatches": [len(fv), len(wv)],
            "fetch_kib_per_dispatch_median": statistics.median(fv),
            "write_kib_per_dispatch_median": statistics.median(wv),
            "copy_probe_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
