@@ -260,8 +260,11 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
             v0[i] = v.x;
             v1[i] = v.y;
         } else {
-            v0[i] = bload(ru, rowok && ok0 ? (rowoff + c0) * 8u : kOOB);
-            v1[i] = bload(ru, rowok && ok1 ? (rowoff + c0 + 1) * 8u : kOOB);
+            // rows of odd length: the pair is one 8-byte aligned 16-byte access; a lane whose
+            // second column lies past the row reads the pair ending at its first
+            const dv2 v = bload2(ru, rowok && ok0 ? (rowoff + (ok1 ? c0 : c0 - 1)) * 8u : kOOB);
+            v0[i] = ok1 ? v.x : v.y;
+            v1[i] = ok1 ? v.y : 0.0;
         }
         vh[i] = bload(ru, rowok && okh ? (rowoff + ch) * 8u : kOOB);
     }
