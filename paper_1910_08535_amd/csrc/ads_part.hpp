@@ -3,8 +3,10 @@
 // family), where one recurrence per line leaves most of the GPU idle.
 //
 // The 1D matrix A (n x n, bandwidth P, the same for every line of the family) is cut into
-// K chunks of rows [s_k, e_k), s_k = floor(k n / K), e_k = s_{k+1}, of at least 64 >= 2P
-// rows each.  With D the block diagonal of the chunks' own blocks A_kk,
+// K chunks of rows [s_k, e_k), e_k = s_{k+1}, of at least 64 >= 2P rows each (PartGeom):
+// balanced, s_k = floor(k n / K), or, for a single long line, interior chunks of exactly
+// m rows between a first and a last chunk of at most m rows, so that the interior chunks
+// have bitwise equal factors and run as the lines of one segment-kernel launch.  With D the block diagonal of the chunks' own blocks A_kk,
 // A = D (I + S), and the spikes of S are line-independent:
 //     V_k = A_kk^{-1} A(chunk k, first P columns of chunk k+1)     (e_k - s_k) x P
 //     W_k = A_kk^{-1} A(chunk k, last P columns of chunk k-1)      (e_k - s_k) x P
@@ -34,25 +36,37 @@
 
 namespace iga {
 
-// First row of chunk k (k = K: n), in 32-bit arithmetic: the host keeps (K + 1) n below
-// 2^32.
-__host__ __device__ inline int part_start(int k, int n, int K)
-{
-    return (int)((unsigned)k * (unsigned)n / (unsigned)K);
-}
+// Chunk geometry.  m = 0: balanced chunks, s_k = floor(k n / K) in 32-bit arithmetic
+// (the host keeps (K + 1) n below 2^32).  m > 0: s_0 = 0, s_k = f + (k-1) m for
+// 0 < k < K, s_K = n.
+struct PartGeom {
+    int n, K, f, m;
+    __host__ __device__ int start(int k) const
+    {
+        if (m == 0) return (int)((unsigned)k * (unsigned)n / (unsigned)K);
+        return k <= 0 ? 0 : (k >= K ? n : f + (k - 1) * m);
+    }
+    // the chunk of row r: s_k <= r < s_{k+1}
+    __host__ __device__ int chunk(int r) const
+    {
+        if (m == 0) return (int)(((unsigned)(r + 1) * (unsigned)K + (unsigned)n - 1u) / (unsigned)n) - 1;
+        return r < f ? 0 : min(1 + (r - f) / m, K - 1);
+    }
+};
 
 // Chunk LU factors: thread k factorizes rows [s_k, e_k) of A on their own; thread 0 also
 // writes the kFactorPad zero rows after row n that the segment kernel reads past the end.
 template <int P>
-__global__ void part_factor_kernel(const double* __restrict__ A, int n, int K, double* __restrict__ F,
+__global__ void part_factor_kernel(const double* __restrict__ A, PartGeom pg, double* __restrict__ F,
                                    double* __restrict__ B)
 {
+    const int n = pg.n, K = pg.K;
     constexpr int FR = P + 1;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
     if (k == 0)
         for (int i = 0; i < kFactorPad * FR; ++i) F[(size_t)n * FR + i] = B[(size_t)n * FR + i] = 0.0;
-    lu_rows<P>(A, part_start(k, n, K), part_start(k + 1, n, K), F, B);
+    lu_rows<P>(A, pg.start(k), pg.start(k + 1), F, B);
 }
 
 // Spikes: thread (k, side, j) solves A_kk v = column j of the coupling block (side 0: V_k,
@@ -60,15 +74,16 @@ __global__ void part_factor_kernel(const double* __restrict__ A, int n, int K, d
 // rows [s_k, e_k) of V or Wt (P doubles per row).  Spikes that do not exist (V of the last
 // chunk, W of the first) are written as zeros.
 template <int P>
-__global__ void part_spike_kernel(const double* __restrict__ A, int n, int K,
+__global__ void part_spike_kernel(const double* __restrict__ A, PartGeom pg,
                                   const double* __restrict__ F, const double* __restrict__ B,
                                   double* __restrict__ V, double* __restrict__ Wt)
 {
+    const int K = pg.K;
     constexpr int W = 2 * P + 1, FR = P + 1;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= K * 2 * P) return;
     const int j = id % P, side = (id / P) % 2, k = id / (2 * P);
-    const int s = part_start(k, n, K), e = part_start(k + 1, n, K);
+    const int s = pg.start(k), e = pg.start(k + 1);
     double* out = side == 0 ? V : Wt;
     const bool exists = side == 0 ? k < K - 1 : k > 0;
     double yw[P];
@@ -137,14 +152,15 @@ __device__ void small_inverse(double (&a)[Q][Q], double (&inv)[Q][Q])
 // Block LU of the reduced system (one thread): Gamma_k (k >= 1; Gamma_0 = 0) and
 // Delta_k^{-1} for k = 0 .. K-2, 2P x 2P each, row-major.
 template <int P>
-__global__ void part_reduce_setup_kernel(const double* __restrict__ V, const double* __restrict__ Wt, int n,
-                                         int K, double* __restrict__ G, double* __restrict__ Dinv)
+__global__ void part_reduce_setup_kernel(const double* __restrict__ V, const double* __restrict__ Wt,
+                                         PartGeom pg, double* __restrict__ G, double* __restrict__ Dinv)
 {
+    const int K = pg.K;
     constexpr int Q = 2 * P;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double prev[Q][Q];   // Delta_{k-1}^{-1}
     for (int k = 0; k + 1 < K; ++k) {
-        const int s = part_start(k, n, K), e = part_start(k + 1, n, K);
+        const int s = pg.start(k), e = pg.start(k + 1);
         double D[Q][Q];
         for (int i = 0; i < Q; ++i)
             for (int j = 0; j < Q; ++j) D[i][j] = i == j ? 1.0 : 0.0;
@@ -188,16 +204,17 @@ __global__ void part_reduce_setup_kernel(const double* __restrict__ V, const dou
 // t = o inner + i.  Rows are read eight at a time ahead of the recurrence.  dst may be src.
 template <int P>
 __global__ __launch_bounds__(256) void part_local_kernel(const double* __restrict__ F,
-                                                         const double* __restrict__ B, int n, int K,
+                                                         const double* __restrict__ B, PartGeom pg,
                                                          int lines, int inner, const double* src, double* dst)
 {
+    const int n = pg.n, K = pg.K;
     constexpr int FR = P + 1, U = 8;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= lines * K) return;
     const int t = id % lines, k = id / lines;
     const int o = t / inner, i = t - o * inner;
     const size_t base = (size_t)o * n * inner + i;
-    const int s = part_start(k, n, K), e = part_start(k + 1, n, K);
+    const int s = pg.start(k), e = pg.start(k + 1);
     double yw[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) yw[q] = 0.0;
@@ -267,10 +284,11 @@ __host__ __device__ constexpr int part_table_doubles(int K)
 template <int P, bool STAGED>
 __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restrict__ G,
                                                          const double* __restrict__ Dinv,
-                                                         const double* __restrict__ V, int n, int K,
+                                                         const double* __restrict__ V, PartGeom pg,
                                                          int lines, int inner,
                                                          const double* __restrict__ x, double* __restrict__ Z)
 {
+    const int n = pg.n, K = pg.K;
     constexpr bool staged = STAGED;
     constexpr int Q = 2 * P;
     extern __shared__ double part_y[];
@@ -285,7 +303,7 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
     double hb[KB][Q];
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
-        const int e = part_start(min(kk, K - 2) + 1, n, K);
+        const int e = pg.start(min(kk, K - 2) + 1);
 #pragma unroll
         for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
     }
@@ -303,7 +321,7 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
                     v[u] = Dinv[j - nq];
                 } else {
                     const int jj = j - 2 * nq, k = jj / (P * P), a = (jj / P) % P, b = jj % P;
-                    v[u] = V[(size_t)(part_start(k + 1, n, K) + a) * P + b];
+                    v[u] = V[(size_t)(pg.start(k + 1) + a) * P + b];
                 }
             }
 #pragma unroll
@@ -334,7 +352,7 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
         if (k0 > 0) {
 #pragma unroll
             for (int kk = 0; kk < KB; ++kk) {
-                const int e = part_start(min(k0 + kk, K - 2) + 1, n, K);
+                const int e = pg.start(min(k0 + kk, K - 2) + 1);
 #pragma unroll
                 for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
             }
@@ -392,7 +410,7 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
 #pragma unroll
             for (int q = 0; q < P * P; ++q) vn[q] = VTs[(size_t)kn * P * P + q];
         } else {
-            const int s1 = part_start(kn + 1, n, K);   // first row of chunk kn + 1
+            const int s1 = pg.start(kn + 1);   // first row of chunk kn + 1
 #pragma unroll
             for (int a = 0; a < P; ++a)
 #pragma unroll
@@ -429,14 +447,15 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
 constexpr int kCorr = 4;
 template <int P>
 __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restrict__ V,
-                                                           const double* __restrict__ Wt, int n, int K,
+                                                           const double* __restrict__ Wt, PartGeom pg,
                                                            int lines, int inner, int rows,
                                                            const double* __restrict__ Z, double* __restrict__ x)
 {
+    const int n = pg.n, K = pg.K;
     constexpr int Q = 2 * P;
     if (inner == 1) {
         const int k = blockIdx.x, o0 = blockIdx.y * kCorr;
-        const int r1 = part_start(k + 1, n, K);
+        const int r1 = pg.start(k + 1);
         double zt[kCorr][P], zu[kCorr][P];
 #pragma unroll
         for (int u = 0; u < kCorr; ++u) {
@@ -447,7 +466,7 @@ __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restr
                 zu[u][j] = k > 0 ? Z[((size_t)(k - 1) * Q + j) * lines + o] : 0.0;
             }
         }
-        for (int r = part_start(k, n, K) + threadIdx.x; r < r1; r += blockDim.x) {
+        for (int r = pg.start(k) + threadIdx.x; r < r1; r += blockDim.x) {
             double vr[P], wr[P], xv[kCorr];
 #pragma unroll
             for (int j = 0; j < P; ++j) {
@@ -475,7 +494,7 @@ __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restr
 #pragma unroll
     for (int u = 0; u < kCorr; ++u) {
         const int g = min(blockIdx.x * kCorr + u, rows - 1), o = g / n, r = g - o * n;
-        const int k = (int)(((unsigned)(r + 1) * (unsigned)K + (unsigned)n - 1u) / (unsigned)n) - 1;   // s_k <= r < e_k
+        const int k = pg.chunk(r);
         const int t = o * inner + i;
         idx[u] = ((size_t)o * n + r) * inner + i;
         xv[u] = x[idx[u]];

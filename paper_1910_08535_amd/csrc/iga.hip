@@ -75,9 +75,9 @@ struct iga_ctx {
     // of the LU factors of its square PG mass
     int refine[3] = {1, 1, 1};
     double* lu[3] = {nullptr, nullptr, nullptr};
-    // partitioned solve of the Galerkin mass along axes with few lines: chunk length and
-    // count, the tables F | B | V | Wt | Gamma | Delta^-1 per axis, and per-line scratch
-    int part_m[3] = {0, 0, 0}, part_K[3] = {0, 0, 0};
+    // partitioned solve of the Galerkin mass along axes with few lines: chunk geometry,
+    // the tables F | B | V | Wt | Gamma | Delta^-1 per axis, and per-line scratch
+    iga::PartGeom part_g[3] = {};
     double* part[3] = {nullptr, nullptr, nullptr};
     double* part_z = nullptr;
     size_t part_z_n = 0;
@@ -840,20 +840,31 @@ void seg_allow_lds(size_t bytes)
         (void)hipGetLastError();
 }
 
-// Chunk count K of the partitioned solve of a family of `lines` lines of n rows, or 0 when
-// the family keeps one recurrence per line: that is when its lines fill at least 128
+// Chunk geometry of the partitioned solve of a family of `lines` lines of n rows; K = 0
+// when the family keeps one recurrence per line: that is when its lines fill at least 128
 // workgroups of 64 lines (half the compute units), or when a chunk would have fewer than
-// 64 rows.  With lines enough for the lanes of a wave the chunks are solved by the
-// segment kernel, at most 96 rows (two waves) each.  Fewer lines (1D) take one thread
-// per chunk, of about sqrt(3 n) rows: a chunk's two substitutions then cost about as much
-// as a line's reduced sweeps (2 n / m steps of a 2P x 2P block).
-int part_chunks(int n, long long lines)
+// 64 rows.  With lines enough for the lanes of a wave the chunks are balanced and solved
+// by the segment kernel, at most 96 rows (two waves) each.  A single line of at least
+// 2 kLineChunk rows gets interior chunks of kLineChunk rows (bitwise equal factors: one
+// segment-kernel launch runs them as its lines) between a first and a last chunk of at
+// most kLineChunk rows.  Other families with few lines take one thread per balanced
+// chunk of about sqrt(3 n) rows: a chunk's two substitutions then cost about as much as
+// a line's reduced sweeps (2 n / m steps of a 2P x 2P block).
+constexpr int kLineChunk = 1536;
+iga::PartGeom part_geom(int n, long long lines)
 {
+    iga::PartGeom g{n, 0, 0, 0};
     const long long total = lines * n;
-    if (total >= (1LL << 31) || (lines + 63) / 64 >= 128) return 0;
+    if (total >= (1LL << 31) || (lines + 63) / 64 >= 128) return g;
     int K;
     if (lines >= 64) {
         K = (n + 95) / 96;
+    } else if (lines == 1 && n >= 2 * kLineChunk) {
+        const int inner_chunks = (n - kLineChunk) / kLineChunk;   // rest r in [m, 2m)
+        const int r = n - inner_chunks * kLineChunk;
+        K = inner_chunks + 2;
+        g.f = r / 2;
+        g.m = kLineChunk;
     } else {
         int m = 64;
         while ((long long)m * m < 3LL * n && m < 8192) m *= 2;
@@ -863,18 +874,26 @@ int part_chunks(int n, long long lines)
     // the kernels' 32-bit chunk arithmetic
     if (K < 2 || n / K < 64 || K > 65535 || (long long)(K - 1) * 6 * 8 > 65536 ||
         (long long)(K + 1) * n >= (1LL << 32))
-        return 0;
-    return K;
+        return iga::PartGeom{n, 0, 0, 0};
+    g.K = K;
+    return g;
 }
 
-// Tables of the partitioned solve along axis a in K chunks (built once per context), and
-// scratch for `lines` lines.  The chunk factors F, B have kFactorPad zero rows after row n,
-// as the segment kernel reads them.
-int ensure_part(iga_ctx* c, int a, int K, long long lines)
+// Longest chunk of a geometry.
+int part_longest(const iga::PartGeom& g)
 {
-    const int n = c->N[a], p = c->p, Q = 2 * p;
+    if (g.m == 0) return (g.n + g.K - 1) / g.K;
+    return std::max({g.f, g.m, g.n - g.start(g.K - 1)});
+}
+
+// Tables of the partitioned solve along axis a (built once per context), and scratch for
+// `lines` lines.  The chunk factors F, B have kFactorPad zero rows after row n, as the
+// segment kernel reads them.
+int ensure_part(iga_ctx* c, int a, const iga::PartGeom& g, long long lines)
+{
+    const int n = c->N[a], p = c->p, Q = 2 * p, K = g.K;
     const size_t tab = (size_t)(n + iga::kFactorPad) * (p + 1);
-    if (!c->part[a] || c->part_K[a] != K) {
+    if (!c->part[a] || c->part_g[a].K != g.K || c->part_g[a].m != g.m || c->part_g[a].f != g.f) {
         const size_t doubles = 2 * tab + 2 * (size_t)n * p + 2 * (size_t)(K - 1) * Q * Q;
         void* mem = nullptr;
         IGA_TRY(dalloc(c, &mem, doubles * sizeof(double)));
@@ -887,21 +906,21 @@ int ensure_part(iga_ctx* c, int a, int K, long long lines)
         const double* A = c->t[a].gm;
         const unsigned gk = (unsigned)((K + 63) / 64), gs = (unsigned)((K * 2 * p + 63) / 64);
         if (p == 2) {
-            hipLaunchKernelGGL(iga::part_factor_kernel<2>, dim3(gk), dim3(64), 0, c->stream, A, n, K, F, B);
-            hipLaunchKernelGGL(iga::part_spike_kernel<2>, dim3(gs), dim3(64), 0, c->stream, A, n, K,
+            hipLaunchKernelGGL(iga::part_factor_kernel<2>, dim3(gk), dim3(64), 0, c->stream, A, g, F, B);
+            hipLaunchKernelGGL(iga::part_spike_kernel<2>, dim3(gs), dim3(64), 0, c->stream, A, g,
                                (const double*)F, (const double*)B, V, Wt);
             hipLaunchKernelGGL(iga::part_reduce_setup_kernel<2>, dim3(1), dim3(64), 0, c->stream,
-                               (const double*)V, (const double*)Wt, n, K, G, Dinv);
+                               (const double*)V, (const double*)Wt, g, G, Dinv);
         } else {
-            hipLaunchKernelGGL(iga::part_factor_kernel<3>, dim3(gk), dim3(64), 0, c->stream, A, n, K, F, B);
-            hipLaunchKernelGGL(iga::part_spike_kernel<3>, dim3(gs), dim3(64), 0, c->stream, A, n, K,
+            hipLaunchKernelGGL(iga::part_factor_kernel<3>, dim3(gk), dim3(64), 0, c->stream, A, g, F, B);
+            hipLaunchKernelGGL(iga::part_spike_kernel<3>, dim3(gs), dim3(64), 0, c->stream, A, g,
                                (const double*)F, (const double*)B, V, Wt);
             hipLaunchKernelGGL(iga::part_reduce_setup_kernel<3>, dim3(1), dim3(64), 0, c->stream,
-                               (const double*)V, (const double*)Wt, n, K, G, Dinv);
+                               (const double*)V, (const double*)Wt, g, G, Dinv);
         }
         IGA_HIP(hipGetLastError());
         c->part[a] = F;
-        c->part_K[a] = K;
+        c->part_g[a] = g;
     }
     const size_t zn = (size_t)lines * (K - 1) * Q;
     if (c->part_z_n < zn) {
@@ -916,12 +935,27 @@ int ensure_part(iga_ctx* c, int a, int K, long long lines)
 int launch_seg(iga_ctx* c, const double* F, const double* B, int n, int K, long long lines, long long inner,
                bool contig, const double* src, double* x, hipStream_t s);
 
+// The chunk solves of a single line with interior chunks of equal length by the segment
+// kernel: the interior chunks as the lines of one launch (the factors of chunk 1 serve
+// them all), then the first and the last chunk; 1 when they do not fit it.
+int launch_line_chunks(iga_ctx* c, const iga::PartGeom& g, const double* F, const double* B, const double* src,
+                       double* x, hipStream_t s)
+{
+    const int FR = c->p + 1, s1 = g.start(1), sl = g.start(g.K - 1);
+    int rc = launch_seg(c, F + (size_t)s1 * FR, B + (size_t)s1 * FR, g.m, 1, g.K - 2, 1, true, src + s1, x + s1, s);
+    if (rc != IGA_OK) return rc;
+    rc = launch_seg(c, F, B, g.f, 1, 1, 1, true, src, x, s);
+    if (rc != IGA_OK) return rc;
+    return launch_seg(c, F + (size_t)sl * FR, B + (size_t)sl * FR, g.n - sl, 1, 1, 1, true, src + sl, x + sl, s);
+}
+
 // One family by the partitioned solve: chunk solves from src into x, the reduced sweeps
 // per line, the spike correction.
-int launch_part(iga_ctx* c, int a, int K, int lines, int inner, const double* src, double* x, hipStream_t s)
+int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner, const double* src, double* x,
+                hipStream_t s)
 {
-    IGA_TRY(ensure_part(c, a, K, lines));
-    const int n = c->N[a], p = c->p;
+    IGA_TRY(ensure_part(c, a, g, lines));
+    const int n = c->N[a], p = c->p, K = g.K;
     const size_t tab = (size_t)(n + iga::kFactorPad) * (p + 1);
     const double* F = c->part[a];
     const double* B = F + tab;
@@ -943,16 +977,16 @@ int launch_part(iga_ctx* c, int a, int K, int lines, int inner, const double* sr
     dim3 g3, b3;
     const int rows = (lines / inner) * n;   // rows of the line groups (inner > 1)
     if (inner == 1) {
-        const int longest = (n + K - 1) / K;
         g3 = dim3((unsigned)K, (unsigned)((lines + iga::kCorr - 1) / iga::kCorr));
-        b3 = dim3((unsigned)std::min(256, (longest + 63) / 64 * 64));
+        b3 = dim3((unsigned)std::min(256, (part_longest(g) + 63) / 64 * 64));
     } else {
         g3 = dim3((unsigned)((rows + iga::kCorr - 1) / iga::kCorr), (unsigned)((inner + 255) / 256));
         b3 = dim3(256);
     }
     bool local_done = false;
-    if (lines >= 64) {
-        const int rc = launch_seg(c, F, B, n, K, lines, inner, a == 0, src, x, s);
+    if (lines >= 64 || g.m > 0) {
+        const int rc = g.m > 0 ? launch_line_chunks(c, g, F, B, src, x, s)
+                               : launch_seg(c, F, B, n, K, lines, inner, a == 0, src, x, s);
         if (rc != 1) {   // 1: the chunks do not fit the segment kernel
             IGA_TRY(rc);
             local_done = true;
@@ -960,25 +994,25 @@ int launch_part(iga_ctx* c, int a, int K, int lines, int inner, const double* sr
     }
     if (p == 2) {
         if (!local_done)
-            hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, n, K, lines, inner, src, x);
+            hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
         if (staged)
-            hipLaunchKernelGGL((iga::part_reduce_kernel<2, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+            hipLaunchKernelGGL((iga::part_reduce_kernel<2, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else
-            hipLaunchKernelGGL((iga::part_reduce_kernel<2, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+            hipLaunchKernelGGL((iga::part_reduce_kernel<2, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
-        hipLaunchKernelGGL(iga::part_correct_kernel<2>, g3, b3, 0, s, V, Wt, n, K, lines, inner, rows,
+        hipLaunchKernelGGL(iga::part_correct_kernel<2>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
                            (const double*)c->part_z, x);
     } else {
         if (!local_done)
-            hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, n, K, lines, inner, src, x);
+            hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
         if (staged)
-            hipLaunchKernelGGL((iga::part_reduce_kernel<3, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+            hipLaunchKernelGGL((iga::part_reduce_kernel<3, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else
-            hipLaunchKernelGGL((iga::part_reduce_kernel<3, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, n, K,
+            hipLaunchKernelGGL((iga::part_reduce_kernel<3, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
-        hipLaunchKernelGGL(iga::part_correct_kernel<3>, g3, b3, 0, s, V, Wt, n, K, lines, inner, rows,
+        hipLaunchKernelGGL(iga::part_correct_kernel<3>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
                            (const double*)c->part_z, x);
     }
     IGA_HIP(hipGetLastError());
@@ -1041,9 +1075,9 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
         const double* src = a == 0 ? b : x;
         const int n = c->N[a];
         if (!pg) {
-            const int K = part_chunks(n, lines[a]);
-            if (K > 0) {
-                IGA_TRY(launch_part(c, a, K, (int)lines[a], (int)inner[a], src, x, s));
+            const iga::PartGeom g = part_geom(n, lines[a]);
+            if (g.K > 0) {
+                IGA_TRY(launch_part(c, a, g, (int)lines[a], (int)inner[a], src, x, s));
                 continue;
             }
         }

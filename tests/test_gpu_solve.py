@@ -61,7 +61,8 @@ SOLVE_CASES = [
     (3, 3, (1000, 20, 12), None, None),            # long x-lines beside short y and z lines
     (2, 2, (1024, 1024), None, None),              # lines of two halves in both families
     (2, 3, (1300, 50), (0.0, 0.0), (2.0, 1.0)),
-    (1, 2, (5000,), (0.0,), (2.0,)),               # one line: partitioned into chunks
+    (1, 2, (5000,), (0.0,), (2.0,)),               # one line: interior chunks of equal length
+    (1, 3, (4000,), None, None),                   # one interior chunk between the end chunks
     (1, 3, (128,), None, None),                    # two chunks, the second longer
     (2, 3, (4, 300), None, None),                  # y-lines partitioned, x-lines not
     (2, 3, (70, 500), (0.0, -1.0), (1.0, 1.0)),    # y-lines in chunks of the segment kernel
