@@ -267,21 +267,20 @@ __global__ __launch_bounds__(256) void part_local_kernel(const double* __restric
     }
 }
 
-// Step 2: one thread per line, T lines per workgroup.  With `staged` the workgroup first
-// copies the block tables (Gamma_k, Delta_k^{-1} and V_{k+1}^T for every k) into LDS, so
-// that the sweeps wait on no memory; otherwise they read them from memory a step ahead.
-// Each thread reads all its h_k = x rows e_k - P .. e_k + P - 1 (k = 0 .. K-2) into LDS,
-// sixteen steps' loads at once (the first sixteen beside the table loads), runs the
-// forward sweep there (y_k replaces h_k) and the backward sweep, which writes zeta_k to Z
-// (entry (k, q) of line t at Z[(k 2P + q) lines + t]).
-// LDS: [tables: (K-1) (2 (2P)^2 + P^2) if staged | T (K-1) 2P].
+// Step 2: one thread per line, T lines per workgroup.  The workgroup first copies the
+// block tables (Gamma_k, Delta_k^{-1} and V_{k+1}^T for every k) into LDS, so that the
+// sweeps wait on no memory.  Each thread reads all its h_k = x rows e_k - P .. e_k + P - 1
+// (k = 0 .. K-2) into LDS, sixteen steps' loads at once (the first sixteen beside the
+// table loads), runs the forward sweep there (y_k replaces h_k) and the backward sweep,
+// which writes zeta_k to Z (entry (k, q) of line t at Z[(k 2P + q) lines + t]).
+// LDS: [tables: (K-1) (2 (2P)^2 + P^2) | T (K-1) 2P].
 template <int P>
 __host__ __device__ constexpr int part_table_doubles(int K)
 {
     return (K - 1) * (2 * 4 * P * P + P * P);
 }
 
-template <int P, bool STAGED>
+template <int P>
 __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restrict__ G,
                                                          const double* __restrict__ Dinv,
                                                          const double* __restrict__ V, PartGeom pg,
@@ -289,7 +288,6 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
                                                          const double* __restrict__ x, double* __restrict__ Z)
 {
     const int n = pg.n, K = pg.K;
-    constexpr bool staged = STAGED;
     constexpr int Q = 2 * P;
     extern __shared__ double part_y[];
     const int T = blockDim.x, tid = threadIdx.x;
@@ -307,7 +305,7 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
 #pragma unroll
         for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
     }
-    if constexpr (staged) {
+    {
         // eight entries per thread in flight at a time: [Gamma | Delta^-1 | V^T]
         const int nq = (K - 1) * Q * Q, nt = 2 * nq + (K - 1) * P * P;
         for (int j0 = 0; j0 < nt; j0 += 8 * T) {
@@ -331,23 +329,11 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
         __syncthreads();
     }
     if (t >= lines) return;   // no barrier below: each thread uses its own LDS column
-    double* yl = part_y + (staged ? part_table_doubles<P>(K) : 0) + tid;
-    // block tables, from LDS (a pointer known to be LDS, so the reads are LDS reads) or
-    // from memory (the same for every thread; read through vector registers, a zero the
-    // compiler cannot see through, as scalar registers do not hold them)
-    int vz;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
-    const double* Gp;
-    const double* Dp;
-    if constexpr (staged) {
-        Gp = tabs;
-        Dp = tabs + (K - 1) * Q * Q;
-    } else {
-        Gp = G + vz;
-        Dp = Dinv + vz;
-    }
+    double* yl = part_y + part_table_doubles<P>(K) + tid;
+    // block tables in LDS (pointers known to be LDS, so the reads are LDS reads)
+    const double* Gp = tabs;
+    const double* Dp = tabs + (K - 1) * Q * Q;
     const double* VTs = tabs + 2 * (K - 1) * Q * Q;
-    V += vz;
     for (int k0 = 0; k0 + 1 < K; k0 += KB) {
         if (k0 > 0) {
 #pragma unroll
@@ -406,16 +392,8 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
         const int kn = k > 0 ? k - 1 : k;
 #pragma unroll
         for (int q = 0; q < Q * Q; ++q) dn[q] = Dp[(size_t)kn * Q * Q + q];
-        if constexpr (staged) {
 #pragma unroll
-            for (int q = 0; q < P * P; ++q) vn[q] = VTs[(size_t)kn * P * P + q];
-        } else {
-            const int s1 = pg.start(kn + 1);   // first row of chunk kn + 1
-#pragma unroll
-            for (int a = 0; a < P; ++a)
-#pragma unroll
-                for (int b = 0; b < P; ++b) vn[a * P + b] = V[(size_t)(s1 + a) * P + b];
-        }
+        for (int q = 0; q < P * P; ++q) vn[q] = VTs[(size_t)kn * P * P + q];
         double rhs[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) rhs[q] = yl[(size_t)(k * Q + q) * T];
@@ -435,6 +413,158 @@ __global__ __launch_bounds__(64) void part_reduce_kernel(const double* __restric
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) Z[((size_t)k * Q + q) * lines + t] = zn[q];
+    }
+}
+
+// Step 2 for long chains (block tables too large for LDS; a single long line): the
+// workgroup's 64 threads stream the tables through an LDS ring, kStreamSteps steps at a
+// time, the next batch loading while the first TL threads (one line each) run the
+// current one.  LDS: [ring: 2 kStreamSteps (2P)^2 + P^2 | TL (K-1) 2P].
+constexpr int kStreamSteps = 16;
+template <int P>
+__host__ __device__ constexpr int part_stream_ring_doubles()
+{
+    return 2 * kStreamSteps * (4 * P * P + P * P);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void part_reduce_stream_kernel(const double* __restrict__ G,
+                                                                const double* __restrict__ Dinv,
+                                                                const double* __restrict__ V, PartGeom pg,
+                                                                int lines, int inner, int TL,
+                                                                const double* __restrict__ x,
+                                                                double* __restrict__ Z)
+{
+    constexpr int Q = 2 * P, QQ = Q * Q, PP = P * P, EW = QQ + PP;   // ring entry: Q^2 (+ P^2)
+    constexpr int SH = (kStreamSteps * EW + 63) / 64;                // ring doubles per thread
+    const int n = pg.n, K = pg.K;
+    extern __shared__ double part_y[];
+    double* const ring = part_y;                                     // 2 halves of kStreamSteps EW
+    const int tid = threadIdx.x;
+    const int t = blockIdx.x * TL + tid;
+    const bool active = tid < TL && t < lines;
+    const int tc = min(active ? t : blockIdx.x * TL, lines - 1);
+    const int o = tc / inner, i = tc - o * inner;
+    const size_t base = (size_t)o * n * inner + i;
+    double* yl = part_y + part_stream_ring_doubles<P>() + tid;
+    const int nst = K - 1;   // steps 0 .. K-2
+    if (active)
+        for (int k0 = 0; k0 < nst; k0 += kStreamSteps) {   // a batch of steps' loads at once
+            double hb[kStreamSteps][Q];
+#pragma unroll
+            for (int kk = 0; kk < kStreamSteps; ++kk) {
+                const int e = pg.start(min(k0 + kk, nst - 1) + 1);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) hb[kk][q] = x[base + (size_t)(e - P + q) * inner];
+            }
+#pragma unroll
+            for (int kk = 0; kk < kStreamSteps; ++kk)
+                if (k0 + kk < nst) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) yl[(size_t)((k0 + kk) * Q + q) * TL] = hb[kk][q];
+                }
+        }
+    // one batch of ring entries: forward entries hold Gamma_k; backward entries Delta_k^{-1}
+    // and V_{k+1}^T (step k of the batch order; its entry at e * EW)
+    auto fetch = [&](bool fwd, int b, double (&reg)[SH]) {
+#pragma unroll
+        for (int u = 0; u < SH; ++u) {
+            const int j = u * 64 + tid;
+            const int e = j / EW, w = j - e * EW;
+            const int kk = fwd ? 1 + b * kStreamSteps + e : nst - 1 - (b * kStreamSteps + e);
+            double v = 0.0;
+            if (j < kStreamSteps * EW && kk >= 0 && kk < nst) {
+                if (w < QQ)
+                    v = fwd ? G[(size_t)kk * QQ + w] : Dinv[(size_t)kk * QQ + w];
+                else if (!fwd && kk + 1 < nst)
+                    v = V[(size_t)(pg.start(kk + 1) + (w - QQ) / P) * P + (w - QQ) % P];
+            }
+            reg[u] = v;
+        }
+    };
+    auto put = [&](int half, const double (&reg)[SH]) {
+#pragma unroll
+        for (int u = 0; u < SH; ++u) {
+            const int j = u * 64 + tid;
+            if (j < kStreamSteps * EW) ring[half * kStreamSteps * EW + j] = reg[u];
+        }
+    };
+    double reg[SH];
+    // forward: y_k = h_k - Gamma_k y_{k-1}, k = 1 .. K-2 in batches
+    double y[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) y[q] = active ? yl[(size_t)q * TL] : 0.0;
+    const int nbf = (nst - 1 + kStreamSteps - 1) / kStreamSteps;
+    fetch(true, 0, reg);
+    put(0, reg);
+    __syncthreads();
+    for (int b = 0; b < nbf; ++b) {
+        fetch(true, b + 1, reg);
+        if (active) {
+            const double* rb = ring + (b & 1) * kStreamSteps * EW;
+            for (int e = 0; e < kStreamSteps; ++e) {
+                const int k = 1 + b * kStreamSteps + e;
+                if (k > nst - 1) break;
+                double h[Q];
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    double acc = yl[(size_t)(k * Q + a) * TL];
+#pragma unroll
+                    for (int c = 0; c < Q; ++c) acc = fma(-rb[e * EW + a * Q + c], y[c], acc);
+                    h[a] = acc;
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    y[q] = h[q];
+                    yl[(size_t)(k * Q + q) * TL] = h[q];
+                }
+            }
+        }
+        put((b + 1) & 1, reg);
+        __syncthreads();
+    }
+    // backward: zeta_k = Delta_k^{-1} (y_k - F_k zeta_{k+1}), k = K-2 .. 0 in batches
+    double zn[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) zn[q] = 0.0;
+    const int nbb = (nst + kStreamSteps - 1) / kStreamSteps;
+    fetch(false, 0, reg);
+    put(0, reg);
+    __syncthreads();
+    for (int b = 0; b < nbb; ++b) {
+        fetch(false, b + 1, reg);
+        if (active) {
+            const double* rb = ring + (b & 1) * kStreamSteps * EW;
+            for (int e = 0; e < kStreamSteps; ++e) {
+                const int k = nst - 1 - (b * kStreamSteps + e);
+                if (k < 0) break;
+                // the entry of step k holds Delta_k^{-1} and V_{k+1}^T
+                double rhs[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) rhs[q] = yl[(size_t)(k * Q + q) * TL];
+                if (k < nst - 1) {
+                    const double* vt = rb + e * EW + QQ;
+#pragma unroll
+                    for (int a = 0; a < P; ++a) {
+                        double acc = rhs[P + a];
+#pragma unroll
+                        for (int c = 0; c < P; ++c) acc = fma(-vt[a * P + c], zn[P + c], acc);
+                        rhs[P + a] = acc;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < Q; ++c) acc = fma(rb[e * EW + a * Q + c], rhs[c], acc);
+                    zn[a] = acc;
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) Z[((size_t)k * Q + q) * lines + t] = zn[q];
+            }
+        }
+        put((b + 1) & 1, reg);
+        __syncthreads();
     }
 }
 

@@ -965,7 +965,7 @@ int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner,
     const double* Dinv = G + (size_t)(K - 1) * 4 * p * p;
     const unsigned g1 = (unsigned)(((size_t)lines * K + 255) / 256);
     // reduced sweeps: T lines per workgroup, (K-1) 2P doubles of LDS each, and the block
-    // tables beside them when they take at most 32 KiB; at most 64 KiB in all
+    // tables beside them when they take at most 32 KiB (at most 64 KiB in all)
     const size_t per_line = (size_t)(K - 1) * 2 * p * sizeof(double);
     const size_t tabs = (size_t)(p == 2 ? iga::part_table_doubles<2>(K) : iga::part_table_doubles<3>(K)) *
                         sizeof(double);
@@ -973,6 +973,12 @@ int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner,
     const unsigned T = (unsigned)std::max<size_t>(1, std::min<size_t>(64, (65536 - (staged ? tabs : 0)) / per_line));
     const unsigned g2 = (unsigned)((lines + T - 1) / T);
     const size_t lds2 = T * per_line + (staged ? tabs : 0);
+    // otherwise the tables stream through an LDS ring beside TL lines
+    const size_t ring = (size_t)(p == 2 ? iga::part_stream_ring_doubles<2>() : iga::part_stream_ring_doubles<3>()) *
+                        sizeof(double);
+    const int TL = (int)std::max<size_t>(1, std::min<size_t>(64, (65536 - ring) / per_line));
+    const unsigned g2s = (unsigned)((lines + TL - 1) / TL);
+    const size_t lds2s = ring + (size_t)TL * per_line;
     // correction
     dim3 g3, b3;
     const int rows = (lines / inner) * n;   // rows of the line groups (inner > 1)
@@ -996,22 +1002,22 @@ int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner,
         if (!local_done)
             hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
         if (staged)
-            hipLaunchKernelGGL((iga::part_reduce_kernel<2, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
+            hipLaunchKernelGGL(iga::part_reduce_kernel<2>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else
-            hipLaunchKernelGGL((iga::part_reduce_kernel<2, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
-                               lines, inner, (const double*)x, c->part_z);
+            hipLaunchKernelGGL(iga::part_reduce_stream_kernel<2>, dim3(g2s), dim3(64), lds2s, s, G, Dinv, V, g,
+                               lines, inner, TL, (const double*)x, c->part_z);
         hipLaunchKernelGGL(iga::part_correct_kernel<2>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
                            (const double*)c->part_z, x);
     } else {
         if (!local_done)
             hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
         if (staged)
-            hipLaunchKernelGGL((iga::part_reduce_kernel<3, true>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
+            hipLaunchKernelGGL(iga::part_reduce_kernel<3>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else
-            hipLaunchKernelGGL((iga::part_reduce_kernel<3, false>), dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
-                               lines, inner, (const double*)x, c->part_z);
+            hipLaunchKernelGGL(iga::part_reduce_stream_kernel<3>, dim3(g2s), dim3(64), lds2s, s, G, Dinv, V, g,
+                               lines, inner, TL, (const double*)x, c->part_z);
         hipLaunchKernelGGL(iga::part_correct_kernel<3>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
                            (const double*)c->part_z, x);
     }
