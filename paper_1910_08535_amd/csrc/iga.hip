@@ -845,9 +845,9 @@ void seg_allow_lds(size_t bytes)
 // workgroups of 64 lines (half the compute units), or when a chunk would have fewer than
 // 64 rows.  With lines enough for the lanes of a wave the chunks are balanced and solved
 // by the segment kernel, at most 96 rows (two waves) each.  A single line of at least
-// 2 kLineChunk rows gets interior chunks of kLineChunk rows (bitwise equal factors: one
-// segment-kernel launch runs them as its lines) between a first and a last chunk of at
-// most kLineChunk rows.  Other families with few lines take one thread per balanced
+// 2 kLineChunk rows gets interior chunks of equal length, at most kLineChunk rows
+// (bitwise equal factors: one segment-kernel launch runs them as its lines), between a
+// first and a last chunk of 64 to a few hundred rows.  Other families with few lines take one thread per balanced
 // chunk of about sqrt(3 n) rows: a chunk's two substitutions then cost about as much as
 // a line's reduced sweeps (2 n / m steps of a 2P x 2P block).
 constexpr int kLineChunk = 1536;
@@ -860,11 +860,11 @@ iga::PartGeom part_geom(int n, long long lines)
     if (lines >= 64) {
         K = (n + 95) / 96;
     } else if (lines == 1 && n >= 2 * kLineChunk) {
-        const int inner_chunks = (n - kLineChunk) / kLineChunk;   // rest r in [m, 2m)
-        const int r = n - inner_chunks * kLineChunk;
-        K = inner_chunks + 2;
-        g.f = r / 2;
-        g.m = kLineChunk;
+        // I interior chunks of m rows leave r = n - I m in [128, 128 + I) rows to the ends
+        const int I = (n - 128 + kLineChunk - 1) / kLineChunk;
+        g.m = (n - 128) / I;
+        g.f = (n - I * g.m) / 2;
+        K = I + 2;
     } else {
         int m = 64;
         while ((long long)m * m < 3LL * n && m < 8192) m *= 2;
