@@ -851,7 +851,7 @@ void seg_allow_lds(size_t bytes)
 // chunk of about sqrt(3 n) rows: a chunk's two substitutions then cost about as much as
 // a line's reduced sweeps (2 n / m steps of a 2P x 2P block).
 constexpr int kLineChunk = 1536;
-iga::PartGeom part_geom(int n, long long lines)
+iga::PartGeom part_geom(int n, long long lines, int p)
 {
     iga::PartGeom g{n, 0, 0, 0};
     const long long total = lines * n;
@@ -870,9 +870,11 @@ iga::PartGeom part_geom(int n, long long lines)
         while ((long long)m * m < 3LL * n && m < 8192) m *= 2;
         K = n / m;
     }
-    // grid rows of the chunks, the reduced sweeps of one line in at most 64 KiB of LDS, and
-    // the kernels' 32-bit chunk arithmetic
-    if (K < 2 || n / K < 64 || K > 65535 || (long long)(K - 1) * 6 * 8 > 65536 ||
+    // grid rows of the chunks, the reduced sweeps of one line (with the streaming ring of
+    // the block tables) in at most 64 KiB of LDS, and the kernels' 32-bit chunk arithmetic
+    const long long ring = (long long)(p == 2 ? iga::part_stream_ring_doubles<2>() : iga::part_stream_ring_doubles<3>()) *
+                           (long long)sizeof(double);
+    if (K < 2 || n / K < 64 || K > 65535 || (long long)(K - 1) * 2 * p * 8 + ring > 65536 ||
         (long long)(K + 1) * n >= (1LL << 32))
         return iga::PartGeom{n, 0, 0, 0};
     g.K = K;
@@ -1081,7 +1083,7 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
         const double* src = a == 0 ? b : x;
         const int n = c->N[a];
         if (!pg) {
-            const iga::PartGeom g = part_geom(n, lines[a]);
+            const iga::PartGeom g = part_geom(n, lines[a], c->p);
             if (g.K > 0) {
                 IGA_TRY(launch_part(c, a, g, (int)lines[a], (int)inner[a], src, x, s));
                 continue;
