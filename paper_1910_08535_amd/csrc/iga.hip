@@ -842,8 +842,10 @@ void seg_allow_lds(size_t bytes)
 
 // Chunk geometry of the partitioned solve of a family of `lines` lines of n rows; K = 0
 // when the family keeps one recurrence per line: that is when its lines fill at least 128
-// workgroups of 64 lines (half the compute units), or when a chunk would have fewer than
-// 64 rows.  With lines enough for the lanes of a wave the chunks are balanced and solved
+// workgroups of 64 lines (half the compute units), when the lines are shorter than 256
+// rows (the three launches of the partitioned solve then cost more than the short
+// recurrence: 37 against 32 us at 152 rows and 152 lines), or when a chunk would have
+// fewer than 64 rows.  With lines enough for the lanes of a wave the chunks are balanced and solved
 // by the segment kernel, at most 96 rows (two waves) each.  A single line of at least
 // 2 kLineChunk rows gets interior chunks of equal length, at most kLineChunk rows
 // (bitwise equal factors: one segment-kernel launch runs them as its lines), between a
@@ -855,7 +857,7 @@ iga::PartGeom part_geom(int n, long long lines, int p)
 {
     iga::PartGeom g{n, 0, 0, 0};
     const long long total = lines * n;
-    if (total >= (1LL << 31) || (lines + 63) / 64 >= 128) return g;
+    if (n < 256 || total >= (1LL << 31) || (lines + 63) / 64 >= 128) return g;
     int K;
     if (lines >= 64) {
         K = (n + 95) / 96;

@@ -54,6 +54,7 @@ SOLVE_CASES = [
     (3, 3, (14, 19, 12), None, None),
     (3, 3, (130, 9, 7), None, None),               # repeated rows along x, 3D
     (3, 2, (6, 150, 11), None, None),              # repeated rows along y
+    (3, 2, (8, 300, 9), None, None),               # y-lines in chunks of the segment kernel
     (1, 2, (1,), None, None),                      # one element: N = p + 1
     (2, 3, (1, 5), None, None),
     (3, 2, (1, 1, 1), (0.0, 1.0, 2.0), (0.5, 3.0, 2.25)),
@@ -63,7 +64,7 @@ SOLVE_CASES = [
     (2, 3, (1300, 50), (0.0, 0.0), (2.0, 1.0)),
     (1, 2, (5000,), (0.0,), (2.0,)),               # one line: interior chunks of equal length
     (1, 3, (4000,), None, None),                   # one interior chunk between the end chunks
-    (1, 3, (128,), None, None),                    # two chunks, the second longer
+    (1, 3, (300,), None, None),                    # one line of 303 rows: one thread per chunk
     (2, 3, (4, 300), None, None),                  # y-lines partitioned, x-lines not
     (2, 3, (70, 500), (0.0, -1.0), (1.0, 1.0)),    # y-lines in chunks of the segment kernel
 ]
