@@ -842,7 +842,9 @@ void seg_allow_lds(size_t bytes)
 
 // Chunk geometry of the partitioned solve of a family of `lines` lines of n rows; K = 0
 // when the family keeps one recurrence per line: that is when its lines fill at least 128
-// workgroups of 64 lines (half the compute units), when the lines are shorter than 256
+// workgroups of 64 lines (half the compute units) and fit the segment kernel (at most
+// 2 * 768 rows; longer lines would take the one-line-per-lane streaming kernel), when
+// the lines are shorter than 256
 // rows (the three launches of the partitioned solve then cost more than the short
 // recurrence: 37 against 32 us at 152 rows and 152 lines), or when a chunk would have
 // fewer than 64 rows.  With lines enough for the lanes of a wave the chunks are balanced and solved
@@ -857,7 +859,8 @@ iga::PartGeom part_geom(int n, long long lines, int p)
 {
     iga::PartGeom g{n, 0, 0, 0};
     const long long total = lines * n;
-    if (n < 256 || total >= (1LL << 31) || (lines + 63) / 64 >= 128) return g;
+    const int seg_cap = 2 * iga::kSeg * iga::kSegMaxWaves;
+    if (n < 256 || total >= (1LL << 31) || ((lines + 63) / 64 >= 128 && n <= seg_cap)) return g;
     int K;
     if (lines >= 64) {
         K = (n + 95) / 96;

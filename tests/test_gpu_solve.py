@@ -60,6 +60,7 @@ SOLVE_CASES = [
     (3, 2, (1, 1, 1), (0.0, 1.0, 2.0), (0.5, 3.0, 2.25)),
     (2, 2, (800, 3), None, None),                  # x-lines longer than the on-chip limit
     (3, 3, (1000, 20, 12), None, None),            # long x-lines beside short y and z lines
+    (3, 2, (1600, 90, 92), None, None),            # many x-lines too long for the segment kernel
     (2, 2, (1024, 1024), None, None),              # lines of two halves in both families
     (2, 3, (1300, 50), (0.0, 0.0), (2.0, 1.0)),
     (1, 2, (5000,), (0.0,), (2.0,)),               # one line: interior chunks of equal length
