@@ -438,6 +438,7 @@ __global__ __launch_bounds__(64) void part_reduce_stream_kernel(const double* __
     constexpr int Q = 2 * P, QQ = Q * Q, PP = P * P, EW = QQ + PP;   // ring entry: Q^2 (+ P^2)
     constexpr int SH = (kStreamSteps * EW + 63) / 64;                // ring doubles per thread
     const int n = pg.n, K = pg.K;
+    constexpr int kSweepUnroll = P == 2 ? 4 : 1;   // p = 3 needs the registers
     extern __shared__ double part_y[];
     double* const ring = part_y;                                     // 2 halves of kStreamSteps EW
     const int tid = threadIdx.x;
@@ -502,9 +503,10 @@ __global__ __launch_bounds__(64) void part_reduce_stream_kernel(const double* __
         fetch(true, b + 1, reg);
         if (active) {
             const double* rb = ring + (b & 1) * kStreamSteps * EW;
-            for (int e = 0; e < kStreamSteps; ++e) {
+            const int ne = min(kStreamSteps, nst - 1 - b * kStreamSteps);   // steps of this batch
+#pragma unroll(kSweepUnroll)
+            for (int e = 0; e < ne; ++e) {
                 const int k = 1 + b * kStreamSteps + e;
-                if (k > nst - 1) break;
                 double h[Q];
 #pragma unroll
                 for (int a = 0; a < Q; ++a) {
@@ -535,9 +537,10 @@ __global__ __launch_bounds__(64) void part_reduce_stream_kernel(const double* __
         fetch(false, b + 1, reg);
         if (active) {
             const double* rb = ring + (b & 1) * kStreamSteps * EW;
-            for (int e = 0; e < kStreamSteps; ++e) {
+            const int ne = min(kStreamSteps, nst - b * kStreamSteps);   // steps of this batch
+#pragma unroll(kSweepUnroll)
+            for (int e = 0; e < ne; ++e) {
                 const int k = nst - 1 - (b * kStreamSteps + e);
-                if (k < 0) break;
                 // the entry of step k holds Delta_k^{-1} and V_{k+1}^T
                 double rhs[Q];
 #pragma unroll
