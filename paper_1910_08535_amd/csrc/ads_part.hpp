@@ -29,7 +29,10 @@
 // This is exact (no truncation of the spikes), so it agrees with the sequential solve to
 // rounding.  The spikes decay fast away from the chunk ends (for the mass matrices of
 // this method Gamma is below 1e-16 for chunks of 64 rows), so the reduced system is well
-// conditioned.
+// conditioned.  Where the entries of E_k and F_k are all below 2^-64 (chunks of about 50
+// rows for p = 2, 70 for p = 3), dropping them changes no value of zeta by more than a
+// small fraction of its last bit; step 2 then solves every interface on its own
+// (part_iface_kernel) instead of the sweeps along the line.
 #pragma once
 #include "ads.hpp"
 #include "common.hpp"
@@ -196,6 +199,68 @@ __global__ void part_reduce_setup_kernel(const double* __restrict__ V, const dou
                 Dinv[((size_t)k * Q + i) * Q + j] = inv[i][j];
                 prev[i][j] = inv[i][j];
             }
+    }
+}
+
+// Truncated reduced system (the truncated SPIKE scheme of Polizzi and Sameh): the blocks
+// E_k and F_k hold the far ends of the spikes, which for chunks of a hundred rows or more
+// lie far below rounding; without them the reduced system is block diagonal, and
+// zeta_k = D_k^{-1} h_k for every interface at once.  One thread per interface k writes
+// D_k^{-1} (row-major) and the largest magnitude of the entries of W_k^B and V_{k+1}^T that
+// this drops (NaN if any of them is NaN), from which the host decides.
+template <int P>
+__global__ __launch_bounds__(64) void part_trunc_setup_kernel(const double* __restrict__ V,
+                                                              const double* __restrict__ Wt, PartGeom pg,
+                                                              double* __restrict__ Minv, double* __restrict__ tip)
+{
+    constexpr int Q = 2 * P;
+    const int K = pg.K;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K - 1) return;
+    const int e = pg.start(k + 1);
+    double D[Q][Q], inv[Q][Q];
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) D[i][j] = i == j ? 1.0 : 0.0;
+    double m = 0.0;
+    for (int i = 0; i < P; ++i)
+        for (int j = 0; j < P; ++j) {
+            D[i][P + j] = V[(size_t)(e - P + i) * P + j];   // V_k^B
+            D[P + i][j] = Wt[(size_t)(e + i) * P + j];      // W_{k+1}^T
+            const double w = k >= 1 ? fabs(Wt[(size_t)(e - P + i) * P + j]) : 0.0;     // W_k^B
+            const double v = k + 2 < K ? fabs(V[(size_t)(e + i) * P + j]) : 0.0;       // V_{k+1}^T
+            if (!(w <= m)) m = w;
+            if (!(v <= m)) m = v;
+        }
+    small_inverse<Q>(D, inv);
+    for (int i = 0; i < Q; ++i)
+        for (int j = 0; j < Q; ++j) Minv[((size_t)k * Q + i) * Q + j] = inv[i][j];
+    tip[k] = m;
+}
+
+// Step 2 of the truncated system: zeta_k = D_k^{-1} h_k, one thread per (line,
+// interface), lines fastest; Z as the sweep kernels write it.
+template <int P>
+__global__ __launch_bounds__(256) void part_iface_kernel(const double* __restrict__ Minv, PartGeom pg,
+                                                         int lines, int inner, const double* __restrict__ x,
+                                                         double* __restrict__ Z)
+{
+    constexpr int Q = 2 * P;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long long)lines * (pg.K - 1)) return;
+    const int k = (int)(id / lines), t = (int)(id - (long long)k * lines);
+    const int o = t / inner, i = t - o * inner;
+    const size_t base = (size_t)o * pg.n * inner + i;
+    const int e = pg.start(k + 1);
+    double h[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) h[q] = x[base + (size_t)(e - P + q) * inner];
+    const double* M = Minv + (size_t)k * Q * Q;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) acc = fma(M[a * Q + c], h[c], acc);
+        Z[((size_t)k * Q + a) * lines + t] = acc;
     }
 }
 

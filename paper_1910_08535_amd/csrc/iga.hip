@@ -76,9 +76,10 @@ struct iga_ctx {
     int refine[3] = {1, 1, 1};
     double* lu[3] = {nullptr, nullptr, nullptr};
     // partitioned solve of the Galerkin mass along axes with few lines: chunk geometry,
-    // the tables F | B | V | Wt | Gamma | Delta^-1 per axis, and per-line scratch
+    // the tables F | B | V | Wt | Gamma | Delta^-1 | D^-1 | tip per axis, and per-line scratch
     iga::PartGeom part_g[3] = {};
     double* part[3] = {nullptr, nullptr, nullptr};
+    bool part_trunc[3] = {false, false, false};   // the reduced system is block diagonal to rounding
     double* part_z = nullptr;
     size_t part_z_n = 0;
     // cached explicit-step graph
@@ -893,15 +894,23 @@ int part_longest(const iga::PartGeom& g)
     return std::max({g.f, g.m, g.n - g.start(g.K - 1)});
 }
 
+// Largest dropped entry for which the reduced system is taken as block diagonal: with the
+// inverses of its diagonal blocks of norm about 1, the dropped terms then change no
+// interface value by more than 2^-60 of the largest one.
+constexpr double kTruncTip = 0x1p-64;
+
 // Tables of the partitioned solve along axis a (built once per context), and scratch for
 // `lines` lines.  The chunk factors F, B have kFactorPad zero rows after row n, as the
-// segment kernel reads them.
+// segment kernel reads them.  The tables are F | B | V | Wt | Gamma | Delta^-1 | D^-1 | tip.
+// The host reads the largest dropped spike entry back (one synchronisation per context
+// and axis) to choose the truncated reduced system; during stream capture, or with
+// IGA_PART_EXACT set in the environment, the exact block sweeps run.
 int ensure_part(iga_ctx* c, int a, const iga::PartGeom& g, long long lines)
 {
     const int n = c->N[a], p = c->p, Q = 2 * p, K = g.K;
     const size_t tab = (size_t)(n + iga::kFactorPad) * (p + 1);
     if (!c->part[a] || c->part_g[a].K != g.K || c->part_g[a].m != g.m || c->part_g[a].f != g.f) {
-        const size_t doubles = 2 * tab + 2 * (size_t)n * p + 2 * (size_t)(K - 1) * Q * Q;
+        const size_t doubles = 2 * tab + 2 * (size_t)n * p + 3 * (size_t)(K - 1) * Q * Q + (size_t)(K - 1);
         void* mem = nullptr;
         IGA_TRY(dalloc(c, &mem, doubles * sizeof(double)));
         double* F = (double*)mem;
@@ -910,24 +919,49 @@ int ensure_part(iga_ctx* c, int a, const iga::PartGeom& g, long long lines)
         double* Wt = V + (size_t)n * p;
         double* G = Wt + (size_t)n * p;
         double* Dinv = G + (size_t)(K - 1) * Q * Q;
+        double* Minv = Dinv + (size_t)(K - 1) * Q * Q;
+        double* tip = Minv + (size_t)(K - 1) * Q * Q;
         const double* A = c->t[a].gm;
         const unsigned gk = (unsigned)((K + 63) / 64), gs = (unsigned)((K * 2 * p + 63) / 64);
         if (p == 2) {
             hipLaunchKernelGGL(iga::part_factor_kernel<2>, dim3(gk), dim3(64), 0, c->stream, A, g, F, B);
             hipLaunchKernelGGL(iga::part_spike_kernel<2>, dim3(gs), dim3(64), 0, c->stream, A, g,
                                (const double*)F, (const double*)B, V, Wt);
-            hipLaunchKernelGGL(iga::part_reduce_setup_kernel<2>, dim3(1), dim3(64), 0, c->stream,
-                               (const double*)V, (const double*)Wt, g, G, Dinv);
+            hipLaunchKernelGGL(iga::part_trunc_setup_kernel<2>, dim3(gk), dim3(64), 0, c->stream,
+                               (const double*)V, (const double*)Wt, g, Minv, tip);
         } else {
             hipLaunchKernelGGL(iga::part_factor_kernel<3>, dim3(gk), dim3(64), 0, c->stream, A, g, F, B);
             hipLaunchKernelGGL(iga::part_spike_kernel<3>, dim3(gs), dim3(64), 0, c->stream, A, g,
                                (const double*)F, (const double*)B, V, Wt);
-            hipLaunchKernelGGL(iga::part_reduce_setup_kernel<3>, dim3(1), dim3(64), 0, c->stream,
-                               (const double*)V, (const double*)Wt, g, G, Dinv);
+            hipLaunchKernelGGL(iga::part_trunc_setup_kernel<3>, dim3(gk), dim3(64), 0, c->stream,
+                               (const double*)V, (const double*)Wt, g, Minv, tip);
         }
         IGA_HIP(hipGetLastError());
+        bool trunc = false;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const char* exact = std::getenv("IGA_PART_EXACT");
+        if ((!exact || !*exact || std::strcmp(exact, "0") == 0) &&
+            hipStreamIsCapturing(c->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            std::vector<double> h((size_t)(K - 1));
+            IGA_HIP(hipMemcpyAsync(h.data(), tip, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            IGA_HIP(hipStreamSynchronize(c->stream));
+            double m = 0.0;
+            for (const double v : h)
+                if (!(v <= m)) m = v;   // NaN sticks
+            trunc = m <= kTruncTip;
+        }
+        if (!trunc) {
+            if (p == 2)
+                hipLaunchKernelGGL(iga::part_reduce_setup_kernel<2>, dim3(1), dim3(64), 0, c->stream,
+                                   (const double*)V, (const double*)Wt, g, G, Dinv);
+            else
+                hipLaunchKernelGGL(iga::part_reduce_setup_kernel<3>, dim3(1), dim3(64), 0, c->stream,
+                                   (const double*)V, (const double*)Wt, g, G, Dinv);
+            IGA_HIP(hipGetLastError());
+        }
         c->part[a] = F;
         c->part_g[a] = g;
+        c->part_trunc[a] = trunc;
     }
     const size_t zn = (size_t)lines * (K - 1) * Q;
     if (c->part_z_n < zn) {
@@ -970,7 +1004,10 @@ int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner,
     const double* Wt = V + (size_t)n * p;
     const double* G = Wt + (size_t)n * p;
     const double* Dinv = G + (size_t)(K - 1) * 4 * p * p;
+    const double* Minv = Dinv + (size_t)(K - 1) * 4 * p * p;
+    const bool trunc = c->part_trunc[a];
     const unsigned g1 = (unsigned)(((size_t)lines * K + 255) / 256);
+    const unsigned gi = (unsigned)(((size_t)lines * (K - 1) + 255) / 256);
     // reduced sweeps: T lines per workgroup, (K-1) 2P doubles of LDS each, and the block
     // tables beside them when they take at most 32 KiB (at most 64 KiB in all)
     const size_t per_line = (size_t)(K - 1) * 2 * p * sizeof(double);
@@ -1008,7 +1045,10 @@ int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner,
     if (p == 2) {
         if (!local_done)
             hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
-        if (staged)
+        if (trunc)
+            hipLaunchKernelGGL(iga::part_iface_kernel<2>, dim3(gi), dim3(256), 0, s, Minv, g, lines, inner,
+                               (const double*)x, c->part_z);
+        else if (staged)
             hipLaunchKernelGGL(iga::part_reduce_kernel<2>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else
@@ -1019,7 +1059,10 @@ int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner,
     } else {
         if (!local_done)
             hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
-        if (staged)
+        if (trunc)
+            hipLaunchKernelGGL(iga::part_iface_kernel<3>, dim3(gi), dim3(256), 0, s, Minv, g, lines, inner,
+                               (const double*)x, c->part_z);
+        else if (staged)
             hipLaunchKernelGGL(iga::part_reduce_kernel<3>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else

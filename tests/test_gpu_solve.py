@@ -92,6 +92,43 @@ def test_solve_parity(orc, torch, iga, dim, p, ne, lo, hi):
     mesh.close()
 
 
+# partitioned families: 2D lines in balanced chunks of the segment kernel, single long
+# lines in equal interior chunks, few lines with one thread per chunk; p = 3 chunks of
+# 64-75 rows keep dropped entries above 2^-64, so there the exact sweeps run either way
+PART_CASES = [
+    (2, 2, (1024, 1024), None, None),
+    (2, 3, (1300, 50), (0.0, 0.0), (2.0, 1.0)),
+    (1, 2, (5000,), (0.0,), (2.0,)),
+    (1, 3, (4000,), None, None),
+    (1, 3, (300,), None, None),
+    (2, 3, (4, 300), None, None),
+    (2, 3, (70, 500), (0.0, -1.0), (1.0, 1.0)),
+    (2, 2, (300, 200), None, None),
+]
+
+
+@pytest.mark.parametrize("dim,p,ne,lo,hi", PART_CASES)
+def test_solve_exact_reduced_system(orc, torch, iga, monkeypatch, dim, p, ne, lo, hi):
+    """The partitioned solve with its reduced system taken whole (IGA_PART_EXACT set: block
+    sweeps along each line) and by default (block diagonal where every dropped spike
+    entry is below 2^-64): both agree with the oracle and with each other to rounding."""
+    print(f"solve exact reduced dim={dim} p={p} ne={ne}", flush=True)
+    pb = orc.Problem(dim, p, ne, [p + 1] * dim, lo or [0.0] * dim, hi or [1.0] * dim)
+    b = np.random.default_rng(23).standard_normal(pb.coef_shape())
+    bd = torch.from_numpy(b).cuda()
+    ref = orc.ads_solve(pb, b)
+    mesh = _mesh(iga, dim, p, ne, lo, hi)
+    x = mesh.solve(bd).cpu().numpy()
+    mesh.close()
+    monkeypatch.setenv("IGA_PART_EXACT", "1")
+    mesh = _mesh(iga, dim, p, ne, lo, hi)
+    xe = mesh.solve(bd).cpu().numpy()
+    mesh.close()
+    assert _rel(x, ref) < TOL
+    assert _rel(xe, ref) < TOL
+    assert _rel(x, xe) < 1e-14
+
+
 def test_solve_error_codes(torch, iga):
     mesh = _mesh(iga, 2, 2, (8, 8))
     b = torch.zeros(mesh.coef_shape(), dtype=torch.float64, device="cuda")
