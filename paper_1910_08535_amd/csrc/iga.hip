@@ -80,6 +80,7 @@ struct iga_ctx {
     iga::PartGeom part_g[3] = {};
     double* part[3] = {nullptr, nullptr, nullptr};
     bool part_trunc[3] = {false, false, false};   // the reduced system is block diagonal to rounding
+    bool part_long[3] = {false, false, false};    // short chunks of a single line were refused
     double* part_z = nullptr;
     size_t part_z_n = 0;
     // cached explicit-step graph
@@ -841,6 +842,15 @@ void seg_allow_lds(size_t bytes)
         (void)hipGetLastError();
 }
 
+// Whether the exact reduced sweeps of one line (with the streaming ring of the block
+// tables) fit 64 KiB of LDS.
+bool part_sweeps_fit(const iga::PartGeom& g, int p)
+{
+    const long long ring = (long long)(p == 2 ? iga::part_stream_ring_doubles<2>() : iga::part_stream_ring_doubles<3>()) *
+                           (long long)sizeof(double);
+    return (long long)(g.K - 1) * 2 * p * 8 + ring <= 65536;
+}
+
 // Chunk geometry of the partitioned solve of a family of `lines` lines of n rows; K = 0
 // when the family keeps one recurrence per line: that is when its lines fill at least 128
 // workgroups of 64 lines (half the compute units) and fit the segment kernel (at most
@@ -855,8 +865,14 @@ void seg_allow_lds(size_t bytes)
 // first and a last chunk of 64 to a few hundred rows.  Other families with few lines take one thread per balanced
 // chunk of about sqrt(3 n) rows: a chunk's two substitutions then cost about as much as
 // a line's reduced sweeps (2 n / m steps of a 2P x 2P block).
+// With short_chunks, a single line takes interior chunks of kShortChunk rows instead (two
+// waves of the segment kernel): the block-diagonal reduced system (see ensure_part) solves
+// every interface at once, so more chunks cost no longer chain.  The exact sweeps of that
+// many chunks would not fit LDS, so the context falls back to the long chunks when the
+// truncation is refused.
 constexpr int kLineChunk = 1536;
-iga::PartGeom part_geom(int n, long long lines, int p)
+constexpr int kShortChunk = 96;
+iga::PartGeom part_geom(int n, long long lines, int p, bool short_chunks)
 {
     iga::PartGeom g{n, 0, 0, 0};
     const long long total = lines * n;
@@ -865,6 +881,12 @@ iga::PartGeom part_geom(int n, long long lines, int p)
     int K;
     if (lines >= 64) {
         K = (n + 95) / 96;
+    } else if (lines == 1 && n >= 2 * kLineChunk && short_chunks) {
+        // I interior chunks of m rows leave r = n - I m in [128, 128 + m) rows to the ends
+        g.m = std::max(kShortChunk, (n - 128 + 64999) / 65000);
+        const int I = (n - 128) / g.m;
+        g.f = (n - I * g.m) / 2;
+        K = I + 2;
     } else if (lines == 1 && n >= 2 * kLineChunk) {
         // I interior chunks of m rows leave r = n - I m in [128, 128 + I) rows to the ends
         const int I = (n - 128 + kLineChunk - 1) / kLineChunk;
@@ -877,13 +899,12 @@ iga::PartGeom part_geom(int n, long long lines, int p)
         K = n / m;
     }
     // grid rows of the chunks, the reduced sweeps of one line (with the streaming ring of
-    // the block tables) in at most 64 KiB of LDS, and the kernels' 32-bit chunk arithmetic
-    const long long ring = (long long)(p == 2 ? iga::part_stream_ring_doubles<2>() : iga::part_stream_ring_doubles<3>()) *
-                           (long long)sizeof(double);
-    if (K < 2 || n / K < 64 || K > 65535 || (long long)(K - 1) * 2 * p * 8 + ring > 65536 ||
-        (long long)(K + 1) * n >= (1LL << 32))
-        return iga::PartGeom{n, 0, 0, 0};
+    // the block tables) in at most 64 KiB of LDS unless the chunks are short, and the
+    // kernels' 32-bit chunk arithmetic of balanced chunks
     g.K = K;
+    if (K < 2 || n / K < 64 || K > 65535 || (!(short_chunks && g.m > 0) && !part_sweeps_fit(g, p)) ||
+        (g.m == 0 && (long long)(K + 1) * n >= (1LL << 32)))
+        return iga::PartGeom{n, 0, 0, 0};
     return g;
 }
 
@@ -904,7 +925,10 @@ constexpr double kTruncTip = 0x1p-64;
 // segment kernel reads them.  The tables are F | B | V | Wt | Gamma | Delta^-1 | D^-1 | tip.
 // The host reads the largest dropped spike entry back (one synchronisation per context
 // and axis) to choose the truncated reduced system; during stream capture, or with
-// IGA_PART_EXACT set in the environment, the exact block sweeps run.
+// IGA_PART_EXACT set in the environment, the exact block sweeps run.  kPartReplan: the
+// exact sweeps are needed and do not fit this geometry (short chunks); the context then
+// keeps to long chunks along this axis.
+constexpr int kPartReplan = 1;
 int ensure_part(iga_ctx* c, int a, const iga::PartGeom& g, long long lines)
 {
     const int n = c->N[a], p = c->p, Q = 2 * p, K = g.K;
@@ -950,6 +974,11 @@ int ensure_part(iga_ctx* c, int a, const iga::PartGeom& g, long long lines)
                 if (!(v <= m)) m = v;   // NaN sticks
             trunc = m <= kTruncTip;
         }
+        if (!trunc && !part_sweeps_fit(g, p)) {
+            c->part[a] = nullptr;   // the tables stay with the context
+            c->part_long[a] = true;
+            return kPartReplan;
+        }
         if (!trunc) {
             if (p == 2)
                 hipLaunchKernelGGL(iga::part_reduce_setup_kernel<2>, dim3(1), dim3(64), 0, c->stream,
@@ -991,11 +1020,18 @@ int launch_line_chunks(iga_ctx* c, const iga::PartGeom& g, const double* F, cons
 }
 
 // One family by the partitioned solve: chunk solves from src into x, the reduced sweeps
-// per line, the spike correction.
-int launch_part(iga_ctx* c, int a, const iga::PartGeom& g, int lines, int inner, const double* src, double* x,
+// per line, the spike correction.  1: the family is not partitioned after all (its short
+// chunks were refused and the long ones do not apply).
+int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const double* src, double* x,
                 hipStream_t s)
 {
-    IGA_TRY(ensure_part(c, a, g, lines));
+    int rc0 = ensure_part(c, a, g, lines);
+    if (rc0 == kPartReplan) {
+        g = part_geom(c->N[a], lines, c->p, false);
+        if (g.K == 0) return 1;
+        rc0 = ensure_part(c, a, g, lines);
+    }
+    IGA_TRY(rc0);
     const int n = c->N[a], p = c->p, K = g.K;
     const size_t tab = (size_t)(n + iga::kFactorPad) * (p + 1);
     const double* F = c->part[a];
@@ -1131,10 +1167,13 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
         const double* src = a == 0 ? b : x;
         const int n = c->N[a];
         if (!pg) {
-            const iga::PartGeom g = part_geom(n, lines[a], c->p);
+            const iga::PartGeom g = part_geom(n, lines[a], c->p, !c->part_long[a]);
             if (g.K > 0) {
-                IGA_TRY(launch_part(c, a, g, (int)lines[a], (int)inner[a], src, x, s));
-                continue;
+                const int rc = launch_part(c, a, g, (int)lines[a], (int)inner[a], src, x, s);
+                if (rc != 1) {
+                    IGA_TRY(rc);
+                    continue;
+                }
             }
         }
         const double *F = nullptr, *B = nullptr;
