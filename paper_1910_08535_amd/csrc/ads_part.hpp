@@ -637,8 +637,10 @@ __global__ __launch_bounds__(64) void part_reduce_stream_kernel(const double* __
 }
 
 // Step 3: x -= V[r] t_{k+1} + Wt[r] u_{k-1} on every value, kCorr values per thread with
-// every load issued before the first is used.  x-lines (inner = 1): a workgroup per
-// (chunk, kCorr lines) = (blockIdx.x, blockIdx.y), its threads over the chunk's rows.
+// every load issued before the first is used.  A single line: 256 threads per workgroup
+// flat over its rows (one chunk lookup per row; a workgroup per chunk leaves 10^4 small
+// workgroups for a line of 10^6 rows in chunks of 96).  x-lines (inner = 1): a workgroup
+// per (chunk, kCorr lines) = (blockIdx.x, blockIdx.y), its threads over the chunk's rows.
 // Other families: a workgroup per (kCorr rows of line groups, inner block) =
 // (blockIdx.x, blockIdx.y), its threads over the inner index.  The chunk of a row is
 // uniform across the workgroup, so no thread divides.
@@ -651,6 +653,37 @@ __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restr
 {
     const int n = pg.n, K = pg.K;
     constexpr int Q = 2 * P;
+    if (lines == 1) {
+        // a single line (inner = 1): flat over its rows, kCorr rows per thread a workgroup
+        // apart; interior chunks of equal length (m > 0) have bitwise equal spikes, and all
+        // read chunk 1's, which stay in the cache
+        double xv[kCorr], vr[kCorr][P], wr[kCorr][P], zt[kCorr][P], zu[kCorr][P];
+        const int rb = blockIdx.x * blockDim.x * kCorr + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kCorr; ++u) {
+            const int r = min(rb + u * (int)blockDim.x, n - 1);
+            const int k = pg.chunk(r);
+            const int rs = pg.m > 0 && k > 0 && k + 1 < K ? r - pg.start(k) + pg.start(1) : r;
+            xv[u] = x[r];
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                vr[u][j] = V[(size_t)rs * P + j];
+                wr[u][j] = Wt[(size_t)rs * P + j];
+                zt[u][j] = k < K - 1 ? Z[(size_t)k * Q + P + j] : 0.0;
+                zu[u][j] = k > 0 ? Z[(size_t)(k - 1) * Q + j] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCorr; ++u) {
+            double v = xv[u];
+#pragma unroll
+            for (int j = 0; j < P; ++j) v = fma(-vr[u][j], zt[u][j], v);
+#pragma unroll
+            for (int j = 0; j < P; ++j) v = fma(-wr[u][j], zu[u][j], v);
+            if (rb + u * (int)blockDim.x < n) x[rb + u * blockDim.x] = v;
+        }
+        return;
+    }
     if (inner == 1) {
         const int k = blockIdx.x, o0 = blockIdx.y * kCorr;
         const int r1 = pg.start(k + 1);

@@ -1007,7 +1007,9 @@ int launch_seg(iga_ctx* c, const double* F, const double* B, int n, int K, long 
 
 // The chunk solves of a single line with interior chunks of equal length by the segment
 // kernel: the interior chunks as the lines of one launch (the factors of chunk 1 serve
-// them all), then the first and the last chunk; 1 when they do not fit it.
+// them all), then the first and the last chunk; 1 when they do not fit it.  (The end
+// chunks on two side streams forked from s and joined back were slower: the kernels of the
+// side streams started only after the interior launch, 10-20 us later.)
 int launch_line_chunks(iga_ctx* c, const iga::PartGeom& g, const double* F, const double* B, const double* src,
                        double* x, hipStream_t s)
 {
@@ -1062,7 +1064,10 @@ int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const 
     // correction
     dim3 g3, b3;
     const int rows = (lines / inner) * n;   // rows of the line groups (inner > 1)
-    if (inner == 1) {
+    if (lines == 1) {
+        g3 = dim3((unsigned)((n + 256 * iga::kCorr - 1) / (256 * iga::kCorr)));
+        b3 = dim3(256);
+    } else if (inner == 1) {
         g3 = dim3((unsigned)K, (unsigned)((lines + iga::kCorr - 1) / iga::kCorr));
         b3 = dim3((unsigned)std::min(256, (part_longest(g) + 63) / 64 * 64));
     } else {

@@ -151,6 +151,7 @@ def _gauss_table(orc, pb, seed):
 
 @pytest.mark.parametrize("dim,p,ne,form", [
     (1, 3, (60,), 1),
+    (1, 2, (4000,), 0),            # one line in chunks: end chunks on side streams
     (2, 2, (40, 33), 1),
     (2, 3, (21, 34), 0),
     (3, 2, (12, 10, 9), 0),
