@@ -882,10 +882,12 @@ iga::PartGeom part_geom(int n, long long lines, int p, bool short_chunks)
     if (lines >= 64) {
         K = (n + 95) / 96;
     } else if (lines == 1 && n >= 2 * kLineChunk && short_chunks) {
-        // I interior chunks of m rows leave r = n - I m in [128, 128 + m) rows to the ends
-        g.m = std::max(kShortChunk, (n - 128 + 64999) / 65000);
-        const int I = (n - 128) / g.m;
-        g.f = (n - I * g.m) / 2;
+        // I interior chunks of m rows leave r = n - I m in [32, 32 + m) rows to the ends:
+        // one wave of the segment kernel each while r <= 2 kSeg, else the first one wave
+        // (the end chunks' far spike ends are not part of the block-diagonal system)
+        g.m = std::max(kShortChunk, (n - 32 + 64999) / 65000);
+        const int I = (n - 32) / g.m;
+        g.f = std::min(iga::kSeg, (n - I * g.m) / 2);
         K = I + 2;
     } else if (lines == 1 && n >= 2 * kLineChunk) {
         // I interior chunks of m rows leave r = n - I m in [128, 128 + I) rows to the ends
