@@ -192,7 +192,12 @@ int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, i
    a backward substitution along every line.  Axes with few lines (1D, and 2D up to a
    few thousand lines) are solved in chunks instead: the chunks' own factors, the
    coupling between neighbouring chunks and a small block system per line, all built
-   once per context, give the same solution to rounding.
+   once per context, give the same solution to rounding.  When the coupling between
+   neighbouring chunk boundaries is below 2^-64 (it decays geometrically along a chunk),
+   the block system is taken as block diagonal; deciding this reads one small table back
+   to the host at the context's first solve along the axis (one synchronisation of its
+   stream; during stream capture, and with the environment variable IGA_PART_EXACT set
+   to a value other than 0, the full block system is used).
    b, x: device coefficient arrays (N_z, N_y, N_x); x may equal b (in place); b is not
    modified unless x == b.  form: IGA_GALERKIN_BYPARTS or IGA_GALERKIN_LAPLACIAN (one
    mass matrix for both).
