@@ -428,7 +428,8 @@ def run_ads(args) -> dict:
                                    "GPs": 128 ** 3 * 64 / t_step}
     mesh.close()
     out["kernel"] = ("iga::ads_seg_kernel<P> (one launch per axis); families with few lines: "
-                     "chunk solves, iga::part_reduce_kernel, iga::part_correct_kernel")
+                     "chunk solves, iga::part_iface_kernel (block-diagonal reduced system) or the "
+                     "reduced sweeps, iga::part_correct_kernel")
     return out
 
 
