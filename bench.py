@@ -428,8 +428,8 @@ def run_ads(args) -> dict:
                                    "GPs": 128 ** 3 * 64 / t_step}
     mesh.close()
     out["kernel"] = ("iga::ads_seg_kernel<P> (one launch per axis); families with few lines: "
-                     "chunk solves, iga::part_iface_kernel (block-diagonal reduced system) or the "
-                     "reduced sweeps, iga::part_correct_kernel")
+                     "chunk solves, then iga::part_fix_kernel (block-diagonal reduced system and "
+                     "correction) or the reduced sweeps and iga::part_correct_kernel")
     return out
 
 

@@ -31,8 +31,8 @@
 // this method Gamma is below 1e-16 for chunks of 64 rows), so the reduced system is well
 // conditioned.  Where the entries of E_k and F_k are all below 2^-64 (chunks of about 50
 // rows for p = 2, 70 for p = 3), dropping them changes no value of zeta by more than a
-// small fraction of its last bit; step 2 then solves every interface on its own
-// (part_iface_kernel) instead of the sweeps along the line.
+// small fraction of its last bit; step 2 then solves every interface on its own, inside
+// the correction (part_fix_kernel), instead of the sweeps along the line.
 #pragma once
 #include "ads.hpp"
 #include "common.hpp"
@@ -235,33 +235,6 @@ __global__ __launch_bounds__(64) void part_trunc_setup_kernel(const double* __re
     for (int i = 0; i < Q; ++i)
         for (int j = 0; j < Q; ++j) Minv[((size_t)k * Q + i) * Q + j] = inv[i][j];
     tip[k] = m;
-}
-
-// Step 2 of the truncated system: zeta_k = D_k^{-1} h_k, one thread per (line,
-// interface), lines fastest; Z as the sweep kernels write it.
-template <int P>
-__global__ __launch_bounds__(256) void part_iface_kernel(const double* __restrict__ Minv, PartGeom pg,
-                                                         int lines, int inner, const double* __restrict__ x,
-                                                         double* __restrict__ Z)
-{
-    constexpr int Q = 2 * P;
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (long long)lines * (pg.K - 1)) return;
-    const int k = (int)(id / lines), t = (int)(id - (long long)k * lines);
-    const int o = t / inner, i = t - o * inner;
-    const size_t base = (size_t)o * pg.n * inner + i;
-    const int e = pg.start(k + 1);
-    double h[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) h[q] = x[base + (size_t)(e - P + q) * inner];
-    const double* M = Minv + (size_t)k * Q * Q;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < Q; ++c) acc = fma(M[a * Q + c], h[c], acc);
-        Z[((size_t)k * Q + a) * lines + t] = acc;
-    }
 }
 
 // Step 1 for families of fewer lines than a wave has lanes (1D): one thread per
@@ -740,6 +713,154 @@ __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restr
 #pragma unroll
     for (int u = 0; u < kCorr; ++u) {
         double v = xv[u];
+#pragma unroll
+        for (int j = 0; j < P; ++j) v = fma(-vr[u][j], zt[u][j], v);
+#pragma unroll
+        for (int j = 0; j < P; ++j) v = fma(-wr[u][j], zu[u][j], v);
+        if (blockIdx.x * kCorr + u < (unsigned)rows) x[idx[u]] = v;
+    }
+}
+
+// Steps 2 and 3 of the block-diagonal reduced system in one launch, out of place: the
+// chunk solves left g in w, which nothing here writes, so each workgroup first solves the
+// interfaces its rows need, zeta_k = D_k^{-1} h_k with h_k read from w, and then writes
+// x = g - V_k t_{k+1} - W_k u_{k-1}.  The mappings are those of part_correct_kernel.  A
+// single line's workgroup spans 1024 rows; its chunks have at least 63 rows but for two
+// end chunks of at least 16, so it needs at most 21 interfaces (kFixIf bounds the LDS).
+constexpr int kFixIf = 32;
+template <int P>
+__global__ __launch_bounds__(256) void part_fix_kernel(const double* __restrict__ V,
+                                                       const double* __restrict__ Wt,
+                                                       const double* __restrict__ Minv, PartGeom pg,
+                                                       int lines, int inner, int rows,
+                                                       const double* __restrict__ w, double* __restrict__ x)
+{
+    const int n = pg.n, K = pg.K;
+    constexpr int Q = 2 * P;
+    __shared__ double zl[kFixIf * Q];
+    // entries a0 .. a0+na-1 of zeta_kk of the line whose row r is at base + r inner
+    auto solve_if = [&](int kk, size_t base, int a0, int na, double* z) {
+        const int e = pg.start(kk + 1);
+        double h[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) h[q] = w[base + (size_t)(e - P + q) * inner];
+        const double* M = Minv + (size_t)kk * Q * Q;
+        for (int a = 0; a < na; ++a) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < Q; ++c) acc = fma(M[(a0 + a) * Q + c], h[c], acc);
+            z[a] = acc;
+        }
+    };
+    double gv[kCorr], vr[kCorr][P], wr[kCorr][P], zt[kCorr][P], zu[kCorr][P];
+    if (lines == 1) {
+        const int r0 = blockIdx.x * blockDim.x * kCorr;
+        const int ka = pg.chunk(r0), kb = pg.chunk(min(r0 + (int)blockDim.x * kCorr - 1, n - 1));
+        const int nif = min(kb - ka + 2, kFixIf);   // interfaces ka-1 .. kb
+        for (int t = threadIdx.x; t < nif; t += blockDim.x) {
+            const int kk = ka - 1 + t;
+            if (kk >= 0 && kk <= K - 2) solve_if(kk, 0, 0, Q, zl + t * Q);
+        }
+        __syncthreads();
+        const int rb = r0 + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kCorr; ++u) {
+            const int r = min(rb + u * (int)blockDim.x, n - 1);
+            const int k = pg.chunk(r);
+            const int rs = pg.m > 0 && k > 0 && k + 1 < K ? r - pg.start(k) + pg.start(1) : r;
+            const int it = min(k - ka + 1, kFixIf - 1), iu = min(k - ka, kFixIf - 1);
+            gv[u] = w[r];
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                vr[u][j] = V[(size_t)rs * P + j];
+                wr[u][j] = Wt[(size_t)rs * P + j];
+                zt[u][j] = k < K - 1 ? zl[it * Q + P + j] : 0.0;
+                zu[u][j] = k > 0 ? zl[iu * Q + j] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCorr; ++u) {
+            double v = gv[u];
+#pragma unroll
+            for (int j = 0; j < P; ++j) v = fma(-vr[u][j], zt[u][j], v);
+#pragma unroll
+            for (int j = 0; j < P; ++j) v = fma(-wr[u][j], zu[u][j], v);
+            if (rb + u * (int)blockDim.x < n) x[rb + u * blockDim.x] = v;
+        }
+        return;
+    }
+    if (inner == 1) {
+        // threads 2u + s solve zeta_{k-1+s} of line o0 + u into LDS
+        const int k = blockIdx.x, o0 = blockIdx.y * kCorr;
+        if (threadIdx.x < 2 * kCorr) {
+            const int u = threadIdx.x >> 1, kk = k - 1 + (threadIdx.x & 1);
+            if (kk >= 0 && kk <= K - 2) solve_if(kk, (size_t)min(o0 + u, lines - 1) * n, 0, Q, zl + threadIdx.x * Q);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kCorr; ++u)
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                zt[u][j] = k < K - 1 ? zl[(2 * u + 1) * Q + P + j] : 0.0;
+                zu[u][j] = k > 0 ? zl[2 * u * Q + j] : 0.0;
+            }
+        const int r1 = pg.start(k + 1);
+        for (int r = pg.start(k) + threadIdx.x; r < r1; r += blockDim.x) {
+            double vk[P], wk[P];
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                vk[j] = V[(size_t)r * P + j];
+                wk[j] = Wt[(size_t)r * P + j];
+            }
+#pragma unroll
+            for (int u = 0; u < kCorr; ++u) gv[u] = w[(size_t)min(o0 + u, lines - 1) * n + r];
+#pragma unroll
+            for (int u = 0; u < kCorr; ++u) {
+                double v = gv[u];
+#pragma unroll
+                for (int j = 0; j < P; ++j) v = fma(-vk[j], zt[u][j], v);
+#pragma unroll
+                for (int j = 0; j < P; ++j) v = fma(-wk[j], zu[u][j], v);
+                if (o0 + u < lines) x[(size_t)(o0 + u) * n + r] = v;
+            }
+        }
+        return;
+    }
+    // other families: the rows of a workgroup are uniform across it, and so is the change
+    // of (line group, chunk) from one row to the next, where the thread solves anew
+    const int i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= inner) return;
+    size_t idx[kCorr];
+    int po = -1, pk = -1;
+    double ct[P], cu[P];
+#pragma unroll
+    for (int u = 0; u < kCorr; ++u) {
+        const int g = min(blockIdx.x * kCorr + u, rows - 1), o = g / n, r = g - o * n;
+        const int k = pg.chunk(r);
+        const size_t base = (size_t)o * n * inner + i;
+        if (o != po || k != pk) {
+            if (k < K - 1) solve_if(k, base, P, P, ct);
+            else
+                for (int j = 0; j < P; ++j) ct[j] = 0.0;
+            if (k > 0) solve_if(k - 1, base, 0, P, cu);
+            else
+                for (int j = 0; j < P; ++j) cu[j] = 0.0;
+            po = o;
+            pk = k;
+        }
+        idx[u] = base + (size_t)r * inner;
+        gv[u] = w[idx[u]];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            zt[u][j] = ct[j];
+            zu[u][j] = cu[j];
+            vr[u][j] = V[(size_t)r * P + j];
+            wr[u][j] = Wt[(size_t)r * P + j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kCorr; ++u) {
+        double v = gv[u];
 #pragma unroll
         for (int j = 0; j < P; ++j) v = fma(-vr[u][j], zt[u][j], v);
 #pragma unroll

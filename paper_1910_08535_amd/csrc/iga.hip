@@ -83,6 +83,8 @@ struct iga_ctx {
     bool part_long[3] = {false, false, false};    // short chunks of a single line were refused
     double* part_z = nullptr;
     size_t part_z_n = 0;
+    double* part_w = nullptr;   // chunk solutions of the block-diagonal reduced system
+    size_t part_w_n = 0;
     // cached explicit-step graph
     hipGraphExec_t gexec = nullptr;
     const double* g_u = nullptr;
@@ -1047,7 +1049,6 @@ int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const 
     const double* Minv = Dinv + (size_t)(K - 1) * 4 * p * p;
     const bool trunc = c->part_trunc[a];
     const unsigned g1 = (unsigned)(((size_t)lines * K + 255) / 256);
-    const unsigned gi = (unsigned)(((size_t)lines * (K - 1) + 255) / 256);
     // reduced sweeps: T lines per workgroup, (K-1) 2P doubles of LDS each, and the block
     // tables beside them when they take at most 32 KiB (at most 64 KiB in all)
     const size_t per_line = (size_t)(K - 1) * 2 * p * sizeof(double);
@@ -1076,10 +1077,17 @@ int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const 
         g3 = dim3((unsigned)((rows + iga::kCorr - 1) / iga::kCorr), (unsigned)((inner + 255) / 256));
         b3 = dim3(256);
     }
+    // the block-diagonal reduced system solves out of place: chunk solutions in part_w,
+    // then one launch for the interfaces and the correction into x
+    double* dst = x;
+    if (trunc) {
+        IGA_TRY(scratch(c, &c->part_w, &c->part_w_n, (size_t)lines * n));
+        dst = c->part_w;
+    }
     bool local_done = false;
     if (lines >= 64 || g.m > 0) {
-        const int rc = g.m > 0 ? launch_line_chunks(c, g, F, B, src, x, s)
-                               : launch_seg(c, F, B, n, K, lines, inner, a == 0, src, x, s);
+        const int rc = g.m > 0 ? launch_line_chunks(c, g, F, B, src, dst, s)
+                               : launch_seg(c, F, B, n, K, lines, inner, a == 0, src, dst, s);
         if (rc != 1) {   // 1: the chunks do not fit the segment kernel
             IGA_TRY(rc);
             local_done = true;
@@ -1087,32 +1095,34 @@ int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const 
     }
     if (p == 2) {
         if (!local_done)
-            hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
+            hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, dst);
         if (trunc)
-            hipLaunchKernelGGL(iga::part_iface_kernel<2>, dim3(gi), dim3(256), 0, s, Minv, g, lines, inner,
-                               (const double*)x, c->part_z);
+            hipLaunchKernelGGL(iga::part_fix_kernel<2>, g3, b3, 0, s, V, Wt, Minv, g, lines, inner, rows,
+                               (const double*)dst, x);
         else if (staged)
             hipLaunchKernelGGL(iga::part_reduce_kernel<2>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else
             hipLaunchKernelGGL(iga::part_reduce_stream_kernel<2>, dim3(g2s), dim3(64), lds2s, s, G, Dinv, V, g,
                                lines, inner, TL, (const double*)x, c->part_z);
-        hipLaunchKernelGGL(iga::part_correct_kernel<2>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
-                           (const double*)c->part_z, x);
+        if (!trunc)
+            hipLaunchKernelGGL(iga::part_correct_kernel<2>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
+                               (const double*)c->part_z, x);
     } else {
         if (!local_done)
-            hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, x);
+            hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, dst);
         if (trunc)
-            hipLaunchKernelGGL(iga::part_iface_kernel<3>, dim3(gi), dim3(256), 0, s, Minv, g, lines, inner,
-                               (const double*)x, c->part_z);
+            hipLaunchKernelGGL(iga::part_fix_kernel<3>, g3, b3, 0, s, V, Wt, Minv, g, lines, inner, rows,
+                               (const double*)dst, x);
         else if (staged)
             hipLaunchKernelGGL(iga::part_reduce_kernel<3>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
         else
             hipLaunchKernelGGL(iga::part_reduce_stream_kernel<3>, dim3(g2s), dim3(64), lds2s, s, G, Dinv, V, g,
                                lines, inner, TL, (const double*)x, c->part_z);
-        hipLaunchKernelGGL(iga::part_correct_kernel<3>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
-                           (const double*)c->part_z, x);
+        if (!trunc)
+            hipLaunchKernelGGL(iga::part_correct_kernel<3>, g3, b3, 0, s, V, Wt, g, lines, inner, rows,
+                               (const double*)c->part_z, x);
     }
     IGA_HIP(hipGetLastError());
     return IGA_OK;
