@@ -1026,8 +1026,10 @@ int launch_line_chunks(iga_ctx* c, const iga::PartGeom& g, const double* F, cons
 }
 
 // One family by the partitioned solve: chunk solves from src into x, the reduced sweeps
-// per line, the spike correction.  1: the family is not partitioned after all (its short
-// chunks were refused and the long ones do not apply).
+// per line, the spike correction; with the block-diagonal reduced system, chunk solves
+// from src into scratch, then the interfaces and the correction into x in one launch.
+// 1: the family is not partitioned after all (its short chunks were refused and the long
+// ones do not apply).
 int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const double* src, double* x,
                 hipStream_t s)
 {
