@@ -727,23 +727,40 @@ __global__ __launch_bounds__(256) void part_correct_kernel(const double* __restr
 // x = g - V_k t_{k+1} - W_k u_{k-1}.  The mappings are those of part_correct_kernel.  A
 // single line's workgroup spans 1024 rows; its chunks have at least 63 rows but for two
 // end chunks of at least 16, so it needs at most 21 interfaces (kFixIf bounds the LDS).
+// With ends set (a single line in equal interior chunks, m > 0), the end chunks were not
+// solved beforehand: a workgroup whose rows reach chunk 0 or 1 (K-2 or K-1) solves chunk 0
+// (K-1) itself from src, staged in LDS, one thread running the two substitutions, and
+// takes that chunk's g from LDS (at most kFixEnd rows; the two workgroups at a chunk
+// boundary both solve it).
 constexpr int kFixIf = 32;
+constexpr int kFixEnd = 80;
 template <int P>
 __global__ __launch_bounds__(256) void part_fix_kernel(const double* __restrict__ V,
                                                        const double* __restrict__ Wt,
                                                        const double* __restrict__ Minv, PartGeom pg,
                                                        int lines, int inner, int rows,
-                                                       const double* __restrict__ w, double* __restrict__ x)
+                                                       const double* __restrict__ w, double* __restrict__ x,
+                                                       const double* __restrict__ F, const double* __restrict__ B,
+                                                       const double* __restrict__ src, int ends)
 {
     const int n = pg.n, K = pg.K;
-    constexpr int Q = 2 * P;
+    constexpr int Q = 2 * P, FR = P + 1;
     __shared__ double zl[kFixIf * Q];
+    __shared__ double el[2][kFixEnd];          // g of the first / last chunk
+    __shared__ double et[kFixEnd * 2 * FR];    // their factor rows while one is solved
+    int e0 = -1, e1 = n;                       // rows below e0 / from e1 on come from el
+    // g of row r of the line at base
+    auto gval = [&](size_t base, int r) -> double {
+        if (r < e0) return el[0][r];
+        if (r >= e1) return el[1][r - e1];
+        return w[base + (size_t)r * inner];
+    };
     // entries a0 .. a0+na-1 of zeta_kk of the line whose row r is at base + r inner
     auto solve_if = [&](int kk, size_t base, int a0, int na, double* z) {
         const int e = pg.start(kk + 1);
         double h[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) h[q] = w[base + (size_t)(e - P + q) * inner];
+        for (int q = 0; q < Q; ++q) h[q] = gval(base, e - P + q);
         const double* M = Minv + (size_t)kk * Q * Q;
         for (int a = 0; a < na; ++a) {
             double acc = 0.0;
@@ -756,6 +773,49 @@ __global__ __launch_bounds__(256) void part_fix_kernel(const double* __restrict_
     if (lines == 1) {
         const int r0 = blockIdx.x * blockDim.x * kCorr;
         const int ka = pg.chunk(r0), kb = pg.chunk(min(r0 + (int)blockDim.x * kCorr - 1, n - 1));
+        if (ends)
+            for (int side = 0; side < 2; ++side) {   // uniform across the workgroup
+                if (side == 0 ? ka > 1 : kb < K - 2) continue;
+                const int s0 = side == 0 ? 0 : pg.start(K - 1), len = min(side == 0 ? pg.start(1) : n - s0, kFixEnd);
+                for (int t = threadIdx.x; t < len; t += blockDim.x) {
+                    el[side][t] = src[s0 + t];
+#pragma unroll
+                    for (int q = 0; q < FR; ++q) {
+                        et[t * 2 * FR + q] = F[(size_t)(s0 + t) * FR + q];
+                        et[t * 2 * FR + FR + q] = B[(size_t)(s0 + t) * FR + q];
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {   // forward y_r = b_r F_rP - sum F_rq y_{r-P+q}, then backward
+                    double yw[P];
+#pragma unroll
+                    for (int q = 0; q < P; ++q) yw[q] = 0.0;
+                    for (int t = 0; t < len; ++t) {
+                        double y = el[side][t] * et[t * 2 * FR + P];
+#pragma unroll
+                        for (int q = 0; q < P; ++q) y = fma(-et[t * 2 * FR + q], yw[q], y);
+                        el[side][t] = y;
+#pragma unroll
+                        for (int q = 0; q + 1 < P; ++q) yw[q] = yw[q + 1];
+                        yw[P - 1] = y;
+                    }
+                    double xw[P];   // xw[q-1] = x_{t+q}
+#pragma unroll
+                    for (int q = 0; q < P; ++q) xw[q] = 0.0;
+                    for (int t = len - 1; t >= 0; --t) {
+                        double v = el[side][t] * et[t * 2 * FR + FR + P];
+#pragma unroll
+                        for (int q = P; q >= 1; --q) v = fma(-et[t * 2 * FR + FR + q - 1], xw[q - 1], v);
+                        el[side][t] = v;
+#pragma unroll
+                        for (int q = P - 1; q >= 1; --q) xw[q] = xw[q - 1];
+                        xw[0] = v;
+                    }
+                }
+                __syncthreads();
+                if (side == 0) e0 = len;
+                else e1 = s0;
+            }
         const int nif = min(kb - ka + 2, kFixIf);   // interfaces ka-1 .. kb
         for (int t = threadIdx.x; t < nif; t += blockDim.x) {
             const int kk = ka - 1 + t;
@@ -769,7 +829,7 @@ __global__ __launch_bounds__(256) void part_fix_kernel(const double* __restrict_
             const int k = pg.chunk(r);
             const int rs = pg.m > 0 && k > 0 && k + 1 < K ? r - pg.start(k) + pg.start(1) : r;
             const int it = min(k - ka + 1, kFixIf - 1), iu = min(k - ka, kFixIf - 1);
-            gv[u] = w[r];
+            gv[u] = gval(0, r);
 #pragma unroll
             for (int j = 0; j < P; ++j) {
                 vr[u][j] = V[(size_t)rs * P + j];

@@ -1011,15 +1011,15 @@ int launch_seg(iga_ctx* c, const double* F, const double* B, int n, int K, long 
 
 // The chunk solves of a single line with interior chunks of equal length by the segment
 // kernel: the interior chunks as the lines of one launch (the factors of chunk 1 serve
-// them all), then the first and the last chunk; 1 when they do not fit it.  (The end
-// chunks on two side streams forked from s and joined back were slower: the kernels of the
-// side streams started only after the interior launch, 10-20 us later.)
+// them all), then, with `ends`, the first and the last chunk; 1 when they do not fit it.
+// (The end chunks on two side streams forked from s and joined back were slower: the
+// kernels of the side streams started only after the interior launch, 10-20 us later.)
 int launch_line_chunks(iga_ctx* c, const iga::PartGeom& g, const double* F, const double* B, const double* src,
-                       double* x, hipStream_t s)
+                       double* x, hipStream_t s, bool ends)
 {
     const int FR = c->p + 1, s1 = g.start(1), sl = g.start(g.K - 1);
     int rc = launch_seg(c, F + (size_t)s1 * FR, B + (size_t)s1 * FR, g.m, 1, g.K - 2, 1, true, src + s1, x + s1, s);
-    if (rc != IGA_OK) return rc;
+    if (rc != IGA_OK || !ends) return rc;
     rc = launch_seg(c, F, B, g.f, 1, 1, 1, true, src, x, s);
     if (rc != IGA_OK) return rc;
     return launch_seg(c, F + (size_t)sl * FR, B + (size_t)sl * FR, g.n - sl, 1, 1, 1, true, src + sl, x + sl, s);
@@ -1086,21 +1086,28 @@ int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const 
         IGA_TRY(scratch(c, &c->part_w, &c->part_w_n, (size_t)lines * n));
         dst = c->part_w;
     }
+    // a single line's end chunks solved inside part_fix_kernel, from src, which must then
+    // not be x: a workgroup may read rows of the last chunk that its neighbour writes
+    int ends = trunc && g.m > 0 && (const double*)x != src && g.f <= iga::kFixEnd &&
+                       n - g.start(K - 1) <= iga::kFixEnd
+                   ? 1
+                   : 0;
     bool local_done = false;
     if (lines >= 64 || g.m > 0) {
-        const int rc = g.m > 0 ? launch_line_chunks(c, g, F, B, src, dst, s)
+        const int rc = g.m > 0 ? launch_line_chunks(c, g, F, B, src, dst, s, !ends)
                                : launch_seg(c, F, B, n, K, lines, inner, a == 0, src, dst, s);
         if (rc != 1) {   // 1: the chunks do not fit the segment kernel
             IGA_TRY(rc);
             local_done = true;
         }
     }
+    if (!local_done) ends = 0;   // the one-thread-per-chunk kernel solves every chunk
     if (p == 2) {
         if (!local_done)
             hipLaunchKernelGGL(iga::part_local_kernel<2>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, dst);
         if (trunc)
             hipLaunchKernelGGL(iga::part_fix_kernel<2>, g3, b3, 0, s, V, Wt, Minv, g, lines, inner, rows,
-                               (const double*)dst, x);
+                               (const double*)dst, x, F, B, src, ends);
         else if (staged)
             hipLaunchKernelGGL(iga::part_reduce_kernel<2>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);
@@ -1115,7 +1122,7 @@ int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const 
             hipLaunchKernelGGL(iga::part_local_kernel<3>, dim3(g1), dim3(256), 0, s, F, B, g, lines, inner, src, dst);
         if (trunc)
             hipLaunchKernelGGL(iga::part_fix_kernel<3>, g3, b3, 0, s, V, Wt, Minv, g, lines, inner, rows,
-                               (const double*)dst, x);
+                               (const double*)dst, x, F, B, src, ends);
         else if (staged)
             hipLaunchKernelGGL(iga::part_reduce_kernel<3>, dim3(g2), dim3(T), lds2, s, G, Dinv, V, g,
                                lines, inner, (const double*)x, c->part_z);

@@ -104,6 +104,9 @@ PART_CASES = [
     (2, 3, (4, 300), None, None),
     (2, 3, (70, 500), (0.0, -1.0), (1.0, 1.0)),
     (2, 2, (300, 200), None, None),
+    (1, 2, (4118,), None, None),   # a workgroup boundary inside the last chunk: two solve it
+    (1, 3, (4147,), None, None),   # the same with a last chunk of 70 rows (two waves)
+    (1, 2, (4178,), None, None),   # a workgroup boundary inside the chunk before the last
 ]
 
 
