@@ -867,8 +867,9 @@ bool part_sweeps_fit(const iga::PartGeom& g, int p)
 // first and a last chunk of 64 to a few hundred rows.  Other families with few lines take one thread per balanced
 // chunk of about sqrt(3 n) rows: a chunk's two substitutions then cost about as much as
 // a line's reduced sweeps (2 n / m steps of a 2P x 2P block).
-// With short_chunks, a single line takes interior chunks of kShortChunk rows instead (two
-// waves of the segment kernel): the block-diagonal reduced system (see ensure_part) solves
+// With short_chunks, a single line (of any length from 256 rows) takes interior chunks of
+// kShortChunk rows instead (two waves of the segment kernel): the block-diagonal reduced
+// system (see ensure_part) solves
 // every interface at once, so more chunks cost no longer chain.  The exact sweeps of that
 // many chunks would not fit LDS, so the context falls back to the long chunks when the
 // truncation is refused.
@@ -883,7 +884,7 @@ iga::PartGeom part_geom(int n, long long lines, int p, bool short_chunks)
     int K;
     if (lines >= 64) {
         K = (n + 95) / 96;
-    } else if (lines == 1 && n >= 2 * kLineChunk && short_chunks) {
+    } else if (lines == 1 && short_chunks) {
         // I interior chunks of m rows leave r = n - I m in [32, 32 + m) rows to the ends:
         // one wave of the segment kernel each while r <= 2 kSeg, else the first one wave
         // (the end chunks' far spike ends are not part of the block-diagonal system)
