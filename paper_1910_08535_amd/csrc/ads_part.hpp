@@ -4,9 +4,10 @@
 //
 // The 1D matrix A (n x n, bandwidth P, the same for every line of the family) is cut into
 // K chunks of rows [s_k, e_k), e_k = s_{k+1}, of at least 64 >= 2P rows each (PartGeom):
-// balanced, s_k = floor(k n / K), or, for a single long line, interior chunks of exactly
-// m rows between a first and a last chunk of at most m rows, so that the interior chunks
-// have bitwise equal factors and run as the lines of one segment-kernel launch.  With D the block diagonal of the chunks' own blocks A_kk,
+// balanced, s_k = floor(k n / K), or, for a single line, interior chunks of exactly m rows
+// between a first and a last chunk (of 16 or more rows), so that the interior chunks have
+// bitwise equal factors and run as the lines of one segment-kernel launch.  With D the
+// block diagonal of the chunks' own blocks A_kk,
 // A = D (I + S), and the spikes of S are line-independent:
 //     V_k = A_kk^{-1} A(chunk k, first P columns of chunk k+1)     (e_k - s_k) x P
 //     W_k = A_kk^{-1} A(chunk k, last P columns of chunk k-1)      (e_k - s_k) x P
