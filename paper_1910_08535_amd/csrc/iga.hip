@@ -857,10 +857,10 @@ bool part_sweeps_fit(const iga::PartGeom& g, int p)
 // when the family keeps one recurrence per line: that is when its lines fill at least 128
 // workgroups of 64 lines (half the compute units) and fit the segment kernel (at most
 // 2 * 768 rows; longer lines would take the one-line-per-lane streaming kernel), when
-// the lines are shorter than 256
-// rows (the three launches of the partitioned solve then cost more than the short
-// recurrence: 37 against 32 us at 152 rows and 152 lines), or when a chunk would have
-// fewer than 64 rows.  With lines enough for the lanes of a wave the chunks are balanced and solved
+// the lines are shorter than 128 rows (with 128 to 255 rows the two launches of the
+// block-diagonal reduced system beat the whole lines: 2D 150^2 32 -> 25 us, 200^2
+// 38 -> 27 us for p = 2; the three launches of the exact sweeps about tie), or when a
+// chunk would have fewer than 64 rows.  With lines enough for the lanes of a wave the chunks are balanced and solved
 // by the segment kernel, at most 96 rows (two waves) each.  A single line of at least
 // 2 kLineChunk rows gets interior chunks of equal length, at most kLineChunk rows
 // (bitwise equal factors: one segment-kernel launch runs them as its lines), between a
@@ -880,7 +880,7 @@ iga::PartGeom part_geom(int n, long long lines, int p, bool short_chunks)
     iga::PartGeom g{n, 0, 0, 0};
     const long long total = lines * n;
     const int seg_cap = 2 * iga::kSeg * iga::kSegMaxWaves;
-    if (n < 256 || total >= (1LL << 31) || ((lines + 63) / 64 >= 128 && n <= seg_cap)) return g;
+    if (n < 128 || total >= (1LL << 31) || ((lines + 63) / 64 >= 128 && n <= seg_cap)) return g;
     int K;
     if (lines >= 64) {
         K = (n + 95) / 96;
