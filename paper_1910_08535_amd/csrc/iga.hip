@@ -884,6 +884,9 @@ iga::PartGeom part_geom(int n, long long lines, int p, bool short_chunks)
     int K;
     if (lines >= 64) {
         K = (n + 95) / 96;
+        // p = 3 chunks below 76 rows leave the dropped spike ends above 2^-64 (1.9e-17 at 64
+        // rows, falling 0.54 per row): fewer, longer chunks keep the block-diagonal path
+        if (p == 3) K = std::max(2, std::min(K, n / 76));
     } else if (lines == 1 && short_chunks) {
         // I interior chunks of m rows leave r = n - I m in [32, 32 + m) rows to the ends:
         // one wave of the segment kernel each while r <= 2 kSeg, else the first one wave
