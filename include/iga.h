@@ -60,6 +60,10 @@
  *   - Calls enqueue kernels on the context's HIP stream and return without waiting
  *     (asynchronous); argument errors are detected and returned before anything is
  *     enqueued.  One context per stream; calls on one context are not thread-safe.
+ *   - A call that would allocate device memory (context creation, the scratch of a
+ *     first call that needs it, the tables of a first solve) returns IGA_E_INVAL while
+ *     the context's stream is being captured into a graph; calls after it can be
+ *     captured.
  *   - Return value: IGA_OK (0) or a negative IGA_E_* code; nothing throws.
  *   - All arithmetic is FP64.
  */
@@ -196,8 +200,11 @@ int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, i
    neighbouring chunk boundaries is below 2^-64 (it decays geometrically along a chunk),
    the block system is taken as block diagonal; deciding this reads one small table back
    to the host at the context's first solve along the axis (one synchronisation of its
-   stream; during stream capture, and with the environment variable IGA_PART_EXACT set
-   to a value other than 0, the full block system is used).
+   stream; with the environment variable IGA_PART_EXACT set to a value other than 0, the
+   full block system is used; iga_solve_info reports the choice).
+   The first solve of a context allocates and builds these tables, so it must not be
+   captured into a graph (IGA_E_INVAL while the context's stream is capturing); once it
+   has run, solves can be captured and replayed.
    b, x: device coefficient arrays (N_z, N_y, N_x); x may equal b (in place); b is not
    modified unless x == b.  form: IGA_GALERKIN_BYPARTS or IGA_GALERKIN_LAPLACIAN (one
    mass matrix for both).
@@ -207,6 +214,22 @@ int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, i
    Errors: IGA_E_INVAL, IGA_E_SINGULAR for IGA_PG with spans made of whole elements (the
    PG mass matrix then has rank at most prod_a ne[a] < prod_a N_a), IGA_E_NOMEM. */
 int iga_solve(iga_ctx *ctx, int32_t form, const double *b, double *x);
+
+/* How the solves along axis `axis` (0 = x) of a context run, as chosen at its first solve
+   (host outputs, nullable): *scheme is
+     IGA_SOLVE_NONE            no solve has run on the context yet;
+     IGA_SOLVE_LINES           one forward and one backward recurrence along every line;
+     IGA_SOLVE_PART_EXACT      partitioned into *chunks chunks per line, the small block
+                               system that couples the chunks solved exactly along the line;
+     IGA_SOLVE_PART_BLOCKDIAG  partitioned, that block system taken as block diagonal (its
+                               dropped coupling below 2^-64, as described at iga_solve).
+   Reads host state only; never blocks.  Errors: IGA_E_INVAL (null ctx, axis outside
+   [0, dim)). */
+#define IGA_SOLVE_NONE 0
+#define IGA_SOLVE_LINES 1
+#define IGA_SOLVE_PART_EXACT 2
+#define IGA_SOLVE_PART_BLOCKDIAG 3
+int iga_solve_info(const iga_ctx *ctx, int32_t axis, int32_t *scheme, int32_t *chunks);
 
 /* nsteps forward-Euler steps of u_t = Lap u + f (Section 4.2) in a Galerkin form with
    the consistent mass:
@@ -273,6 +296,13 @@ int iga_dirichlet_rows(iga_ctx *ctx, int32_t form, int32_t side_mask, const doub
 int iga_set_tile(iga_ctx *ctx, int32_t key, int32_t value);
 int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);
 
+/* Bandwidth reference of the fused 2D apply (not part of the method): reads the n doubles
+   of src once and writes them to dst_a and dst_b (device, caller-owned, no overlap), with
+   the 16-byte accesses and streaming stores of the apply kernel, on hip_stream (NULL =
+   default stream).  Its time is the floor a launch moving the same bytes can reach.
+   Errors: IGA_E_INVAL (null pointer, n = 0 or n >= 2^29). */
+int iga_copy_probe(const double *src, double *dst_a, double *dst_b, size_t n, void *hip_stream);
+
 /* Error string of an IGA_* code (static storage). */
 const char *iga_strerror(int code);
 
@@ -319,9 +349,11 @@ int iga_batch_poll(iga_batch *b, uint64_t ticket, int32_t *state);
 /* Blocks until the running launch, if any, is done. */
 int iga_batch_wait(iga_batch *b);
 /* Autotuner: times the queued jobs (which stay queued; applies are idempotent) with
-   every chunk height of the 2D kernel, `reps` launches each (HIP events on the batch
-   stream), keeps the fastest for later launches and writes it to best_rows and its
-   time per launch in milliseconds to best_ms (host, both nullable). */
+   every chunk height of the 2D kernel: the job list is uploaded once per height, then
+   `reps` launches of the persistent kernel are timed with HIP events on the batch stream
+   (the launches only, no host work or copy between them).  Keeps the fastest height for
+   later launches and writes it to best_rows and its time per launch in milliseconds to
+   best_ms (host, both nullable).  Blocks until the timed launches are done. */
 int iga_batch_autotune(iga_batch *b, int32_t reps, int32_t *best_rows, float *best_ms);
 int iga_batch_destroy(iga_batch *b);
 

@@ -128,8 +128,22 @@ void retain_pool_memory()
     done[dev] = true;
 }
 
+// True when the context's stream is being captured into a graph.  Tables and scratch
+// are never built during capture: an allocation recorded into a caller's graph would
+// exist only while that graph runs, yet the context would keep using it.
+bool capturing(const iga_ctx* c)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
 int dalloc(iga_ctx* c, void** p, size_t bytes)
 {
+    if (capturing(c)) return IGA_E_INVAL;
     if (bytes == 0) bytes = 8;
     if (hipMallocAsync(p, bytes, c->stream) != hipSuccess) {
         (void)hipGetLastError();
@@ -145,6 +159,7 @@ int dalloc(iga_ctx* c, void** p, size_t bytes)
 int scratch(iga_ctx* c, double** buf, size_t* cap, size_t n)
 {
     if (*cap >= n && *buf) return IGA_OK;
+    if (capturing(c)) return IGA_E_INVAL;
     if (*buf) {
         auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)*buf);
         if (it != c->allocs.end()) c->allocs.erase(it);
@@ -1229,6 +1244,16 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
 
 extern "C" {
 
+int iga_copy_probe(const double* src, double* dst_a, double* dst_b, size_t n, void* hip_stream)
+{
+    if (!src || !dst_a || !dst_b || n == 0 || n >= ((size_t)1 << 29)) return IGA_E_INVAL;
+    const size_t threads = (n + 1) / 2;
+    hipLaunchKernelGGL(iga::copy2_kernel, dim3((unsigned)((threads + iga::kBlock - 1) / iga::kBlock)),
+                       dim3(iga::kBlock), 0, (hipStream_t)hip_stream, src, dst_a, dst_b, n);
+    IGA_HIP(hipGetLastError());
+    return IGA_OK;
+}
+
 const char* iga_strerror(int code)
 {
     switch (code) {
@@ -1592,6 +1617,21 @@ int iga_solve(iga_ctx* c, int32_t form, const double* b, double* x)
     }
     IGA_TRY(ensure_factors(c));
     return launch_solve(c, b, x, c->stream);
+}
+
+int iga_solve_info(const iga_ctx* c, int32_t axis, int32_t* scheme, int32_t* chunks)
+{
+    if (!c || axis < 0 || axis >= c->dim) return IGA_E_INVAL;
+    int32_t sc = IGA_SOLVE_NONE, k = 0;
+    if (c->part[axis]) {
+        sc = c->part_trunc[axis] ? IGA_SOLVE_PART_BLOCKDIAG : IGA_SOLVE_PART_EXACT;
+        k = c->part_g[axis].K;
+    } else if (c->chol[axis] || c->lu[axis]) {
+        sc = IGA_SOLVE_LINES;
+    }
+    if (scheme) *scheme = sc;
+    if (chunks) *chunks = k;
+    return IGA_OK;
 }
 
 int iga_galerkin_step(iga_ctx* c, int32_t form, double* u, double dt, const iga_source* f,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libiga.so")
 
 IGA_OK, IGA_E_INVAL, IGA_E_UNSUPPORTED, IGA_E_NOMEM, IGA_E_DEVICE, IGA_E_AGAIN = 0, -1, -2, -3, -4, -5
 IGA_E_SINGULAR = -6
+SOLVE_NONE, SOLVE_LINES, SOLVE_PART_EXACT, SOLVE_PART_BLOCKDIAG = 0, 1, 2, 3
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM, SPANS_REFINED = 0, 1, 2, 3
@@ -76,12 +77,14 @@ _SIGS = {
     "iga_apply": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "iga_explicit_step": [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Source), C.c_int32],
     "iga_solve": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "iga_solve_info": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "iga_boundary_terms": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Side), C.c_void_p, C.c_double,
                            C.c_double, C.c_void_p],
     "iga_dirichlet_rows": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
     "iga_galerkin_step": [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.POINTER(Source),
                           C.c_int32],
     "iga_strerror": [C.c_int],
+    "iga_copy_probe": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
     "iga_set_tile": [C.c_void_p, C.c_int32, C.c_int32],
     "iga_get_tile": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
     "iga_batch_create": [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
@@ -191,6 +194,12 @@ def iga_solve(h, form: int, b_ptr: int, x_ptr: int) -> None:
     _check(lib().iga_solve(h, form, C.c_void_p(b_ptr), C.c_void_p(x_ptr)), "iga_solve")
 
 
+def iga_solve_info(h, axis: int) -> Tuple[int, int]:
+    scheme, chunks = C.c_int32(), C.c_int32()
+    _check(lib().iga_solve_info(h, axis, C.byref(scheme), C.byref(chunks)), "iga_solve_info")
+    return scheme.value, chunks.value
+
+
 def iga_galerkin_step(h, form: int, u_ptr: int, dt: float, src: Optional[Source],
                       nsteps: int) -> None:
     _check(lib().iga_galerkin_step(h, form, C.c_void_p(u_ptr), dt,
@@ -206,6 +215,11 @@ def iga_get_tile(h, key: int) -> int:
     v = C.c_int32()
     _check(lib().iga_get_tile(h, key, C.byref(v)), "iga_get_tile")
     return v.value
+
+
+def iga_copy_probe(src_ptr: int, a_ptr: int, b_ptr: int, n: int, stream: int) -> None:
+    _check(lib().iga_copy_probe(C.c_void_p(src_ptr), C.c_void_p(a_ptr), C.c_void_p(b_ptr), n,
+                                C.c_void_p(stream)), "iga_copy_probe")
 
 
 # ---- torch convenience layer ----------------------------------------------------
@@ -329,6 +343,10 @@ class Mesh:
         x = out if out is not None else self._new(self.coef_shape())
         iga_solve(self.h, form, _ptr(b), _ptr(x))
         return x
+
+    def solve_info(self, axis: int) -> Tuple[int, int]:
+        """(scheme, chunks per line) of the solves along an axis (SOLVE_* constants)."""
+        return iga_solve_info(self.h, axis)
 
     def galerkin_step(self, u, dt: float, form: int = GALERKIN_LAPLACIAN, f_table=None,
                       sin_amp: float = 0.0, nsteps: int = 1):
