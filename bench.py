@@ -178,6 +178,28 @@ def run_c2(args):
     torch.cuda.synchronize()
     assert torch.equal(m, m2) and torch.equal(l, l2)
 
+    # copy floor: the same bytes (one read, two streamed writes per coefficient) moved by a
+    # plain copy kernel over the same rotated buffer sets, timed the same way
+    n = u0.numel()
+
+    def copy_step(k):
+        u, m, l = sets[k % nsets]
+        iga.iga_copy_probe(u.data_ptr(), m.data_ptr(), l.data_ptr(), n, stream.cuda_stream)
+
+    for k in range(args.warmup):
+        copy_step(k)
+    cgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cgraph, stream=stream):
+        for k in range(args.steps):
+            copy_step(k)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    cgraph.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    copy_s = ev0.elapsed_time(ev1) * 1e-3 / args.steps
+    assert torch.equal(sets[0][1], sets[0][0]) and torch.equal(sets[0][2], sets[0][0])
+
     achieved = BYTES_C2 / per_launch_s / 1e9
     traffic = measured_traffic("apply2d_p2_1024")
     out = {
@@ -205,6 +227,10 @@ def run_c2(args):
                      "kernel": "iga::apply2d_kernel<2, 8, 3, true>",
                      "algorithmic_bytes_per_launch": BYTES_C2,
                      "avg_launch_us": per_launch_s * 1e6},
+        "copy_floor": {"kernel": "iga::copy2_kernel (read once, two streamed writes)",
+                       "avg_launch_us": copy_s * 1e6, "GBs": BYTES_C2 / copy_s / 1e9,
+                       "frac": BYTES_C2 / copy_s / 1e9 / HBM_PEAK_GBS,
+                       "apply_over_floor": per_launch_s / copy_s},
     }
     return out
 

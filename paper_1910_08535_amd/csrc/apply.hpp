@@ -420,4 +420,23 @@ __global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__
     if (i < n) dst[i] = src[i];
 }
 
+// The memory traffic of the fused apply without its arithmetic: every value of src read
+// once, written to two arrays, 16 bytes per lane and access, outputs streamed past the
+// caches as the 2D kernel stores them.  A bandwidth reference, not part of the method.
+__global__ __launch_bounds__(kBlock) void copy2_kernel(const double* __restrict__ src, double* __restrict__ a,
+                                                       double* __restrict__ b, size_t n)
+{
+    const size_t i = 2 * ((size_t)blockIdx.x * kBlock + threadIdx.x);
+    const auto rs = buf(src, n), ra = buf(a, n), rb = buf(b, n);
+    if (i + 1 < n) {
+        const dv2 v = bload2(rs, (unsigned)(i * 8));
+        bstore2<kStream>(ra, (unsigned)(i * 8), v.x, v.y);
+        bstore2<kStream>(rb, (unsigned)(i * 8), v.x, v.y);
+    } else if (i < n) {
+        const double v = bload(rs, (unsigned)(i * 8));
+        bstore<kStream>(ra, (unsigned)(i * 8), v);
+        bstore<kStream>(rb, (unsigned)(i * 8), v);
+    }
+}
+
 }  // namespace iga

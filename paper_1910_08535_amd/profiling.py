@@ -5,6 +5,8 @@ Used by hand after a profiling run:
     python -m paper_1910_08535_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1910_08535_amd.profiling traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> <kernel substring> <copy MiB> <workload> "<commands>"
+    python -m paper_1910_08535_amd.profiling pmc <out.md> <kernel substring> "<commands>"
+        <counter_collection.csv> [...]
 
 `traffic` scales each counter by what it reads for a plain copy of known size (the
 torch copy kernel the benchmark runs with --copy-probe-mb), giving HBM bytes per launch
@@ -116,8 +118,59 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, worklo
     return rec
 
 
+# counters summed over the device per dispatch, and what each ratio below means
+_RATIOS = (
+    ("VALU instructions per wave", "SQ_INSTS_VALU", "SQ_WAVES"),
+    ("FP64 FMA instructions per wave", "SQ_INSTS_VALU_FMA_F64", "SQ_WAVES"),
+    ("LDS instructions per wave", "SQ_INSTS_LDS", "SQ_WAVES"),
+    ("vector memory instructions per wave", "SQ_INSTS_VMEM", "SQ_WAVES"),
+    ("scalar ALU instructions per wave", "SQ_INSTS_SALU", "SQ_WAVES"),
+    ("share of wave time waiting on a dependency (s_waitcnt)", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"),
+    ("share of wave time waiting for anything", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES"),
+    ("share of wave time issuing VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES"),
+)
+
+
+def pmc_markdown(out_md: str, kernel: str, command: str, csvs) -> dict:
+    """Median per dispatch of every counter collected for the kernels matching `kernel`
+    (rocprofv3 --pmc CSV files, one per pass), and the ratios above."""
+    vals = {}
+    name = None
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            if kernel not in r["Kernel_Name"]:
+                continue
+            name = r["Kernel_Name"]
+            vals.setdefault(r["Counter_Name"], {}).setdefault(r["Dispatch_Id"], 0.0)
+            vals[r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no dispatch of a kernel matching {kernel!r}")
+    med = {c: statistics.median(d.values()) for c, d in vals.items()}
+    lines = ["# rocprofv3 counters", "", f"Kernel: `{name}`", "",
+             "Commands (from the repository root, after `cd /tmp && export TMPDIR=/tmp` as the "
+             "profiler needs), one per pass:", "", "```", command, "```", "",
+             "| counter | median per dispatch | dispatches |", "|---|---|---|"]
+    for c in sorted(med):
+        lines.append(f"| {c} | {med[c]:.6g} | {len(vals[c])} |")
+    lines += ["", "| ratio | value |", "|---|---|"]
+    ratios = {}
+    for label, a, b in _RATIOS:
+        if a in med and b in med and med[b] > 0:
+            ratios[label] = med[a] / med[b]
+            lines.append(f"| {label} ({a} / {b}) | {ratios[label]:.4g} |")
+    fam = [k for k in KERNEL_SOURCES if k in name]
+    if fam:
+        lines += ["", f"Sources hash of {fam[0]} ({', '.join(KERNEL_SOURCES[fam[0]])}): "
+                      f"`{kernel_source_hash(fam[0])}`"]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return {"median": med, "ratios": ratios}
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
+    if sys.argv[1] == "pmc":
+        print(json.dumps(pmc_markdown(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:]), indent=1))
+    elif sys.argv[1] == "stats":
         stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),
