@@ -186,6 +186,20 @@ int iga_apply(iga_ctx *ctx, int32_t form, const double *u, double *mass_out, dou
    Errors: IGA_E_INVAL (also for other span kinds), IGA_E_NOMEM. */
 int iga_explicit_step(iga_ctx *ctx, double *u, double dt, const iga_source *f, int32_t nsteps);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): iga_explicit_step with the same kernels and
+   results, bit for bit, that allocates nothing.  The steps ping-pong between u and a work
+   buffer that is a static device array of the library, IGA_NOALLOC_MAX_DOUBLES doubles
+   (64 MiB) on every device the library runs on, held until the process ends; the call
+   launches directly (no graph is cached).  Every call on a device shares that device's
+   array, which keeps the last call's contents: calls that overlap on one device (other
+   streams, other threads, other contexts) race and must be ordered by the caller.
+   Sources: sin_amp only; a Gauss-point table gives IGA_E_UNSUPPORTED.
+   Errors: IGA_E_INVAL (as iga_explicit_step), IGA_E_UNSUPPORTED (table source),
+   IGA_E_NOMEM (more than IGA_NOALLOC_MAX_DOUBLES coefficients), IGA_E_DEVICE. */
+#define IGA_NOALLOC_MAX_DOUBLES ((size_t)1 << 23)
+int iga_explicit_step_noalloc(iga_ctx *ctx, double *u, double dt, const iga_source *f, int32_t nsteps);
+
 /* Alternating-directions direct solve with the Galerkin mass (Section 4.1):
      (M_z (x) M_y (x) M_x) x = b,   M_a(i, j) = int B_i B_j  on axis a,
    the matrix of the Galerkin L2 projection.  The Kronecker structure reduces it to

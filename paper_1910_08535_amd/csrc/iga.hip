@@ -69,6 +69,7 @@ struct iga_ctx {
     size_t elem_n = 0;
     double* work = nullptr;
     size_t work_n = 0;
+    double* scratch = nullptr;   // the device's static work buffer (iga_explicit_step_noalloc)
     // banded Cholesky factors of the Galerkin mass per axis (built at the first solve)
     double* chol[3] = {nullptr, nullptr, nullptr};
     // refined test space: refined elements per trial element, and the sweep tables (F | B)
@@ -156,7 +157,7 @@ int dalloc(iga_ctx* c, void** p, size_t bytes)
 
 // Scratch of at least n doubles, grown on demand.  The old buffer is released in
 // stream order, after every kernel queued before the growth.
-int scratch(iga_ctx* c, double** buf, size_t* cap, size_t n)
+int ensure_scratch(iga_ctx* c, double** buf, size_t* cap, size_t n)
 {
     if (*cap >= n && *buf) return IGA_OK;
     if (capturing(c)) return IGA_E_INVAL;
@@ -434,8 +435,8 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
     }
     const size_t nr = nrows(c, form);
     const size_t nelem_vals = form == IGA_PG ? nel : nel * (size_t)np1;
-    IGA_TRY(scratch(c, &c->elem, &c->elem_n, nelem_vals));
-    IGA_TRY(scratch(c, &c->farr, &c->farr_n, nr));
+    IGA_TRY(ensure_scratch(c, &c->elem, &c->elem_n, nelem_vals));
+    IGA_TRY(ensure_scratch(c, &c->farr, &c->farr_n, nr));
     sa.table = table;
     sa.elem = c->elem;
     sa.rows = c->farr;
@@ -592,9 +593,18 @@ struct AxisCache {
     // constants shared by every context of the device: {1, 0 x 7} | two int zeros | ones
     double* consts = nullptr;
     size_t nones = 0;
+    // this device's copy of `scratch` (below): the address of the symbol on the device
+    double* scratch = nullptr;
 };
 
 AxisCache g_cache[64];
+
+// Work buffer of iga_explicit_step_noalloc: a file-scope device array, one copy per device
+// for the life of the process.  Host code uses the address that hipGetSymbolAddress gives
+// for the current device, never the array's name (on the host that name is a stand-in,
+// not a device address).
+constexpr size_t kScratchDoubles = IGA_NOALLOC_MAX_DOUBLES;   // 64 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 AxisCache* device_cache()
 {
@@ -638,6 +648,15 @@ int shared_consts(iga_ctx* c, size_t n)
     c->unit = g->consts;
     c->zero = (int*)(g->consts + 8);
     c->ones = g->consts + 9;
+    if (!g->scratch) {   // once per device, with that device current
+        void* sp = nullptr;
+        if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+            (void)hipGetLastError();
+            return IGA_E_DEVICE;
+        }
+        g->scratch = (double*)sp;
+    }
+    c->scratch = g->scratch;
     return IGA_OK;
 }
 
@@ -1102,7 +1121,7 @@ int launch_part(iga_ctx* c, int a, iga::PartGeom g, int lines, int inner, const 
     // then one launch for the interfaces and the correction into x
     double* dst = x;
     if (trunc) {
-        IGA_TRY(scratch(c, &c->part_w, &c->part_w_n, (size_t)lines * n));
+        IGA_TRY(ensure_scratch(c, &c->part_w, &c->part_w_n, (size_t)lines * n));
         dst = c->part_w;
     }
     // a single line's end chunks solved inside part_fix_kernel, from src, which must then
@@ -1538,12 +1557,12 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
     const double* table = f ? f->table : nullptr;
     if (!std::isfinite(amp)) return IGA_E_INVAL;
     const size_t n = prod3(c->N);
-    IGA_TRY(scratch(c, &c->work, &c->work_n, n));
+    IGA_TRY(ensure_scratch(c, &c->work, &c->work_n, n));
     if (table) {   // make sure the source scratch exists before any capture
         size_t nel = 1;
         for (int a = 0; a < c->dim; ++a) nel *= (size_t)c->ne[a];
-        IGA_TRY(scratch(c, &c->elem, &c->elem_n, nel));
-        IGA_TRY(scratch(c, &c->farr, &c->farr_n, n));
+        IGA_TRY(ensure_scratch(c, &c->elem, &c->elem_n, nel));
+        IGA_TRY(ensure_scratch(c, &c->farr, &c->farr_n, n));
     }
     auto enqueue = [&](hipStream_t s) -> int {
         ApplyArgs g = make_args(c, IGA_PG, true, amp != 0.0);
@@ -1607,6 +1626,37 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
     return IGA_OK;
 }
 
+int iga_explicit_step_noalloc(iga_ctx* c, double* u, double dt, const iga_source* f, int32_t nsteps)
+{
+    if (!c || !u || nsteps < 0 || !std::isfinite(dt)) return IGA_E_INVAL;
+    if (c->spans != IGA_SPANS_SUPPORT) return IGA_E_INVAL;
+    if (f && f->table) return IGA_E_UNSUPPORTED;   // its element sums would need memory of their own
+    const double amp = f ? f->sin_amp : 0.0;
+    if (!std::isfinite(amp)) return IGA_E_INVAL;
+    const size_t n = prod3(c->N);
+    if (n > kScratchDoubles) return IGA_E_NOMEM;
+    if (!c->scratch) return IGA_E_DEVICE;
+    if (nsteps == 0) return IGA_OK;
+    // the launches of iga_explicit_step, ping-ponging through the static buffer
+    ApplyArgs g = make_args(c, IGA_PG, true, amp != 0.0);
+    g.alpha = 1.0;
+    g.beta = dt;
+    g.gsep = dt * amp;
+    g.garr = dt;
+    double* const work = c->scratch;
+    for (int k = 0; k < nsteps; ++k) {
+        g.u = (k & 1) ? work : u;
+        g.out = (k & 1) ? u : work;
+        IGA_TRY(launch_apply(c, g, c->stream, true));
+    }
+    if (nsteps & 1) {
+        hipLaunchKernelGGL(iga::copy_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           c->stream, u, (const double*)work, n);
+        IGA_HIP(hipGetLastError());
+    }
+    return IGA_OK;
+}
+
 int iga_solve(iga_ctx* c, int32_t form, const double* b, double* x)
 {
     if (!c || !b || !x || !valid_form(form)) return IGA_E_INVAL;
@@ -1645,7 +1695,7 @@ int iga_galerkin_step(iga_ctx* c, int32_t form, double* u, double dt, const iga_
     if (!std::isfinite(amp)) return IGA_E_INVAL;
     if (pg && table) return IGA_E_UNSUPPORTED;   // Gauss-point tables are on the trial grid
     if (nsteps == 0) return IGA_OK;
-    IGA_TRY(scratch(c, &c->work, &c->work_n, prod3(c->N)));
+    IGA_TRY(ensure_scratch(c, &c->work, &c->work_n, prod3(c->N)));
     IGA_TRY(pg ? ensure_lu(c) : ensure_factors(c));
     ApplyArgs g = make_args(c, form, false, amp != 0.0);
     g.alpha = 1.0;

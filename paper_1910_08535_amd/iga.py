@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libiga.so")
 IGA_OK, IGA_E_INVAL, IGA_E_UNSUPPORTED, IGA_E_NOMEM, IGA_E_DEVICE, IGA_E_AGAIN = 0, -1, -2, -3, -4, -5
 IGA_E_SINGULAR = -6
 SOLVE_NONE, SOLVE_LINES, SOLVE_PART_EXACT, SOLVE_PART_BLOCKDIAG = 0, 1, 2, 3
+NOALLOC_MAX_DOUBLES = 1 << 23   # coefficients iga_explicit_step_noalloc takes at most
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM, SPANS_REFINED = 0, 1, 2, 3
@@ -76,6 +77,7 @@ _SIGS = {
                 C.POINTER(Source), C.c_void_p],
     "iga_apply": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "iga_explicit_step": [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Source), C.c_int32],
+    "iga_explicit_step_noalloc": [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(Source), C.c_int32],
     "iga_solve": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
     "iga_solve_info": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "iga_boundary_terms": [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Side), C.c_void_p, C.c_double,
@@ -177,6 +179,12 @@ def iga_explicit_step(h, u_ptr: int, dt: float, src: Optional[Source], nsteps: i
     _check(lib().iga_explicit_step(h, C.c_void_p(u_ptr), dt,
                                    C.byref(src) if src is not None else None, nsteps),
            "iga_explicit_step")
+
+
+def iga_explicit_step_noalloc(h, u_ptr: int, dt: float, src: Optional[Source], nsteps: int) -> None:
+    _check(lib().iga_explicit_step_noalloc(h, C.c_void_p(u_ptr), dt,
+                                           C.byref(src) if src is not None else None, nsteps),
+           "iga_explicit_step_noalloc")
 
 
 def iga_boundary_terms(h, form: int, sides, u_ptr: int, alpha: float, beta: float, b_ptr: int) -> None:
