@@ -7,17 +7,29 @@
 //
 // A workgroup owns an output tile of TX x TY rows of every plane of a z-chunk of TZ
 // planes and streams through the chunk plane by plane:
-//   * every thread owns a fixed set of (x, y) points of the tile's input footprint (the
-//     tile plus p-wide halos, clipped to the array); their coefficients of the last 2p+1
-//     planes sit in a register ring, so each coefficient is loaded once per chunk and the
-//     z-halo planes cost loads only, never arithmetic;
-//   * the z pass writes Z1, Z2 of the footprint to LDS; the y pass (two output rows per
-//     task, so 2p+2 loads feed 2 outputs) writes Y1, Y2 to LDS; the x pass (two output
-//     columns per task, 128-bit LDS reads) forms the rows and stores them;
-//   * tasks are enumerated flat over the tile, so tiles of any width keep the lanes busy.
-// Band entries: rows of the interior range of an axis share one set of taps, which every
-// thread holds once (uniform loads); only the few tasks that touch the first or last 2p
-// rows of an axis read their own rows' taps.  Taps of the z pass are uniform per plane.
+//   * every thread owns fixed (x, y) points of the tile's input footprint (the tile plus
+//     p-wide halos, clipped to the array); their coefficients of the planes zo-p .. zo+p
+//     sit in a register ring (2p slots rotating, the newest plane in its own register), so
+//     each coefficient is loaded once per chunk and the z-halo planes cost loads only;
+//   * the three passes are software-pipelined over the planes: step k runs the z pass of
+//     plane k (registers -> LDS stage Z), the y pass of plane k-1 (stage Z -> stage Y) and
+//     the x pass of plane k-2 (stage Y -> memory), each stage double-buffered, so a plane
+//     costs ONE workgroup barrier and the work of three planes is in flight together;
+//   * every thread has at most one y task (two output rows of one footprint column, from
+//     the 2p + 2 values of that column: stage Z is stored by columns, an odd column stride
+//     keeping lanes on distinct banks) and one x task (two output columns of one row, from
+//     128-bit reads of a stage Y row, stored with one 16-byte access); the tasks are fixed
+//     per thread for the whole chunk, so their addresses are computed once;
+//   * tasks of interior rows (columns) come first, padded to whole waves, so that each
+//     wave takes one branch of the tap choice; interior taps are read with uniform
+//     (scalar) loads, the rows at the ends of an axis read their own taps, staged in LDS
+//     once per workgroup.  Taps of the z pass are uniform per plane;
+//   * each step issues the same memory operations in every thread (the ring prefetch and
+//     the x task's stores, out of the buffer's range where there is nothing to store), so
+//     the waits for the prefetched plane never have to drain the stores.
+// Without mass output the y pass folds the operator weights into one array,
+// B = alpha Y1 + beta Y2, so the x pass forms  alpha mass + beta lap = Mx B + beta Dx Y1
+// with two stencils instead of three.
 #pragma once
 
 #include "apply.hpp"
@@ -29,33 +41,28 @@ namespace iga {
 struct Plan3D {
     int tx, ty, tz, nblk;   // tiles along x, y and z-chunks; their product
     int TX, TY, TZ;         // output rows per tile along x (even), y, z
-    int LW;                 // LDS row length: TX + 2p (even)
+    int LW;                 // footprint columns: TX + 2p
+    int LS;                 // row stride of the LDS stages: LW rounded up to even
+    int LH;                 // footprint rows: TY + 2p
 };
+
+constexpr int kRY3 = 2;        // output rows per y task
+constexpr int kMaxNT3 = 512;   // threads per workgroup, at most
 
 // footprint points per thread (z pass): the register ring holds (2p+1) x npz values
 __host__ __device__ constexpr int npz(int P)
 {
     return P == 3 ? 2 : 3;
 }
-constexpr int kMaxNT3 = 512;   // threads per workgroup, at most
 
-// LDS of a plan.  Z1, Z2 are stored by column (LW columns of zcol(TY, P) doubles: the
-// footprint's TY + 2p rows, padded to an odd count so that lanes reading neighbouring
-// columns hit different banks) -- the y pass then reads consecutive addresses; Y1, Y2
-// are stored by row (TY rows of LW doubles) for the x pass.
-__host__ __device__ inline int zcol(int TY, int P)
+// LDS of a plan, in doubles: stage Z (two buffers of Z1 | Z2, LW columns of (LH | 1)),
+// stage Y (two buffers of A | B, TY rows of LS), then, staged once per workgroup, the band rows
+// of the tile's x columns and y rows ([M (2p+1) | D (2p+1)] each; read only by tasks on
+// the first or last rows of an axis) and their S and F factors.
+__host__ __device__ inline size_t lds3d_doubles(int TX, int TY, int LS, int LH, int P)
 {
-    return (TY + 2 * P) | 1;
-}
-
-// After them, staged once per workgroup: the band rows of the tile's x columns and y
-// rows ([M (2p+1) | D (2p+1)] each; read only by tasks on the first or last 2p rows of
-// an axis) and their S and F factors.  The plane loop then issues no global loads besides
-// the coefficient prefetch, so no memory wait in it drains that prefetch.
-__host__ __device__ inline size_t lds3d_doubles(int TX, int TY, int LW, int P)
-{
-    return (size_t)(2 * zcol(TY, P) + 2 * TY) * (size_t)LW + (size_t)(TX + TY) * (4 * P + 2) +
-           2 * (size_t)(TX + TY);
+    const size_t zsz = (size_t)(LH | 1) * (TX + 2 * P);   // stage Z by columns
+    return 4 * zsz + 4 * (size_t)TY * LS + (size_t)(TX + TY) * (4 * P + 2) + 2 * (size_t)(TX + TY);
 }
 
 // Band rows r0 .. r0+n-1 of an axis into LDS rows of 2W doubles (rows past the axis: 0).
@@ -80,9 +87,6 @@ __device__ __forceinline__ void lds_taps(double (&m)[W], double (&d)[W], const d
         d[k] = row[W + k];
     }
 }
-
-// Unaligned (8-byte) pair of doubles: one 16-byte store where the hardware allows it.
-typedef double dv2u __attribute__((ext_vector_type(2), aligned(8)));
 
 // Loads through the constant address space: with a uniform address the compiler issues
 // scalar loads, and the taps then occupy scalar registers instead of vector ones.
@@ -110,9 +114,44 @@ __device__ __forceinline__ int opaque(int v)
     return v;
 }
 
+// Rows idx and idx + 1 (the second only when `two`) from v = alpha mass + beta lap, with
+// the epilogue of row_value (sources, then the scale) and one 16-byte store per pair.
+template <int MODE>
+__device__ __forceinline__ void finish_folded(const ApplyArgs& g, size_t idx, double v0, double s0, double f0,
+                                              double v1, double s1, double f1, bool two)
+{
+    typedef double pair_t __attribute__((ext_vector_type(2), aligned(8)));
+    double a0 = 0.0, a1 = 0.0;
+    if constexpr ((MODE & kFarr) != 0) {
+        if (two) {
+            const pair_t fa = *reinterpret_cast<const pair_t*>(g.farr + idx);
+            a0 = fa.x;
+            a1 = fa.y;
+        } else {
+            a0 = g.farr[idx];
+        }
+    }
+    if constexpr ((MODE & kScaleSrc) != 0) {
+        v0 = fma(g.gsep, f0, v0);
+        v1 = fma(g.gsep, f1, v1);
+    }
+    if constexpr ((MODE & kFarr) != 0) {
+        v0 = fma(g.garr, a0, v0);
+        v1 = fma(g.garr, a1, v1);
+    }
+    if constexpr ((MODE & kScaleSrc) != 0) {
+        v0 *= s0;
+        v1 *= s1;
+    }
+    if (two)
+        *reinterpret_cast<pair_t*>(g.out + idx) = pair_t{v0, v1};
+    else
+        g.out[idx] = v0;
+}
+
 // One output of a pass: a stencil over a[o .. o+2P] (first factor) and b[] (second).
-template <int P>
-__device__ __forceinline__ void pstep(const double (&a)[2 * P + 2], const double (&b)[2 * P + 2], int o,
+template <int P, int N>
+__device__ __forceinline__ void pstep(const double (&a)[N], const double (&b)[N], int o,
                                       const double (&m)[2 * P + 1], const double (&d)[2 * P + 1],
                                       double& y1, double& y2)
 {
@@ -125,23 +164,23 @@ __device__ __forceinline__ void pstep(const double (&a)[2 * P + 2], const double
     }
 }
 
-// y pass of one task: output rows r and r+1 from the 2P+2 values a[], b[] of Z1, Z2 in
-// the column (input rows r-P .. r+P+1).
-template <int P>
-__device__ __forceinline__ void ypair(const double (&a)[2 * P + 2], const double (&b)[2 * P + 2],
-                                      const double (&m0)[2 * P + 1], const double (&d0)[2 * P + 1],
-                                      const double (&m1)[2 * P + 1], const double (&d1)[2 * P + 1],
-                                      double& y10, double& y20, double& y11, double& y21)
+// The x pass of one output column (offset o in the 2P + 2 values a[] (Y1) and b[] (Y2, or
+// the folded B)).  Folded: o0 = Mx B, o1 = Dx Y1 (the row is alpha mass + beta lap =
+// o0 + beta o1); otherwise o0 = mass, o1 = lap.
+template <int P, bool FOLD>
+__device__ __forceinline__ void xcol(const double (&a)[2 * P + 2], const double (&b)[2 * P + 2], int o,
+                                     const double (&m)[2 * P + 1], const double (&d)[2 * P + 1], double& o0,
+                                     double& o1)
 {
-    y10 = y20 = y11 = y21 = 0.0;
+    if constexpr (FOLD) {
+        o0 = o1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 2 * P + 1; ++k) {
-        y10 = fma(m0[k], a[k], y10);
-        y20 = fma(d0[k], a[k], y20);
-        y20 = fma(m0[k], b[k], y20);
-        y11 = fma(m1[k], a[k + 1], y11);
-        y21 = fma(d1[k], a[k + 1], y21);
-        y21 = fma(m1[k], b[k + 1], y21);
+        for (int k = 0; k < 2 * P + 1; ++k) {
+            o0 = fma(m[k], b[k + o], o0);
+            o1 = fma(d[k], a[k + o], o1);
+        }
+    } else {
+        pstep<P>(a, b, o, m, d, o0, o1);
     }
 }
 
@@ -150,229 +189,308 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
 {
     constexpr int W = 2 * P + 1;
     constexpr int kNPZ = npz(P);
+    constexpr bool kFold = (MODE & kMass) == 0;   // B = alpha Y1 + beta Y2
     extern __shared__ __attribute__((aligned(16))) double lds3[];
     const AxisOp &X = g.ax[0], &Y = g.ax[1], &Z = g.ax[2];
-    const int NT = (int)blockDim.x, tid = (int)threadIdx.x;
+    const int tid = (int)threadIdx.x;
     const int L = xcd_logical_block((int)blockIdx.x, pl.nblk);
     const int bx = L % pl.tx, by = (L / pl.tx) % pl.ty, bz = L / (pl.tx * pl.ty);
     const int x0 = bx * pl.TX, y0 = by * pl.TY, z0 = bz * pl.TZ;
     const int x1 = min(x0 + pl.TX, X.R), y1 = min(y0 + pl.TY, Y.R), z1 = min(z0 + pl.TZ, Z.R);
     if (x0 >= x1 || y0 >= y1 || z0 >= z1) return;   // the whole workgroup
-    const int LW = pl.LW, LH = zcol(pl.TY, P);
-    double* sZ1 = lds3;                 // [LW][LH]: column-major
-    double* sZ2 = sZ1 + LH * LW;
-    double* sY1 = sZ2 + LH * LW;        // [TY][LW]: row-major
-    double* sY2 = sY1 + pl.TY * LW;
-
-    // band rows of the tile's columns and rows, then their S and F: [x S | x F | y S | y F]
-    double* tx_ = sY2 + pl.TY * LW;
-    double* ty_ = tx_ + pl.TX * 2 * W;
-    double* sfx = ty_ + pl.TY * 2 * W;
-    double* sfy = sfx + 2 * pl.TX;
-    stage_taps<W>(tx_, X, x0, pl.TX, tid, NT);
-    stage_taps<W>(ty_, Y, y0, pl.TY, tid, NT);
-
-    // LDS slots outside the array stay zero for the whole chunk
-    const int nl = (2 * LH + 2 * pl.TY) * LW;
-    for (int i = tid; i < nl; i += NT) lds3[i] = 0.0;
-    if constexpr ((MODE & kScaleSrc) != 0) {
-        for (int i = tid; i < pl.TX; i += NT) {
-            const int x = min(x0 + i, X.R - 1);
-            sfx[i] = X.S[x];
-            sfx[pl.TX + i] = X.F[x];
-        }
-        for (int i = tid; i < pl.TY; i += NT) {
-            const int y = min(y0 + i, Y.R - 1);
-            sfy[i] = Y.S[y];
-            sfy[pl.TY + i] = Y.F[y];
-        }
+    const int LS = pl.LS, LH = pl.LH;
+    const int LHc = LH | 1;             // column stride of stage Z (odd: no bank conflicts)
+    const int zsz = LHc * pl.LW, ysz = pl.TY * LS;
+    double* const sZ = lds3;            // [2 buffers][Z1 | Z2][LW columns][LHc]
+    double* const sY = sZ + 4 * zsz;    // [2 buffers][A | B][TY][LS]
+    double* const tx_ = sY + 4 * ysz;   // band rows of the tile's columns, then rows
+    double* const ty_ = tx_ + pl.TX * 2 * W;
+    double* const sfx = ty_ + pl.TY * 2 * W;   // [x S | x F | y S | y F]
+    double* const sfy = sfx + 2 * pl.TX;
+    stage_taps<W>(tx_, X, x0, pl.TX, tid, kMaxNT3);
+    stage_taps<W>(ty_, Y, y0, pl.TY, tid, kMaxNT3);
+    for (int i = tid; i < 4 * (zsz + ysz); i += kMaxNT3) lds3[i] = 0.0;
+    for (int i = tid; i < pl.TX; i += kMaxNT3) {
+        const int x = min(x0 + i, X.R - 1);
+        sfx[i] = X.S[x];
+        sfx[pl.TX + i] = X.F[x];
+    }
+    for (int i = tid; i < pl.TY; i += kMaxNT3) {
+        const int y = min(y0 + i, Y.R - 1);
+        sfy[i] = Y.S[y];
+        sfy[pl.TY + i] = Y.F[y];
     }
 
-    // footprint of the tile: input columns xa..xb-1 and rows ya..yb-1
-    const int NX = X.N, NY = Y.N, NZ = Z.N;
+    // ---- footprint points of this thread (z pass): input columns xa..xb-1, rows ya..yb-1
+    const int NX = X.N, NYc = Y.N, NZ = Z.N;
     const int xa = max(x0 - P, 0), xb = min(x1 + P, NX);
-    const int ya = max(y0 - P, 0), yb = min(y1 + P, NY);
+    const int ya = max(y0 - P, 0), yb = min(y1 + P, NYc);
     const int RW = xb - xa, npt = RW * (yb - ya);
+    const int lc0 = xa - (x0 - P);   // stage column of input column xa
     unsigned goff[kNPZ];
     int loff[kNPZ];
 #pragma unroll
     for (int i = 0; i < kNPZ; ++i) {
-        const int j = tid + i * NT;
+        const int j = tid + i * kMaxNT3;
         const int r = j / RW, cc = j - r * RW;
         const bool ok = j < npt;
         goff[i] = ok ? (unsigned)((ya + r) * NX + xa + cc) * 8u : kOOB;
-        loff[i] = ok ? (xa + cc - (x0 - P)) * LH + (ya + r - (y0 - P)) : -1;
+        loff[i] = ok ? (lc0 + cc) * LHc + (ya + r - (y0 - P)) : -1;
     }
-    const size_t plane = (size_t)NX * NY;
+    const size_t plane = (size_t)NX * NYc;
     auto plane_buf = [&](int zi) {
-        const bool ok = zi >= 0 && zi < NZ;
+        const bool ok = zi >= 0 && zi < NZ && zi < z1 + P;
         return buf(g.u + (ok ? (size_t)zi * plane : 0), ok ? plane : 0);
     };
 
-    // ring: plane z0 - P + s in slot s (mod W); slot 2P is loaded last
-    double rz[W][kNPZ];
-#pragma unroll
-    for (int s = 0; s < W; ++s) {
-        const auto rb = plane_buf(z0 - P + s);
-#pragma unroll
-        for (int i = 0; i < kNPZ; ++i) rz[s][i] = bload(rb, goff[i]);
+    // ---- the y task of this thread: output rows 2q, 2q+1 of footprint column c; tasks of
+    // interior row pairs first, padded to whole waves, so that every wave takes one branch
+    const int TYv = y1 - y0, TXv = x1 - x0, TZv = z1 - z0;
+    const int nqy = (TYv + 1) >> 1;
+    int qa = Y.ilo - y0;
+    qa = qa <= 0 ? 0 : (qa + 1) >> 1;                  // first pair with y0 + 2q >= ilo
+    int qb = Y.ihi - y0 - 1;
+    qb = qb < 0 ? 0 : (qb >> 1) + 1;                   // pairs with y0 + 2q + 1 <= ihi
+    qa = min(qa, nqy);
+    qb = min(max(qb, qa), nqy);
+    const int nYI = (qb - qa) * RW, nYIp = (nYI + 63) & ~63, nYB = (nqy - (qb - qa)) * RW;
+    bool yv, yint;
+    int yq, yc;
+    if (tid < nYIp) {
+        yint = true;
+        yv = tid < nYI;
+        const int t = yv ? tid : 0;
+        yq = qa + t / RW;
+        yc = t - (t / RW) * RW;
+    } else {
+        yint = false;
+        const int t0 = tid - nYIp;
+        yv = t0 < nYB;
+        const int t = yv ? t0 : 0;
+        const int j = t / RW;
+        yq = j < qa ? j : j + (qb - qa);
+        yc = t - j * RW;
     }
-    __syncthreads();   // LDS zeroed before the first footprint write
+    const int ylc = lc0 + yc;
+    const int yrd = ylc * LHc + 2 * yq;                // stage offset of footprint row 2q
+    const bool ytwo = 2 * yq + 1 < TYv;
 
-    // task counts of the y and x passes
-    const int TYv = y1 - y0, TXv = x1 - x0;
-    const int npy = (TYv + 1) >> 1;
+    // ---- the x task of this thread: output columns 2i, 2i+1 of tile row r; interior
+    // pairs first, padded to whole waves
     const int npx = (TXv + 1) >> 1;
     int ia = X.ilo - x0;
-    ia = ia <= 0 ? 0 : (ia + 1) >> 1;                  // first pair with x0 + 2i >= ilo
+    ia = ia <= 0 ? 0 : (ia + 1) >> 1;
     int ib = X.ihi - x0 - 1;
-    ib = ib < 0 ? 0 : (ib >> 1) + 1;                   // pairs with x0 + 2i + 1 <= ihi
+    ib = ib < 0 ? 0 : (ib >> 1) + 1;
     ia = min(ia, npx);
     ib = min(max(ib, ia), npx);
     const int nI = ib - ia, nB = npx - nI;
-    const int ntxI = TYv * nI, ntx = TYv * npx;
-    const int lc0 = xa - (x0 - P);   // LDS column of input column xa
-    // strides of the division-free task walks (NT tasks per step)
-    const int ydq = NT / RW, ydc = NT - (NT / RW) * RW;
-    const int xdr = nI > 0 ? NT / nI : 0, xdi = nI > 0 ? NT - (NT / nI) * nI : 0;
+    const int nXI = TYv * nI, nXIp = (nXI + 63) & ~63, nXB = TYv * nB;
+    bool xv, xint;
+    int xr, xi;
+    if (tid < nXIp) {
+        xint = true;
+        xv = tid < nXI;
+        const int t = xv ? tid : 0;
+        xr = nI > 0 ? t / nI : 0;
+        xi = ia + (t - xr * nI);
+    } else {
+        xint = false;
+        const int t0 = tid - nXIp;
+        xv = t0 < nXB;
+        const int t = xv ? t0 : 0;
+        xr = nB > 0 ? t / nB : 0;
+        const int j = t - xr * nB;
+        xi = j < ia ? j : j + nI;
+    }
+    xi = min(xi, npx - 1);
+    const int xrd = xr * LS + 2 * xi;                  // stage offset of the task's first input
+    const int gx = x0 + 2 * xi, gy = y0 + xr;
+    const bool xtwo = gx + 1 < x1;
+    const unsigned pin = (unsigned)(gy * X.R + gx) * 8u;   // byte offset inside an output plane
+    const unsigned opair = xv && xtwo ? pin : kOOB, osing = xv && !xtwo ? pin : kOOB;
+    __syncthreads();   // stages zeroed, taps and factors staged
 
-    int cur = 0;   // slot of plane zo - P
-    for (int zo = z0; zo < z1; ++zo) {
-        // ---- z pass (slot layout known at compile time in each branch) ----
-        double zm[W], zd[W];
-        uniform_row<W>(zm, zd, Z.M, Z.D, opaque(zo));
+
+    // ring: planes z0 - P .. z0 + P - 1 in slots 0 .. 2P-1 (slot s holds plane zo - P + s
+    // shifted by the phase), plane z0 + P in `nv`
+    double rz[2 * P][kNPZ], nv[kNPZ];
 #pragma unroll
-        for (int ph = 0; ph < W; ++ph) {
-            if (ph == cur) {
+    for (int s2 = 0; s2 < 2 * P; ++s2) {
+        const auto rb = plane_buf(z0 - P + s2);
 #pragma unroll
-                for (int i = 0; i < kNPZ; ++i) {
-                    double s1 = 0.0, s2 = 0.0;
+        for (int i = 0; i < kNPZ; ++i) rz[s2][i] = bload(rb, goff[i]);
+    }
+    {
+        const auto rb = plane_buf(z0 + P);
 #pragma unroll
-                    for (int k = 0; k < W; ++k) {
-                        const double v = rz[(ph + k) % W][i];
-                        s1 = fma(zm[k], v, s1);
-                        s2 = fma(zd[k], v, s2);
-                    }
-                    if (loff[i] >= 0) {
-                        sZ1[loff[i]] = s1;
-                        sZ2[loff[i]] = s2;
+        for (int i = 0; i < kNPZ; ++i) nv[i] = bload(rb, goff[i]);
+    }
+    const size_t oplane = (size_t)X.R * Y.R;
+
+    int cur = 0;   // ring slot of plane zo - P
+    for (int k = 0; k < TZv + 2; ++k) {
+        // ---- z pass of plane z0 + k into stage Z buffer (k & 1) (past the chunk: harmless
+        // values into a buffer no later pass reads) ----
+        {
+            const int zo = min(z0 + k, z1 - 1);
+            double* const z1s = sZ + (k & 1) * 2 * zsz;
+            double* const z2s = z1s + zsz;
+            double zm[W], zd[W];
+            uniform_row<W>(zm, zd, Z.M, Z.D, opaque(zo));
+#pragma unroll
+            for (int ph = 0; ph < 2 * P; ++ph) {
+                if (ph == cur) {
+#pragma unroll
+                    for (int i = 0; i < kNPZ; ++i) {
+                        if (k < TZv && loff[i] >= 0) {   // the last two steps only rotate
+                            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                            for (int kk = 0; kk < 2 * P; ++kk) {
+                                const double v = rz[(ph + kk) % (2 * P)][i];
+                                s1 = fma(zm[kk], v, s1);
+                                s2 = fma(zd[kk], v, s2);
+                            }
+                            s1 = fma(zm[2 * P], nv[i], s1);
+                            s2 = fma(zd[2 * P], nv[i], s2);
+                            z1s[loff[i]] = s1;
+                            z2s[loff[i]] = s2;
+                        }
+                        rz[ph][i] = nv[i];   // plane zo - P leaves, plane zo + P takes its slot
                     }
                 }
-                // plane zo - P is no longer needed: its slot takes plane zo + P + 1
-                const auto rb = plane_buf(zo + P + 1 < z1 + P ? zo + P + 1 : -1);
-#pragma unroll
-                for (int i = 0; i < kNPZ; ++i) rz[ph][i] = bload(rb, goff[i]);
             }
+            cur = cur == 2 * P - 1 ? 0 : cur + 1;
+            const auto rb = plane_buf(z0 + k + P + 1);
+#pragma unroll
+            for (int i = 0; i < kNPZ; ++i) nv[i] = bload(rb, goff[i]);
         }
-        cur = cur == W - 1 ? 0 : cur + 1;
-        __syncthreads();
 
-        // ---- y pass: rows y0 + 2q, y0 + 2q + 1 of footprint column xa + c ----
-        double yim[W], yid[W];
-        uniform_row<W>(yim, yid, Y.M, Y.D, opaque(Y.ilo <= Y.ihi ? Y.ilo : 0));
-        // task t = q * RW + c, walked without divisions
-        int q = tid / RW, c = tid - (tid / RW) * RW;
-        for (; q < npy;) {
-            const int r0 = y0 + 2 * q;
-            const int lc = lc0 + c;
-            const double* z1p = sZ1 + lc * LH + 2 * q;   // input rows r0 - P .. r0 + P + 1
-            const double* z2p = sZ2 + lc * LH + 2 * q;
-            double a[2 * P + 2], b[2 * P + 2];
+        // ---- y pass of plane z0 + k - 1: stage Z buffer ((k-1) & 1) -> stage Y ----
+        if (yv && k >= 1 && k <= TZv) {
+            const double* const c1 = sZ + ((k - 1) & 1) * 2 * zsz + yrd;
+            const double* const c2 = c1 + zsz;
+            double* const ya_ = sY + ((k - 1) & 1) * 2 * ysz + 2 * yq * LS + ylc;
+            double* const yb_ = ya_ + ysz;
+            double y10 = 0.0, y20 = 0.0, y11 = 0.0, y21 = 0.0;
+            if (yint) {
+                double yim[W], yid[W];
+                uniform_row<W>(yim, yid, Y.M, Y.D, opaque(Y.ilo <= Y.ihi ? Y.ilo : 0));
 #pragma unroll
-            for (int k = 0; k < 2 * P + 2; ++k) {
-                a[k] = z1p[k];
-                b[k] = z2p[k];
-            }
-            double y10, y20, y11, y21;
-            if (r0 >= Y.ilo && r0 + 1 <= Y.ihi) {
-                ypair<P>(a, b, yim, yid, yim, yid, y10, y20, y11, y21);
+                for (int kk = 0; kk < 2 * P + 2; ++kk) {
+                    const double av = c1[kk], bv = c2[kk];
+                    if (kk <= 2 * P) {
+                        y10 = fma(yim[kk], av, y10);
+                        y20 = fma(yid[kk], av, y20);
+                        y20 = fma(yim[kk], bv, y20);
+                    }
+                    if (kk >= 1) {
+                        y11 = fma(yim[kk - 1], av, y11);
+                        y21 = fma(yid[kk - 1], av, y21);
+                        y21 = fma(yim[kk - 1], bv, y21);
+                    }
+                }
             } else {
                 double m[W], d[W];
-                lds_taps<W>(m, d, ty_ + (2 * q) * 2 * W);
-                pstep<P>(a, b, 0, m, d, y10, y20);
-                lds_taps<W>(m, d, ty_ + (2 * q + 1) * 2 * W);
-                pstep<P>(a, b, 1, m, d, y11, y21);
+                lds_taps<W>(m, d, ty_ + (2 * yq) * 2 * W);
+#pragma unroll
+                for (int kk = 0; kk < W; ++kk) {
+                    const double av = c1[kk], bv = c2[kk];
+                    y10 = fma(m[kk], av, y10);
+                    y20 = fma(d[kk], av, y20);
+                    y20 = fma(m[kk], bv, y20);
+                }
+                lds_taps<W>(m, d, ty_ + (2 * yq + 1) * 2 * W);
+#pragma unroll
+                for (int kk = 0; kk < W; ++kk) {
+                    const double av = c1[kk + 1], bv = c2[kk + 1];
+                    y11 = fma(m[kk], av, y11);
+                    y21 = fma(d[kk], av, y21);
+                    y21 = fma(m[kk], bv, y21);
+                }
             }
-            sY1[(2 * q) * LW + lc] = y10;
-            sY2[(2 * q) * LW + lc] = y20;
-            if (r0 + 1 < y1) {
-                sY1[(2 * q + 1) * LW + lc] = y11;
-                sY2[(2 * q + 1) * LW + lc] = y21;
-            }
-            c += ydc;
-            q += ydq;
-            if (c >= RW) {
-                c -= RW;
-                ++q;
+            ya_[0] = y10;
+            yb_[0] = kFold ? fma(g.alpha, y10, g.beta * y20) : y20;
+            if (ytwo) {
+                ya_[LS] = y11;
+                yb_[LS] = kFold ? fma(g.alpha, y11, g.beta * y21) : y21;
             }
         }
-        __syncthreads();
 
-        // ---- x pass: columns x0 + 2i, x0 + 2i + 1 of row y; interior pairs first ----
-        const int oz = zo;
-        const double sz = Z.S[oz], fz = Z.F[oz];
-        double xim[W], xid[W];
-        uniform_row<W>(xim, xid, X.M, X.D, opaque(X.ilo <= X.ihi ? X.ilo : 0));
-        // interior tasks t = row * nI + ii, walked without divisions
-        int irow = 0, ii = 0;
-        if (nI > 0) {
-            irow = tid / nI;
-            ii = tid - irow * nI;
-        }
-        for (int t = tid; t < ntx; t += NT) {
-            int row, i;
-            bool inner;
-            if (t < ntxI) {
-                row = irow;
-                i = ia + ii;
-                inner = true;
-            } else {
-                const int b = t - ntxI;
-                row = b / nB;
-                const int j = b - row * nB;
-                i = j < ia ? j : j + nI;
-                inner = false;
-            }
-            // LDS positions 2i .. 2i + 2P + 1 hold input columns x0 + 2i - P ..
-            const dv2* p1 = reinterpret_cast<const dv2*>(sY1 + row * LW + 2 * i);
-            const dv2* p2 = reinterpret_cast<const dv2*>(sY2 + row * LW + 2 * i);
+        // ---- x pass of plane z0 + k - 2: stage Y buffer (k & 1) -> rows; the stores are
+        // issued by every thread in every step (out of the buffer's range when there is
+        // nothing to store), so each step has the same memory operations ----
+        {
+            const bool live = k >= 2;
+            const int oz = max(z0 + k - 2, 0);
+            const dv2* p1 = reinterpret_cast<const dv2*>(sY + (k & 1) * 2 * ysz + xrd);
+            const dv2* p2 = reinterpret_cast<const dv2*>(sY + (k & 1) * 2 * ysz + ysz + xrd);
             double a[2 * P + 2], b[2 * P + 2];
 #pragma unroll
-            for (int k = 0; k < P + 1; ++k) {
-                const dv2 va = p1[k], vb = p2[k];
-                a[2 * k] = va.x;
-                a[2 * k + 1] = va.y;
-                b[2 * k] = vb.x;
-                b[2 * k + 1] = vb.y;
+            for (int kk = 0; kk < P + 1; ++kk) {
+                const dv2 va = p1[kk], vb = p2[kk];
+                a[2 * kk] = va.x;
+                a[2 * kk + 1] = va.y;
+                b[2 * kk] = vb.x;
+                b[2 * kk + 1] = vb.y;
             }
-            double ms0, lp0, ms1, lp1;
-            const int gx = x0 + 2 * i, gy = y0 + row;
-            if (inner) {
-                ypair<P>(a, b, xim, xid, xim, xid, ms0, lp0, ms1, lp1);
+            double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
+            if (!xv || !live) {
+            } else if (xint) {
+                double xim[W], xid[W];
+                uniform_row<W>(xim, xid, X.M, X.D, opaque(X.ilo <= X.ihi ? X.ilo : 0));
+                xcol<P, kFold>(a, b, 0, xim, xid, o0, o1);
+                xcol<P, kFold>(a, b, 1, xim, xid, o2, o3);
             } else {
                 double m[W], d[W];
-                lds_taps<W>(m, d, tx_ + (2 * i) * 2 * W);
-                pstep<P>(a, b, 0, m, d, ms0, lp0);
-                lds_taps<W>(m, d, tx_ + (2 * i + 1) * 2 * W);
-                pstep<P>(a, b, 1, m, d, ms1, lp1);
+                lds_taps<W>(m, d, tx_ + (2 * xi) * 2 * W);
+                xcol<P, kFold>(a, b, 0, m, d, o0, o1);
+                lds_taps<W>(m, d, tx_ + (2 * xi + 1) * 2 * W);
+                xcol<P, kFold>(a, b, 1, m, d, o2, o3);
             }
-            const size_t idx = ((size_t)oz * Y.R + gy) * X.R + gx;
-            double s0 = 1.0, s1 = 1.0, f0 = 1.0, f1 = 1.0;
+            // uniform scalar loads: a vector load here would be waited for with the
+            // coefficient prefetch issued before it
+            const double sz = ((cdptr)Z.S)[oz], fz = ((cdptr)Z.F)[oz];
+            const size_t pb = live ? (size_t)oz * oplane : 0;
+            const size_t pn = live ? oplane : 0;
+            const auto ro = buf(g.out + pb, pn);
+            double v0, v1;
+            if constexpr (kFold) {
+                v0 = fma(g.beta, o1, o0);
+                v1 = fma(g.beta, o3, o2);
+            } else {
+                const auto rm = buf(g.omass + pb, pn);
+                bstore2<kKeep>(rm, opair, o0, o2);
+                bstore<kKeep>(rm, osing, o0);
+                v0 = fma(g.alpha, o0, g.beta * o1);
+                v1 = fma(g.alpha, o2, g.beta * o3);
+            }
+            // the products in the order of the 2D kernel's epilogue
+            dv2 sxv = {1.0, 1.0}, fxv = {1.0, 1.0};
+            double syz = 1.0;
             if constexpr ((MODE & kScaleSrc) != 0) {
-                const double syz = sfy[row] * sz, fyz = sfy[pl.TY + row] * fz;
-                s0 = sfx[2 * i] * syz;
-                f0 = sfx[pl.TX + 2 * i] * fyz;
-                s1 = sfx[2 * i + 1] * syz;
-                f1 = sfx[pl.TX + 2 * i + 1] * fyz;
+                sxv = *reinterpret_cast<const dv2*>(sfx + 2 * xi);
+                fxv = *reinterpret_cast<const dv2*>(sfx + pl.TX + 2 * xi);
+                syz = sfy[xr] * sz;
+                const double fyz = sfy[pl.TY + xr] * fz;
+                v0 = fma(g.gsep, fxv.x * fyz, v0);
+                v1 = fma(g.gsep, fxv.y * fyz, v1);
             }
-            finish_pair<MODE>(g, idx, ms0, lp0, s0, f0, ms1, lp1, s1, f1, gx + 1 < x1);
-            ii += xdi;
-            irow += xdr;
-            if (ii >= nI) {
-                ii -= nI;
-                ++irow;
+            if constexpr ((MODE & kFarr) != 0) {
+                const auto rf = buf(g.farr + pb, pn);
+                const dv2 fa = bload2(rf, opair);
+                const double fs = bload(rf, osing);
+                v0 = fma(g.garr, xtwo ? fa.x : fs, v0);
+                v1 = fma(g.garr, fa.y, v1);
             }
+            if constexpr ((MODE & kScaleSrc) != 0) {
+                v0 *= sxv.x * syz;
+                v1 *= sxv.y * syz;
+            }
+            bstore2<kKeep>(ro, opair, v0, v1);
+            bstore<kKeep>(ro, osing, v0);
         }
+        __syncthreads();   // LDS stage operations only: stores and prefetches stay in flight
     }
 }
 

@@ -60,6 +60,8 @@ struct iga_ctx {
     hipStream_t cap = nullptr;
     AxisTables t[3] = {};
     std::vector<void*> allocs;
+    std::vector<size_t> alloc_sizes;   // bytes of each entry of allocs
+    size_t own_bytes = 0;              // sum of alloc_sizes: the context's own device memory
     double* unit = nullptr;   // device {1, 0, 0, ...}: tables of an axis beyond dim
     double* ones = nullptr;   // device, all 1: scale / source factors of launches without them
     int* zero = nullptr;      // device {0}
@@ -152,6 +154,8 @@ int dalloc(iga_ctx* c, void** p, size_t bytes)
         return IGA_E_NOMEM;
     }
     c->allocs.push_back(*p);
+    c->alloc_sizes.push_back(bytes);
+    c->own_bytes += bytes;
     return IGA_OK;
 }
 
@@ -163,7 +167,12 @@ int ensure_scratch(iga_ctx* c, double** buf, size_t* cap, size_t n)
     if (capturing(c)) return IGA_E_INVAL;
     if (*buf) {
         auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)*buf);
-        if (it != c->allocs.end()) c->allocs.erase(it);
+        if (it != c->allocs.end()) {
+            const size_t k = (size_t)(it - c->allocs.begin());
+            c->own_bytes -= c->alloc_sizes[k];
+            c->alloc_sizes.erase(c->alloc_sizes.begin() + (std::ptrdiff_t)k);
+            c->allocs.erase(it);
+        }
         IGA_HIP(hipFreeAsync(*buf, c->stream));
         *buf = nullptr;
         *cap = 0;
@@ -257,9 +266,11 @@ void launch_2d(const ApplyArgs& g, hipStream_t s, int order)
 }
 
 // Geometry of a 3D launch: tiles of about 64 output columns; the largest even number of
-// rows whose footprint fits the threads' register rings and whose y and x tasks fit one
-// pass of the workgroup; then the z-chunk depth that fills the chip in the fewest rounds
-// of workgroups (a halo plane costs loads only, counted as a third of a plane).
+// rows whose footprint fits the threads' register rings, whose y and x tasks fit one per
+// thread (with a wave of padding each), and whose LDS stages fit 64 KiB (two workgroups
+// per CU); then the z-chunk depth that fills the chip in the fewest rounds of workgroups
+// (a halo plane costs loads only, counted as a third of a plane; the pipeline's fill and
+// drain as a plane each).
 iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t* lds_bytes)
 {
     using namespace iga;
@@ -270,26 +281,25 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     pl.TX += pl.TX & 1;
     pl.tx = (Rx + pl.TX - 1) / pl.TX;
     pl.LW = pl.TX + 2 * P;
+    pl.LS = pl.LW + (pl.LW & 1);
     const int NT = kMaxNT3;
     const int kNPZ = npz(P);
-    int TY = 2;
-    for (int cand = 2; cand <= 32; cand += 2) {
-        if ((cand + 2 * P) * pl.LW > kNPZ * NT) break;
-        if ((cand / 2) * pl.LW > NT || cand * (pl.TX / 2) > NT) break;
-        if (lds3d_doubles(pl.TX, cand, pl.LW, P) * sizeof(double) > 64 * 1024) break;
-        TY = cand;
-    }
-    if (c->ty3d > 0) TY = c->ty3d;
-    // every footprint point needs a ring slot of some thread; LDS stays within 64 KB
-    while (TY > 2 && ((TY + 2 * P) * pl.LW > kNPZ * NT ||
-                      lds3d_doubles(pl.TX, TY, pl.LW, P) * sizeof(double) > 64 * 1024))
-        TY -= 2;
-    TY = std::min(TY, Ry + (Ry & 1));
+    auto fits = [&](int ty) {
+        return (ty + 2 * P) * pl.LW <= kNPZ * NT && (ty / kRY3) * pl.LW + 63 <= NT &&
+               ty * (pl.TX / 2) + 63 <= NT &&
+               lds3d_doubles(pl.TX, ty, pl.LS, ty + 2 * P, P) * sizeof(double) <= 64 * 1024;
+    };
+    int TY = kRY3;
+    for (int cand = kRY3; cand <= 32; cand += kRY3)
+        if (fits(cand)) TY = cand;
+    if (c->ty3d > 0) TY = std::min(32, (c->ty3d + kRY3 - 1) / kRY3 * kRY3);
+    while (TY > kRY3 && !fits(TY)) TY -= kRY3;
     pl.ty = (Ry + TY - 1) / TY;
     TY = (Ry + pl.ty - 1) / pl.ty;
-    TY += TY & 1;
+    TY = (TY + kRY3 - 1) / kRY3 * kRY3;
     pl.TY = TY;
     pl.ty = (Ry + TY - 1) / TY;
+    pl.LH = TY + 2 * P;
     if (c->tz3d > 0) {
         pl.TZ = std::min(c->tz3d, Rz);
     } else {
@@ -299,7 +309,7 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
         for (int tz = 1; tz <= std::min(Rz, 64); ++tz) {
             const long blocks = (long)pl.tx * pl.ty * ((Rz + tz - 1) / tz);
             const long rounds = (blocks + slots - 1) / slots;
-            const double cost = (double)rounds * (tz + 2.0 * P / 3.0);
+            const double cost = (double)rounds * (tz + 2.0 + 2.0 * P / 3.0);
             if (cost <= best) {
                 best = cost;
                 pl.TZ = tz;
@@ -308,13 +318,8 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     }
     pl.tz = (Rz + pl.TZ - 1) / pl.TZ;
     pl.nblk = pl.tx * pl.ty * pl.tz;
-    // threads: enough for the footprint and the y and x tasks, in whole waves
-    const int need = std::max({((pl.TY + 2 * P) * pl.LW + kNPZ - 1) / kNPZ, (pl.TY / 2) * pl.LW,
-                               pl.TY * (pl.TX / 2)});
-    *nthreads = std::min(NT, std::max(64, (need + 63) / 64 * 64));
-    // every footprint point needs a ring slot
-    while ((size_t)*nthreads * kNPZ < (size_t)(pl.TY + 2 * P) * pl.LW && *nthreads < NT) *nthreads += 64;
-    *lds_bytes = lds3d_doubles(pl.TX, pl.TY, pl.LW, P) * sizeof(double);
+    *nthreads = NT;
+    *lds_bytes = lds3d_doubles(pl.TX, pl.TY, pl.LS, pl.LH, P) * sizeof(double);
     return pl;
 }
 
@@ -598,6 +603,16 @@ struct AxisCache {
 };
 
 AxisCache g_cache[64];
+
+// Device bytes a context holds: the shared axis tables it uses and its own allocations
+// (tables of caller spans, scratch, factors, partition tables).
+size_t ctx_device_bytes(const iga_ctx* c)
+{
+    size_t b = c->own_bytes;
+    for (int a = 0; a < 3; ++a)
+        if (c->shared[a]) b += c->shared[a]->bytes;
+    return b;
+}
 
 // Work buffer of iga_explicit_step_noalloc: a file-scope device array, one copy per device
 // for the life of the process.  Host code uses the address that hipGetSymbolAddress gives
