@@ -382,7 +382,9 @@ int iga_batch_destroy(iga_batch *b);
  * Requests are admitted in submission order while the bytes of the requests in flight
  * (u and both outputs, or u and the step's work buffer) stay within the budget.  An
  * admitted request runs at once on the stream of its mesh's context: contexts are cached
- * (least recently used first out beyond cache_bytes of tables) and bound round-robin to
+ * (least recently used first out while the device memory the cached contexts hold -- their
+ * tables and scratch, such as an explicit step's work buffer -- exceeds cache_bytes; the
+ * most recently used one always stays) and bound round-robin to
  * the server's streams.  2D RHS requests instead join the queue of the persistent batch
  * launch of iga_batch: whenever no launch is running, one launch takes every queued
  * 2D RHS request (continuous batching).  Completion is observed from HIP events; no call
@@ -407,7 +409,8 @@ typedef struct {
 typedef struct iga_server iga_server;
 
 /* nstreams (1..64) streams of default priority; mem_budget_bytes > 0; cache_bytes:
-   limit on the cached contexts' table bytes.  Errors: IGA_E_INVAL, IGA_E_NOMEM. */
+   limit on the device bytes of the cached contexts (tables and scratch).
+   Errors: IGA_E_INVAL, IGA_E_NOMEM. */
 int iga_server_create(int32_t nstreams, size_t mem_budget_bytes, size_t cache_bytes,
                       iga_server **out);
 /* Queues n requests (host array; all or nothing) and admits what fits; tickets (host,
@@ -425,6 +428,9 @@ int iga_server_progress(iga_server *s, uint64_t *done, double *done_time, int32_
    since creation); every output is nullable. */
 int iga_server_stats(const iga_server *s, size_t *used, size_t *peak, int64_t *batch_launches,
                      double *now);
+/* Device bytes held by the cached contexts (tables and scratch, as counted against
+   cache_bytes) and their number; both outputs nullable. */
+int iga_server_cache_stats(const iga_server *s, size_t *cache_bytes, int64_t *contexts);
 /* Waits for the server's streams, then releases its contexts, streams and events. */
 int iga_server_destroy(iga_server *s);
 

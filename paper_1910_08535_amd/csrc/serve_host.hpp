@@ -24,6 +24,7 @@ struct iga_server {
         iga_ctx* c;
         int stream;
         std::list<std::array<int64_t, 5>>::iterator lru;
+        size_t bytes;   // device bytes of the context counted in cache_bytes
     };
     struct KeyHash {
         size_t operator()(const std::array<int64_t, 5>& k) const
@@ -93,6 +94,21 @@ int server_event(iga_server* s, hipEvent_t* ev)
     return IGA_OK;
 }
 
+// Evicts least recently used contexts while the cached contexts' device bytes (tables,
+// scratch such as the explicit step's work buffer) exceed the limit; frees are ordered
+// after each context's work.  The most recently used context always stays.
+void server_evict(iga_server* s)
+{
+    while (s->cache_bytes > s->cache_limit && s->lru.size() > 1) {
+        const auto old = s->lru.front();
+        auto oi = s->cache.find(old);
+        s->cache_bytes -= oi->second.bytes;
+        iga_destroy(oi->second.c);
+        s->cache.erase(oi);
+        s->lru.pop_front();
+    }
+}
+
 int server_ctx(iga_server* s, const iga_request& r, iga_server::Ctx** out)
 {
     const std::array<int64_t, 5> key = {r.dim, r.p, r.ne[0], r.dim > 1 ? r.ne[1] : 1,
@@ -120,17 +136,9 @@ int server_ctx(iga_server* s, const iga_request& r, iga_server::Ctx** out)
     IGA_TRY(iga_create(&d, s->streams[k], &c));
     s->lru.push_back(key);
     auto& e = s->cache[key];
-    e = {c, k, std::prev(s->lru.end())};
-    s->cache_bytes += c->table_bytes;
-    // evict least recently used contexts (their frees are ordered after their work)
-    while (s->cache_bytes > s->cache_limit && s->lru.size() > 1) {
-        const auto old = s->lru.front();
-        auto oi = s->cache.find(old);
-        s->cache_bytes -= oi->second.c->table_bytes;
-        iga_destroy(oi->second.c);
-        s->cache.erase(oi);
-        s->lru.pop_front();
-    }
+    e = {c, k, std::prev(s->lru.end()), ctx_device_bytes(c)};
+    s->cache_bytes += e.bytes;
+    server_evict(s);
     *out = &s->cache.find(key)->second;
     return IGA_OK;
 }
@@ -156,6 +164,11 @@ int server_launch(iga_server* s, iga_server::Item& it)
     IGA_TRY(server_event(s, &it.ev));
     IGA_HIP(hipEventRecord(it.ev, s->streams[e->stream]));
     s->inflight[e->stream].push_back(it);
+    // the call may have grown the context's scratch (the step's work buffer)
+    const size_t now = ctx_device_bytes(e->c);
+    s->cache_bytes += now - e->bytes;
+    e->bytes = now;
+    server_evict(s);
     return IGA_OK;
 }
 
@@ -319,6 +332,14 @@ int iga_server_stats(const iga_server* s, size_t* used, size_t* peak, int64_t* b
     if (peak) *peak = s->peak;
     if (batch_launches) *batch_launches = s->launches;
     if (now) *now = server_time(s);
+    return IGA_OK;
+}
+
+int iga_server_cache_stats(const iga_server* s, size_t* cache_bytes, int64_t* contexts)
+{
+    if (!s) return IGA_E_INVAL;
+    if (cache_bytes) *cache_bytes = s->cache_bytes;
+    if (contexts) *contexts = (int64_t)s->cache.size();
     return IGA_OK;
 }
 

@@ -102,6 +102,7 @@ _SIGS = {
                             C.POINTER(C.c_int32)],
     "iga_server_stats": [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                          C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+    "iga_server_cache_stats": [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)],
     "iga_server_destroy": [C.c_void_p],
 }
 
@@ -517,6 +518,12 @@ class NativeServer:
         _check(lib().iga_server_stats(self.h, C.byref(used), C.byref(peak), C.byref(launches),
                                       C.byref(now)), "iga_server_stats")
         return used.value, peak.value, launches.value, now.value
+
+    def cache_stats(self):
+        """(device bytes of the cached contexts, their number)."""
+        b, n = C.c_size_t(), C.c_int64()
+        _check(lib().iga_server_cache_stats(self.h, C.byref(b), C.byref(n)), "iga_server_cache_stats")
+        return b.value, n.value
 
     def close(self) -> None:
         if getattr(self, "h", None):

@@ -113,3 +113,41 @@ def test_server_rejects_bad_requests(mods):
             break
     assert done.tolist() == t.tolist() and s.stats()[0] == 0
     s.close()
+
+
+def test_cache_counts_step_scratch(mods):
+    """Explicit-step requests leave their work buffer with the cached context: the cache
+    counts it, so many distinct step shapes under a small cache limit keep the cached
+    device memory bounded (the least recently used contexts are evicted)."""
+    import torch
+    iga, serve = mods
+    limit = 8 << 20
+    count = 40
+    s = iga.NativeServer(nstreams=2, budget_bytes=1 << 30, cache_bytes=limit)
+    bufs = []
+    largest = 0
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for k in range(count):
+        ne = (76 + k, 77, 78 + (k % 3))   # distinct shapes, about 4 MB of coefficients each
+        u = torch.zeros(tuple(n + 2 for n in reversed(ne)), dtype=torch.float64, device="cuda")
+        rec = np.zeros(1, dtype=s.dtype)
+        rec["kind"], rec["dim"], rec["p"], rec["nsteps"] = iga.REQ_STEP, 3, 2, 2
+        rec["ne"][0] = list(ne)
+        rec["dt"], rec["sin_amp"], rec["u"] = 1e-6, 1.0, u.data_ptr()
+        s.submit(rec)
+        bufs.append(u)
+        largest = max(largest, 2 * u.numel() * 8)
+        cached, n = s.cache_stats()
+        # the work buffer of each context is counted; at most the limit plus the newest
+        assert cached <= limit + largest, (k, cached)
+    while s.stats()[0] > 0:
+        s.progress()
+    cached, n = s.cache_stats()
+    assert cached <= limit + largest and 1 <= n <= 4, (cached, n)
+    torch.cuda.synchronize()
+    # device memory held beyond the request buffers stays near the cache limit (the
+    # stream-ordered pool keeps freed memory for reuse): far below one work buffer per shape
+    held = free0 - torch.cuda.mem_get_info()[0] - sum(b.numel() * 8 for b in bufs)
+    assert held < count * largest // 4, (held, largest)
+    s.close()
