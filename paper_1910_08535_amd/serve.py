@@ -149,11 +149,9 @@ class Server:
             out = torch.empty((2,) + shape, dtype=torch.float64, device="cuda")
         return (u, out[0], out[1])
 
-    def submit(self, reqs: List[Request], arrivals: List[float]) -> None:
-        """Hands a group of arrived requests to the library (arrival times in the
-        library's clock)."""
-        if not reqs:
-            return
+    def prepare(self, reqs: List[Request]):
+        """The library's request records of `reqs` and their bookkeeping, built before any
+        timing (the client's side of a submission: device buffers and descriptors)."""
         recs = np.zeros(len(reqs), dtype=self.native.dtype)
         records = []
         fresh = False
@@ -171,16 +169,29 @@ class Server:
             else:
                 h = min(1.0 / n for n in req.ne)
                 r["nsteps"], r["dt"], r["sin_amp"] = req.nsteps, h * h / 64.0, 1.0
-            rec = Record(req=req, t_arrive=arrivals[k], tensors=tens)
+            rec = Record(req=req, tensors=tens)
             rec.gauss_points, rec.hbm_bytes = request_work(req)
             records.append(rec)
         if fresh:   # coefficients drawn or outputs allocated on torch's stream just now
             self.torch.cuda.current_stream().synchronize()
+        return recs, records
+
+    def submit(self, reqs: List[Request], arrivals: List[float]) -> None:
+        """Hands a group of arrived requests to the library (arrival times in the
+        library's clock)."""
+        if not reqs:
+            return
+        recs, records = self.prepare(reqs)
+        for rec, t in zip(records, arrivals):
+            rec.t_arrive = t
+        self._submit(recs, records)
+
+    def _submit(self, recs, records) -> None:
         tickets = self.native.submit(recs)
         for t, rec in zip(tickets.tolist(), records):
             self.live[t] = rec
 
-    def _progress(self) -> None:
+    def _progress(self) -> int:
         tickets, times, states, launches = self.native.progress()
         for t, tm, st, ln in zip(tickets.tolist(), times.tolist(), states.tolist(), launches.tolist()):
             rec = self.live.pop(t)
@@ -191,22 +202,31 @@ class Server:
             if not self.keep:
                 rec.tensors = ()
             self.done.append(rec)
+        return len(tickets)
 
     # ---- the loop --------------------------------------------------------------------
     def run(self, requests: List[Request], time_scale: float = 1.0) -> Dict[str, float]:
-        """Serve `requests` (sorted by arrival; arrivals replayed in wall-clock time scaled
-        by time_scale, every request at once for 0) until all are done; returns latency
-        and throughput figures."""
-        pending = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
-        total = len(requests) + len(self.done)
+        """Serve `requests` (arrivals replayed in wall-clock time scaled by time_scale,
+        every request at once for 0) until all are done; returns latency and throughput
+        figures.  The request records are prepared before the clock starts; in the loop a
+        group of arrived requests is one library call."""
+        order = sorted(requests, key=lambda r: r.t_arrive)
+        recs, records = self.prepare(order)
+        arrive = [r.t_arrive * time_scale for r in order]
+        total = len(order) + len(self.done)
         start = self.native.stats()[3]
+        for rec, a in zip(records, arrive):
+            rec.t_arrive = start + a
+        nxt = 0
         t0 = time.perf_counter()
         while len(self.done) < total:
             now = time.perf_counter() - t0
-            group = []
-            while pending and pending[0].t_arrive * time_scale <= now:
-                group.append(pending.popleft())
-            self.submit(group, [start + r.t_arrive * time_scale for r in group])
+            end = nxt
+            while end < len(order) and arrive[end] <= now:
+                end += 1
+            if end > nxt:
+                self._submit(recs[nxt:end], records[nxt:end])
+                nxt = end
             self._progress()
         wall = time.perf_counter() - t0
         return self.summary(wall)
