@@ -163,7 +163,7 @@ int batch_fill(iga_batch* b, size_t n, int* total)
 // The job list of a launch to the device (the graph reads it from there).
 int batch_upload(iga_batch* b, size_t n, int total)
 {
-    b->ctl_host->counter = 0;
+    std::memset(b->ctl_host, 0, sizeof(iga::BatchCtl));
     b->ctl_host->njobs = (int)n;
     b->ctl_host->total = total;
     IGA_HIP(hipMemcpyAsync(b->jobs_dev, b->jobs_host, n * sizeof(iga::BatchJobDev),
