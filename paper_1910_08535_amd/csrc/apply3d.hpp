@@ -184,8 +184,10 @@ __device__ __forceinline__ void xcol(const double (&a)[2 * P + 2], const double 
     }
 }
 
+// Tile L (x fastest, then y, then z-chunk) of the plan, by a workgroup of kMaxNT3 threads
+// with the plan's LDS bytes of dynamic shared memory.
 template <int P, int MODE>
-__global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D pl)
+__device__ __forceinline__ void apply3d_tile(const ApplyArgs& g, const Plan3D& pl, int L)
 {
     constexpr int W = 2 * P + 1;
     constexpr int kNPZ = npz(P);
@@ -193,7 +195,6 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
     extern __shared__ __attribute__((aligned(16))) double lds3[];
     const AxisOp &X = g.ax[0], &Y = g.ax[1], &Z = g.ax[2];
     const int tid = (int)threadIdx.x;
-    const int L = xcd_logical_block((int)blockIdx.x, pl.nblk);
     const int bx = L % pl.tx, by = (L / pl.tx) % pl.ty, bz = L / (pl.tx * pl.ty);
     const int x0 = bx * pl.TX, y0 = by * pl.TY, z0 = bz * pl.TZ;
     const int x1 = min(x0 + pl.TX, X.R), y1 = min(y0 + pl.TY, Y.R), z1 = min(z0 + pl.TZ, Z.R);
@@ -492,6 +493,12 @@ __global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D
         }
         __syncthreads();   // LDS stage operations only: stores and prefetches stay in flight
     }
+}
+
+template <int P, int MODE>
+__global__ __launch_bounds__(kMaxNT3, 4) void apply3d_kernel(ApplyArgs g, Plan3D pl)
+{
+    apply3d_tile<P, MODE>(g, pl, xcd_logical_block((int)blockIdx.x, pl.nblk));
 }
 
 }  // namespace iga

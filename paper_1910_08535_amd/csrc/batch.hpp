@@ -24,7 +24,8 @@ struct BatchJobDev {
     int vec;       // rows of even length: 128-bit row accesses
     int tx, ty;    // strips and row chunks of the job
     int chunk0;    // first chunk number of the job in this launch
-    int pad;
+    int step;      // a lumped explicit step (scaled rows and source into out) instead of
+                   // the mass and Laplacian rows (kernels instantiated with STEPS only)
 };
 
 constexpr int kXcds = 8;   // XCDs of the chip; workgroup b runs on XCD b mod 8
@@ -42,7 +43,7 @@ __global__ void batch_reset_kernel(BatchCtl* ctl)
     if (blockIdx.x == 0 && threadIdx.x < kXcds) ctl->counter[threadIdx.x][0] = 0u;
 }
 
-template <int TY>
+template <int TY, bool STEPS>
 __global__ __launch_bounds__(64) void batch2d_kernel(BatchCtl* ctl, const BatchJobDev* __restrict__ jobs)
 {
     constexpr int LDS = Chunk2D<3, TY>::LDS > Chunk2D<2, TY>::LDS ? Chunk2D<3, TY>::LDS
@@ -74,7 +75,20 @@ __global__ __launch_bounds__(64) void batch2d_kernel(BatchCtl* ctl, const BatchJ
             const BatchJobDev J = jobs[lo];
             const int local = (int)c - J.chunk0;
             const int bx = local % J.tx, by = local / J.tx;
-            if (J.p == 2) {
+            if (STEPS && J.step) {
+                constexpr int M = kOut | kScaleSrc;
+                if (J.p == 2) {
+                    if (J.vec)
+                        apply2d_chunk<2, TY, M, true>(J.g, bx, by, lds);
+                    else
+                        apply2d_chunk<2, TY, M, false>(J.g, bx, by, lds);
+                } else {
+                    if (J.vec)
+                        apply2d_chunk<3, TY, M, true>(J.g, bx, by, lds);
+                    else
+                        apply2d_chunk<3, TY, M, false>(J.g, bx, by, lds);
+                }
+            } else if (J.p == 2) {
                 if (J.vec)
                     apply2d_chunk<2, TY, kOut | kMass, true>(J.g, bx, by, lds);
                 else

@@ -80,7 +80,7 @@ int batch_grid()
         int dev = 0, ncu = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, iga::batch2d_kernel<TY>, 64, 0) !=
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, iga::batch2d_kernel<TY, false>, 64, 0) !=
                 hipSuccess) {
             (void)hipGetLastError();
             ncu = 256;
@@ -95,7 +95,7 @@ template <int TY>
 void batch_enqueue(iga_batch* b, hipStream_t s)
 {
     hipLaunchKernelGGL(iga::batch_reset_kernel, dim3(1), dim3(64), 0, s, b->ctl_dev);
-    hipLaunchKernelGGL(iga::batch2d_kernel<TY>, dim3(batch_grid<TY>()), dim3(64), 0, s, b->ctl_dev,
+    hipLaunchKernelGGL((iga::batch2d_kernel<TY, false>), dim3(batch_grid<TY>()), dim3(64), 0, s, b->ctl_dev,
                        (const iga::BatchJobDev*)b->jobs_dev);
 }
 

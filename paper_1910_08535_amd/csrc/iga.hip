@@ -271,12 +271,13 @@ void launch_2d(const ApplyArgs& g, hipStream_t s, int order)
 // per CU); then the z-chunk depth that fills the chip in the fewest rounds of workgroups
 // (a halo plane costs loads only, counted as a third of a plane; the pipeline's fill and
 // drain as a plane each).
-iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t* lds_bytes)
+// tx3d, ty3d, tz3d: the context's tile settings (0 = automatic).
+iga::Plan3D plan_3d_rows(int P, int Rx, int Ry, int Rz, int tx3d, int ty3d, int tz3d, int* nthreads,
+                         size_t* lds_bytes)
 {
     using namespace iga;
-    const int P = c->p, Rx = g.ax[0].R, Ry = g.ax[1].R, Rz = g.ax[2].R;
     Plan3D pl;
-    pl.tx = c->tx3d > 0 ? (Rx + c->tx3d - 1) / c->tx3d : std::max(1, (Rx + 32) / 66);
+    pl.tx = tx3d > 0 ? (Rx + tx3d - 1) / tx3d : std::max(1, (Rx + 32) / 66);
     pl.TX = (Rx + pl.tx - 1) / pl.tx;
     pl.TX += pl.TX & 1;
     pl.tx = (Rx + pl.TX - 1) / pl.TX;
@@ -292,7 +293,7 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     int TY = kRY3;
     for (int cand = kRY3; cand <= 32; cand += kRY3)
         if (fits(cand)) TY = cand;
-    if (c->ty3d > 0) TY = std::min(32, (c->ty3d + kRY3 - 1) / kRY3 * kRY3);
+    if (ty3d > 0) TY = std::min(32, (ty3d + kRY3 - 1) / kRY3 * kRY3);
     while (TY > kRY3 && !fits(TY)) TY -= kRY3;
     pl.ty = (Ry + TY - 1) / TY;
     TY = (Ry + pl.ty - 1) / pl.ty;
@@ -300,8 +301,8 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     pl.TY = TY;
     pl.ty = (Ry + TY - 1) / TY;
     pl.LH = TY + 2 * P;
-    if (c->tz3d > 0) {
-        pl.TZ = std::min(c->tz3d, Rz);
+    if (tz3d > 0) {
+        pl.TZ = std::min(tz3d, Rz);
     } else {
         const int slots = 2 * 256;
         double best = 1e300;
@@ -321,6 +322,11 @@ iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t*
     *nthreads = NT;
     *lds_bytes = lds3d_doubles(pl.TX, pl.TY, pl.LS, pl.LH, P) * sizeof(double);
     return pl;
+}
+
+iga::Plan3D plan_3d(const iga_ctx* c, const ApplyArgs& g, int* nthreads, size_t* lds_bytes)
+{
+    return plan_3d_rows(c->p, g.ax[0].R, g.ax[1].R, g.ax[2].R, c->tx3d, c->ty3d, c->tz3d, nthreads, lds_bytes);
 }
 
 template <int P, int MODE>
@@ -600,6 +606,9 @@ struct AxisCache {
     size_t nones = 0;
     // this device's copy of `scratch` (below): the address of the symbol on the device
     double* scratch = nullptr;
+    // element-unit PG rows per (p, nq), built once per device and kept: the table and the
+    // event of its build (dropped once the build is known to be complete)
+    std::map<std::pair<int, int>, std::pair<double*, hipEvent_t>> gen;
 };
 
 AxisCache g_cache[64];
@@ -672,6 +681,49 @@ int shared_consts(iga_ctx* c, size_t n)
         g->scratch = (double*)sp;
     }
     c->scratch = g->scratch;
+    return IGA_OK;
+}
+
+// The element-unit PG rows of (p, nq) for work on stream s: built on s at the first use on
+// the device; later users on other streams wait for the build while it may still run.
+int pg_generic(hipStream_t s, int p, int nq, const double** out)
+{
+    AxisCache* g = device_cache();
+    if (!g) return IGA_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g->mu);
+    auto it = g->gen.find({p, nq});
+    if (it != g->gen.end()) {
+        auto& e = it->second;
+        if (e.second) {
+            const hipError_t q = hipEventQuery(e.second);
+            if (q == hipSuccess) {
+                (void)hipEventDestroy(e.second);
+                e.second = nullptr;
+            } else if (q == hipErrorNotReady) {
+                IGA_HIP(hipStreamWaitEvent(s, e.second, 0));
+            } else {
+                return IGA_E_DEVICE;
+            }
+        }
+        *out = e.first;
+        return IGA_OK;
+    }
+    void* mem = nullptr;
+    if (hipMalloc(&mem, iga::pg_generic_doubles(p, nq) * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return IGA_E_NOMEM;
+    }
+    hipEvent_t ev = nullptr;
+    hipLaunchKernelGGL(iga::pg_generic_kernel, dim3(1), dim3(256), 0, s, (double*)mem, p, nq);
+    if (hipGetLastError() != hipSuccess || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(mem);
+        if (ev) (void)hipEventDestroy(ev);
+        return IGA_E_DEVICE;
+    }
+    g->gen[{p, nq}] = {(double*)mem, ev};
+    *out = (const double*)mem;
     return IGA_OK;
 }
 
@@ -1340,13 +1392,16 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
         for (int a = 0; a < c->dim && rc == IGA_OK; ++a) {
             bool built = false;
             rc = axis_acquire(c, a, desc, &c->shared[a], &built);
+            if (rc == IGA_OK && built) {
+                fresh[a] = c->shared[a];
+                // PG rows scaled from the element-unit rows where those hold
+                if (desc->spans == IGA_SPANS_SUPPORT && desc->ne[a] >= iga::pg_generic_min_ne(c->p))
+                    rc = pg_generic(c->stream, c->p, desc->nq[a], &fresh[a]->t.pgen);
+            }
             if (rc == IGA_OK) {
                 c->t[a] = c->shared[a]->t;
                 c->table_bytes += c->shared[a]->bytes;
-                if (built) {
-                    fresh[a] = c->shared[a];
-                    set.t[nbuild++] = c->t[a];
-                }
+                if (built) set.t[nbuild++] = c->t[a];
             }
         }
     } else if (rc == IGA_OK) {

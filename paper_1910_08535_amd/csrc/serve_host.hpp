@@ -1,12 +1,16 @@
 // serve_host.hpp -- host side of the serving API (included by iga.hip, same unit).
 //
-// A request loop inside the library: requests are admitted in submission order while
-// the device bytes of the requests in flight stay within the budget.  Each admitted
-// request runs at once on the stream of its mesh's context (contexts are cached, least
-// recently used first out beyond a byte limit, and bound round-robin to a pool of
-// streams); 2D RHS requests instead join the queue of a persistent batch launch, and one
-// launch takes every queued 2D RHS request whenever no launch is running (continuous
-// batching).  Completion is observed from HIP events, never waited for.
+// A request loop inside the library.  Requests are admitted in submission order while the
+// device bytes of the requests in flight stay within the budget.  A request that the
+// batched iterations take (serve_batch.hpp: every axis of at least 3p+1 elements) becomes
+// a job; any other runs at once on the stream of its mesh's context (contexts cached,
+// least recently used first out beyond a byte limit, bound round-robin to a pool of
+// streams).  While fewer than two iterations are in flight and some job has work left,
+// the loop enqueues the next iteration on a stream of its own: the descriptors of the
+// iteration (one host-to-device copy), the set-up of the jobs admitted since the last
+// one, then one launch per kind of job (1D, 2D, 3D per degree and output mode) over all
+// jobs.  A right-hand-side job runs in one iteration, a step job in one per step.
+// Completion is observed from HIP events, never waited for.
 #pragma once
 
 #include <array>
@@ -14,6 +18,9 @@
 #include <deque>
 #include <list>
 #include <unordered_map>
+
+#include "batch.hpp"
+#include "serve_batch.hpp"
 
 struct iga_server {
     std::vector<hipStream_t> streams;
@@ -36,7 +43,7 @@ struct iga_server {
     };
     std::unordered_map<std::array<int64_t, 5>, Ctx, KeyHash> cache;
     std::list<std::array<int64_t, 5>> lru;   // front = least recently used
-    // requests
+    // requests run on contexts
     struct Item {
         uint64_t ticket;
         iga_request r;
@@ -45,12 +52,45 @@ struct iga_server {
     };
     std::deque<Item> waiting;
     std::vector<std::deque<Item>> inflight;   // per stream, in launch order
-    iga_batch* batch = nullptr;
-    hipStream_t batch_stream = nullptr;
-    hipEvent_t batch_ev = nullptr;
-    std::vector<Item> batch_queued, batch_running;
-    int64_t launches = 0;
-    std::vector<hipEvent_t> events;   // free events
+    std::vector<hipEvent_t> events;           // free events
+    // batched jobs
+    struct Job {
+        uint64_t ticket;
+        iga_request r;
+        size_t bytes;          // counted against the budget
+        int R[3];              // rows (= coefficients) per axis
+        int left;              // iterations still to enqueue (RHS 1, STEP nsteps)
+        int k;                 // steps enqueued
+        bool setup;            // tables still to expand
+        double* tab;           // tables: per axis M | D [| S | F] (2D, 3D), F (1D step)
+        double* work;          // step: work buffer
+        int block;             // the memory block holding tab and work
+        iga::Plan3D pl;        // 3D tiles
+        size_t lds3;           // their LDS bytes
+    };
+    std::list<Job> jobs;       // admitted and unfinished, in admission order
+    std::vector<std::list<Job>::iterator> fresh;   // admitted since the last iteration
+    int64_t pending = 0;       // jobs with iterations still to enqueue
+    struct Block {
+        void* mem;
+        int refs;
+    };
+    std::unordered_map<int, Block> blocks;
+    int next_block = 0;
+    struct Slot {
+        hipEvent_t ev = nullptr;
+        bool busy = false;
+        int64_t iter = -1;
+        std::vector<std::list<Job>::iterator> finishing;
+        char* host = nullptr;   // pinned staging of the iteration's descriptors
+        char* dev = nullptr;    // their device copy
+        size_t cap = 0;
+    };
+    Slot slot[2];
+    hipStream_t bstream = nullptr;
+    const double* gen[iga::kMaxP + 1] = {};   // element-unit PG rows of (p, p+1)
+    int grid2d = 0;                           // workgroups of the persistent 2D launch
+    int64_t launches = 0;                     // iterations enqueued
     struct Done {
         uint64_t ticket;
         double t;
@@ -71,11 +111,56 @@ size_t request_points(const iga_request& r)
     return n;
 }
 
+// The batched iterations take a request whose mesh passes the checks of iga_create and
+// whose every axis has at least 3p+1 elements (where the element-unit rows hold).
+bool batchable(const iga_request& r)
+{
+    iga_mesh_desc d;
+    std::memset(&d, 0, sizeof(d));
+    d.dim = r.dim;
+    d.p = r.p;
+    for (int a = 0; a < 3; ++a) {
+        d.ne[a] = a < r.dim ? r.ne[a] : 1;
+        d.lo[a] = 0.0;
+        d.hi[a] = 1.0;
+        d.nq[a] = r.p + 1;
+    }
+    d.spans = IGA_SPANS_SUPPORT;
+    if (validate_desc(&d) != IGA_OK) return false;
+    for (int a = 0; a < r.dim; ++a)
+        if (r.ne[a] < iga::pg_generic_min_ne(r.p)) return false;
+    return true;
+}
+
+// Doubles of a batched job's own tables: M | D per axis, and the step's S | F (2D, 3D);
+// the step's source rows F when it has a source (1D).
+size_t job_table_doubles(const iga_request& r)
+{
+    const bool step = r.kind == IGA_REQ_STEP;
+    if (r.dim == 1) return step && r.sin_amp != 0.0 ? (size_t)(r.ne[0] + r.p) : 0;
+    const int W = 2 * r.p + 1;
+    size_t n = 0;
+    for (int a = 0; a < r.dim; ++a) n += (size_t)(r.ne[a] + r.p) * (2 * W + (step ? 2 : 0));
+    return n;
+}
+
 // resident bytes of a request in flight: coefficients and outputs, or coefficients and
-// the step's work buffer
+// the step's work buffer; a batched job's tables on top
 size_t request_bytes(const iga_request& r)
 {
-    return (r.kind == IGA_REQ_RHS ? 3 : 2) * request_points(r) * sizeof(double);
+    size_t b = (r.kind == IGA_REQ_RHS ? 3 : 2) * request_points(r) * sizeof(double);
+    if (batchable(r)) b += job_table_doubles(r) * sizeof(double);
+    return b;
+}
+
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device bytes of a job's region: its tables, then the step's work buffer.
+size_t job_region(const iga_server::Job& j)
+{
+    size_t b = up256(job_table_doubles(j.r) * sizeof(double));
+    if (j.r.kind == IGA_REQ_STEP) b += up256(request_points(j.r) * sizeof(double));
+    return b;
 }
 
 double server_time(const iga_server* s)
@@ -172,9 +257,317 @@ int server_launch(iga_server* s, iga_server::Item& it)
     return IGA_OK;
 }
 
+// ---- batched iterations -------------------------------------------------------------
+
+void server_release_block(iga_server* s, int b)
+{
+    if (b < 0) return;
+    auto it = s->blocks.find(b);
+    if (it == s->blocks.end() || --it->second.refs > 0) return;
+    // ordered after every kernel enqueued so far; the last users are complete
+    (void)hipFreeAsync(it->second.mem, s->bstream);
+    s->blocks.erase(it);
+}
+
+void server_finish_job(iga_server* s, std::list<iga_server::Job>::iterator j, int32_t state, int64_t launch)
+{
+    s->used -= j->bytes;
+    if (j->left > 0) --s->pending;
+    server_release_block(s, j->block);
+    s->done.push_back({j->ticket, server_time(s), state, launch});
+    s->jobs.erase(j);
+}
+
+// The descriptor arrays of one iteration, laid out in one buffer (256-byte aligned arrays).
+struct IterLayout {
+    size_t ctl, eu, eb, j1, b1, j2, j3[4], b3[4], total;
+};
+
+template <typename T>
+void put(char* base, size_t off, const std::vector<T>& v)
+{
+    if (!v.empty()) std::memcpy(base + off, v.data(), v.size() * sizeof(T));
+}
+
+// The axis descriptor of axis a of a batched 2D/3D job (tables in tab at *off).
+AxisOp job_axis(const iga_server::Job& j, int a, size_t* off)
+{
+    AxisOp o;
+    std::memset(&o, 0, sizeof(o));
+    const int W = 2 * j.r.p + 1, R = j.R[a];
+    const bool step = j.r.kind == IGA_REQ_STEP;
+    o.M = j.tab + *off;
+    o.D = o.M + (size_t)R * W;
+    // the right-hand side reads no scale or source rows: any table of R rows will do
+    o.S = step ? o.D + (size_t)R * W : o.M;
+    o.F = step ? o.S + R : o.M;
+    o.R = o.N = R;
+    o.ilo = 2 * j.r.p;
+    o.ihi = (int)j.r.ne[a] - 1 - j.r.p;
+    *off += (size_t)R * (2 * W + (step ? 2 : 0));
+    return o;
+}
+
+// Enqueues the next iteration if a slot is free and some job has work left: set-up of the
+// jobs admitted since the last iteration, then every job's next kernel.
+int server_iterate(iga_server* s)
+{
+    using namespace iga;
+    if (s->pending == 0) return IGA_OK;
+    iga_server::Slot* sl = nullptr;
+    for (auto& x : s->slot)
+        if (!x.busy) {
+            sl = &x;
+            break;
+        }
+    if (!sl) return IGA_OK;
+    // memory of the newly admitted jobs: one block
+    size_t total = 0;
+    int holders = 0;
+    for (auto it : s->fresh) {
+        const size_t b = job_region(*it);
+        total += b;
+        holders += b > 0;
+    }
+    char* base = nullptr;
+    int blk = -1;
+    if (total > 0) {
+        void* mem = nullptr;
+        if (hipMallocAsync(&mem, total, s->bstream) != hipSuccess) {
+            (void)hipGetLastError();
+            for (auto it : s->fresh) server_finish_job(s, it, IGA_JOB_FAILED, -1);
+            s->fresh.clear();
+            return IGA_OK;
+        }
+        blk = s->next_block++;
+        s->blocks[blk] = {mem, holders};
+        base = (char*)mem;
+    }
+    std::vector<ExpandUnit> eu;
+    std::vector<int> eb;
+    int nbe = 0;
+    size_t off = 0;
+    for (auto it : s->fresh) {
+        iga_server::Job& j = *it;
+        const iga_request& r = j.r;
+        const size_t b = job_region(j);
+        if (b > 0) {
+            j.tab = (double*)(base + off);
+            j.work = r.kind == IGA_REQ_STEP ? (double*)(base + off + up256(job_table_doubles(r) * sizeof(double)))
+                                            : nullptr;
+            j.block = blk;
+            off += b;
+        }
+        if (!s->gen[r.p]) IGA_TRY(pg_generic(s->bstream, r.p, r.p + 1, &s->gen[r.p]));
+        const bool step = r.kind == IGA_REQ_STEP;
+        size_t toff = 0;
+        for (int a = 0; a < r.dim; ++a) {
+            if (r.dim == 1 && !(step && r.sin_amp != 0.0)) break;
+            ExpandUnit u;
+            std::memset(&u, 0, sizeof(u));
+            u.gen = s->gen[r.p];
+            const int W = 2 * r.p + 1, R = j.R[a];
+            if (r.dim == 1) {
+                u.F = j.tab;
+            } else {
+                u.M = j.tab + toff;
+                u.D = u.M + (size_t)R * W;
+                if (step) {
+                    u.S = u.D + (size_t)R * W;
+                    u.F = u.S + R;
+                    u.ones = r.sin_amp == 0.0;
+                }
+                toff += (size_t)R * (2 * W + (step ? 2 : 0));
+            }
+            u.lo = 0.0;
+            u.hi = 1.0;
+            u.p = r.p;
+            u.nq = r.p + 1;
+            u.ne = (int)r.ne[a];
+            u.R = R;
+            eu.push_back(u);
+            eb.push_back(nbe);
+            nbe += (R + kServeBlock - 1) / kServeBlock;
+        }
+        if (step && (r.nsteps & 1)) {   // odd: the steps start from a copy, the last lands in u
+            ExpandUnit u;
+            std::memset(&u, 0, sizeof(u));
+            u.src = r.u;
+            u.dst = j.work;
+            u.n = (long long)request_points(r);
+            eu.push_back(u);
+            eb.push_back(nbe);
+            nbe += (int)((u.n + kServeBlock - 1) / kServeBlock);
+        }
+        j.setup = false;
+    }
+    s->fresh.clear();
+    // every job's next kernel
+    constexpr int kTY = 16;
+    std::vector<Job1D> j1;
+    std::vector<int> b1;
+    int nb1 = 0;
+    std::vector<BatchJobDev> j2;
+    int chunks = 0;
+    std::vector<Job3D> j3[4];
+    std::vector<int> b3[4];
+    int nb3[4] = {0, 0, 0, 0};
+    size_t lds3[4] = {0, 0, 0, 0};
+    for (auto it = s->jobs.begin(); it != s->jobs.end(); ++it) {
+        iga_server::Job& j = *it;
+        if (j.left == 0) continue;
+        const iga_request& r = j.r;
+        const bool step = r.kind == IGA_REQ_STEP;
+        const double *src = r.u;
+        double* dst = r.lap_out;
+        if (step) {
+            double* first = (r.nsteps & 1) ? j.work : r.u;
+            double* second = first == r.u ? j.work : r.u;
+            src = (j.k & 1) ? second : first;
+            dst = (j.k & 1) ? first : second;
+        }
+        if (r.dim == 1) {
+            Job1D d;
+            std::memset(&d, 0, sizeof(d));
+            d.gen = s->gen[r.p];
+            d.u = src;
+            d.out = dst;
+            d.omass = step ? nullptr : r.mass_out;
+            d.F = step && r.sin_amp != 0.0 ? j.tab : nullptr;
+            d.lo = 0.0;
+            d.hi = 1.0;
+            d.alpha = step ? 1.0 : 0.0;
+            d.beta = step ? r.dt : 1.0;
+            d.gsep = step ? r.dt * r.sin_amp : 0.0;
+            d.p = r.p;
+            d.ne = (int)r.ne[0];
+            d.step = step;
+            j1.push_back(d);
+            b1.push_back(nb1);
+            nb1 += (j.R[0] + kServeBlock - 1) / kServeBlock;
+        } else {
+            ApplyArgs g;
+            std::memset(&g, 0, sizeof(g));
+            size_t toff = 0;
+            for (int a = 0; a < r.dim; ++a) g.ax[a] = job_axis(j, a, &toff);
+            g.u = src;
+            g.out = dst;
+            g.omass = step ? nullptr : r.mass_out;
+            g.alpha = step ? 1.0 : 0.0;
+            g.beta = step ? r.dt : 1.0;
+            g.gsep = step ? r.dt * r.sin_amp : 0.0;
+            g.garr = step ? r.dt : 0.0;
+            if (r.dim == 2) {
+                BatchJobDev d;
+                std::memset(&d, 0, sizeof(d));
+                d.g = g;
+                d.p = r.p;
+                d.vec = (g.ax[0].N % 2 == 0 && g.ax[0].R % 2 == 0) ? 1 : 0;
+                d.tx = (g.ax[0].R + 127) / 128;
+                d.ty = (g.ax[1].R + kTY - 1) / kTY;
+                d.chunk0 = chunks;
+                d.step = step;
+                chunks += d.tx * d.ty;
+                j2.push_back(d);
+            } else {
+                const int q = (r.p - 2) * 2 + (step ? 1 : 0);
+                Job3D d;
+                d.g = g;
+                d.pl = j.pl;
+                j3[q].push_back(d);
+                b3[q].push_back(nb3[q]);
+                nb3[q] += j.pl.nblk;
+                lds3[q] = std::max(lds3[q], j.lds3);
+            }
+        }
+        if (step) ++j.k;
+        if (--j.left == 0) {
+            --s->pending;
+            sl->finishing.push_back(it);
+        }
+    }
+    // descriptors: one host-to-device copy
+    IterLayout L;
+    size_t o = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = o;
+        o = up256(o + bytes);
+        return at;
+    };
+    L.ctl = place(sizeof(BatchCtl));
+    L.eu = place(eu.size() * sizeof(ExpandUnit));
+    L.eb = place(eb.size() * sizeof(int));
+    L.j1 = place(j1.size() * sizeof(Job1D));
+    L.b1 = place(b1.size() * sizeof(int));
+    L.j2 = place(j2.size() * sizeof(BatchJobDev));
+    for (int q = 0; q < 4; ++q) {
+        L.j3[q] = place(j3[q].size() * sizeof(Job3D));
+        L.b3[q] = place(b3[q].size() * sizeof(int));
+    }
+    L.total = o;
+    if (L.total > sl->cap) {
+        const size_t cap = L.total + L.total / 2;
+        if (sl->host) (void)hipHostFree(sl->host);
+        if (sl->dev) (void)hipFreeAsync(sl->dev, s->bstream);
+        sl->host = nullptr;
+        sl->dev = nullptr;
+        sl->cap = 0;
+        IGA_HIP(hipHostMalloc((void**)&sl->host, cap, 0));
+        IGA_HIP(hipMallocAsync((void**)&sl->dev, cap, s->bstream));
+        sl->cap = cap;
+    }
+    BatchCtl ctl;
+    std::memset(&ctl, 0, sizeof(ctl));
+    ctl.njobs = (int)j2.size();
+    ctl.total = chunks;
+    std::memcpy(sl->host + L.ctl, &ctl, sizeof(ctl));
+    put(sl->host, L.eu, eu);
+    put(sl->host, L.eb, eb);
+    put(sl->host, L.j1, j1);
+    put(sl->host, L.b1, b1);
+    put(sl->host, L.j2, j2);
+    for (int q = 0; q < 4; ++q) {
+        put(sl->host, L.j3[q], j3[q]);
+        put(sl->host, L.b3[q], b3[q]);
+    }
+    hipStream_t st = s->bstream;
+    char* dv = sl->dev;
+    IGA_HIP(hipMemcpyAsync(dv, sl->host, L.total, hipMemcpyHostToDevice, st));
+    if (!eu.empty())
+        hipLaunchKernelGGL(serve_expand_kernel, dim3(nbe), dim3(kServeBlock), 0, st, (const ExpandUnit*)(dv + L.eu),
+                           (const int*)(dv + L.eb), (int)eu.size());
+    if (!j1.empty())
+        hipLaunchKernelGGL(serve1d_kernel, dim3(nb1), dim3(kServeBlock), 0, st, (const Job1D*)(dv + L.j1),
+                           (const int*)(dv + L.b1), (int)j1.size());
+    if (!j2.empty())
+        hipLaunchKernelGGL((batch2d_kernel<kTY, true>), dim3(s->grid2d), dim3(64), 0, st, (BatchCtl*)(dv + L.ctl),
+                           (const BatchJobDev*)(dv + L.j2));
+    for (int q = 0; q < 4; ++q) {
+        if (j3[q].empty()) continue;
+        const Job3D* jd = (const Job3D*)(dv + L.j3[q]);
+        const int* bd = (const int*)(dv + L.b3[q]);
+        const int n = (int)j3[q].size();
+        if (q == 0)
+            hipLaunchKernelGGL((serve3d_kernel<2, kOut | kMass>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd, n);
+        else if (q == 1)
+            hipLaunchKernelGGL((serve3d_kernel<2, kOut | kScaleSrc>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd,
+                               n);
+        else if (q == 2)
+            hipLaunchKernelGGL((serve3d_kernel<3, kOut | kMass>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd, n);
+        else
+            hipLaunchKernelGGL((serve3d_kernel<3, kOut | kScaleSrc>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd,
+                               n);
+    }
+    IGA_HIP(hipGetLastError());
+    IGA_HIP(hipEventRecord(sl->ev, st));
+    sl->busy = true;
+    sl->iter = s->launches++;
+    return IGA_OK;
+}
+
 int server_progress(iga_server* s)
 {
-    // completions: events of each stream in launch order, and the batch launch
+    // completions: events of each stream in launch order, then the iterations in order
     for (auto& q : s->inflight) {
         while (!q.empty()) {
             const hipError_t st = hipEventQuery(q.front().ev);
@@ -184,44 +577,46 @@ int server_progress(iga_server* s)
             q.pop_front();
         }
     }
-    if (!s->batch_running.empty()) {
-        const hipError_t st = hipEventQuery(s->batch_ev);
-        if (st == hipSuccess) {
-            for (auto& it : s->batch_running) {
-                it.ev = nullptr;
-                server_finish(s, it, IGA_JOB_DONE, s->launches - 1);
-            }
-            s->batch_running.clear();
-            IGA_TRY(iga_batch_wait(s->batch));   // retires the launch (it is done)
-        } else if (st != hipErrorNotReady) {
-            return IGA_E_DEVICE;
-        }
+    for (;;) {
+        iga_server::Slot* sl = nullptr;
+        for (auto& x : s->slot)
+            if (x.busy && (!sl || x.iter < sl->iter)) sl = &x;
+        if (!sl) break;
+        const hipError_t st = hipEventQuery(sl->ev);
+        if (st == hipErrorNotReady) break;
+        if (st != hipSuccess) return IGA_E_DEVICE;
+        for (auto it : sl->finishing) server_finish_job(s, it, IGA_JOB_DONE, sl->iter);
+        sl->finishing.clear();
+        sl->busy = false;
     }
     // admission, in submission order
     while (!s->waiting.empty()) {
         iga_server::Item& it = s->waiting.front();
         if (s->used + it.bytes > s->budget) break;
         const iga_request& r = it.r;
-        if (r.kind == IGA_REQ_RHS && r.dim == 2) {
-            iga_job j;
-            j.p = r.p;
-            j.ne[0] = r.ne[0];
-            j.ne[1] = r.ne[1];
-            j.u = r.u;
-            j.mass_out = r.mass_out;
-            j.lap_out = r.lap_out;
-            uint64_t t = 0;
-            const int rc = iga_batch_submit(s->batch, &j, 1, &t);
-            if (rc == IGA_E_AGAIN) break;
-            it.ev = nullptr;
-            s->used += it.bytes;
-            if (rc != IGA_OK) {
-                server_finish(s, it, IGA_JOB_FAILED, -1);
-            } else {
-                s->batch_queued.push_back(it);
+        s->used += it.bytes;
+        if (batchable(r)) {
+            iga_server::Job j;
+            std::memset(&j.pl, 0, sizeof(j.pl));
+            j.ticket = it.ticket;
+            j.r = r;
+            j.bytes = it.bytes;
+            for (int a = 0; a < 3; ++a) j.R[a] = a < r.dim ? (int)(r.ne[a] + r.p) : 1;
+            j.left = r.kind == IGA_REQ_RHS ? 1 : r.nsteps;
+            j.k = 0;
+            j.setup = true;
+            j.tab = nullptr;
+            j.work = nullptr;
+            j.block = -1;
+            j.lds3 = 0;
+            if (r.dim == 3) {
+                int nt = 0;
+                j.pl = plan_3d_rows(r.p, j.R[0], j.R[1], j.R[2], 0, 0, 0, &nt, &j.lds3);
             }
+            s->jobs.push_back(j);
+            s->fresh.push_back(std::prev(s->jobs.end()));
+            ++s->pending;
         } else {
-            s->used += it.bytes;
             it.ev = nullptr;
             if (server_launch(s, it) != IGA_OK) {
                 (void)hipGetLastError();
@@ -231,17 +626,11 @@ int server_progress(iga_server* s)
         s->peak = std::max(s->peak, s->used);
         s->waiting.pop_front();
     }
-    // a batch launch takes every queued 2D RHS request when none is running
-    if (s->batch_running.empty() && !s->batch_queued.empty()) {
-        const int rc = iga_batch_flush(s->batch);
-        if (rc != IGA_OK) {
-            for (auto& it : s->batch_queued) server_finish(s, it, IGA_JOB_FAILED, -1);
-            s->batch_queued.clear();
-            return IGA_OK;
-        }
-        IGA_HIP(hipEventRecord(s->batch_ev, s->batch_stream));
-        s->batch_running.swap(s->batch_queued);
-        ++s->launches;
+    // iterations: while a slot is free and some job has work left
+    while (s->pending > 0) {
+        const int64_t before = s->launches;
+        IGA_TRY(server_iterate(s));
+        if (s->launches == before) break;
     }
     return IGA_OK;
 }
@@ -266,9 +655,19 @@ int iga_server_create(int32_t nstreams, size_t mem_budget_bytes, size_t cache_by
         if (ok) s->streams.push_back(st);
     }
     s->inflight.resize(s->streams.size());
-    ok = ok && hipStreamCreateWithFlags(&s->batch_stream, hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&s->batch_ev, hipEventDisableTiming) == hipSuccess &&
-         iga_batch_create(s->batch_stream, 0, 1 << 16, &s->batch) == IGA_OK;
+    ok = ok && hipStreamCreateWithFlags(&s->bstream, hipStreamNonBlocking) == hipSuccess;
+    for (auto& sl : s->slot) ok = ok && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess;
+    if (ok) {   // the persistent 2D launch fills the chip once
+        int dev = 0, ncu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, iga::batch2d_kernel<16, true>, 64, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            ncu = 256;
+            per = 4;
+        }
+        s->grid2d = std::max(8, ncu * std::max(per, 1));
+    }
     if (!ok) {
         (void)hipGetLastError();
         iga_server_destroy(s);
@@ -347,16 +746,22 @@ int iga_server_destroy(iga_server* s)
 {
     if (!s) return IGA_E_INVAL;
     for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-    if (s->batch_stream) (void)hipStreamSynchronize(s->batch_stream);
-    if (s->batch) iga_batch_destroy(s->batch);
+    if (s->bstream) (void)hipStreamSynchronize(s->bstream);
     for (auto& kv : s->cache) iga_destroy(kv.second.c);
     for (auto& q : s->inflight)
         for (auto& it : q)
             if (it.ev) (void)hipEventDestroy(it.ev);
     for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
-    if (s->batch_ev) (void)hipEventDestroy(s->batch_ev);
+    for (auto& kv : s->blocks) (void)hipFreeAsync(kv.second.mem, s->bstream);
+    for (auto& sl : s->slot) {
+        if (sl.dev) (void)hipFreeAsync(sl.dev, s->bstream);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+    }
+    if (s->bstream) (void)hipStreamSynchronize(s->bstream);
+    for (auto& sl : s->slot)
+        if (sl.host) (void)hipHostFree(sl.host);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-    if (s->batch_stream) (void)hipStreamDestroy(s->batch_stream);
+    if (s->bstream) (void)hipStreamDestroy(s->bstream);
     delete s;
     return IGA_OK;
 }

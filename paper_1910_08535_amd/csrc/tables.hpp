@@ -117,6 +117,72 @@ __device__ void basis_ders(int p, int ne, int e, double s, double inv_h,
     }
 }
 
+// Element length and its inverse as every table of an axis forms them.
+__host__ __device__ inline double elem_len(double lo, double hi, int ne) { return (hi - lo) / (double)ne; }
+__host__ __device__ inline double elem_inv_len(double lo, double hi, int ne) { return (double)ne / (hi - lo); }
+
+// Element sum of W sin(pi x) over the Gauss points of element e: gw[q] = weight x Jacobian,
+// gs[q] = local coordinate of point q.
+__device__ __forceinline__ double elem_sine_sum(double lo, double hi, int ne, int e, int nq, const double* gw,
+                                                const double* gs)
+{
+    double es = 0.0;
+    for (int q = 0; q < nq; ++q) {
+        const double x = lo + (hi - lo) * (((double)e + gs[q]) / (double)ne);
+        es = fma(gw[q], sin(M_PI * x), es);
+    }
+    return es;
+}
+
+// Support span of PG row r (elements s .. l) and the row's scale 1/|S_r| of the lumped step.
+__host__ __device__ inline void support_span(int r, int p, int ne, int* s, int* l)
+{
+    *s = r - p > 0 ? r - p : 0;
+    *l = r < ne - 1 ? r : ne - 1;
+}
+
+__host__ __device__ inline double span_scale(int s, int l, int ne, double lo, double hi)
+{
+    return (double)ne / ((double)(l - s + 1) * (hi - lo));
+}
+
+// ---------------------------------------------------------------------------------
+// Petrov-Galerkin rows in element units.  With support spans on a uniform axis of at
+// least 3p+1 elements, the Gauss sums of a PG row depend on the row only through its
+// distance to the nearer end (the B-splines are evaluated in element-local knot units):
+// the first 2p rows, the last 2p rows and one interior row are all the distinct rows,
+// 4p+1 of them.  Summed with weights w_q / 2 and derivatives per unit of the local
+// coordinate they hold for every such axis, and the axis' own rows follow as
+//   M_r = h * Mgen_c(r),   D_r = (1/h) * Dgen_c(r),   h = (hi - lo) / ne.
+// Layout of one (p, nq) table: Mgen[(4p+1) W] | Dgen[(4p+1) W] | w[nq] | s[nq]
+// (Gauss weights on [-1, 1] and the points as local coordinates in [0, 1]).
+// ---------------------------------------------------------------------------------
+__host__ __device__ inline int pg_generic_min_ne(int p) { return 3 * p + 1; }
+
+__host__ __device__ inline size_t pg_generic_doubles(int p, int nq)
+{
+    return 2 * (size_t)(4 * p + 1) * (2 * p + 1) + 2 * (size_t)nq;
+}
+
+// The distinct row (0 .. 4p) that row r of an axis of R rows equals.
+__host__ __device__ inline int pg_row_class(int r, int R, int p)
+{
+    return r < 2 * p ? r : (r >= R - 2 * p ? 4 * p - (R - 1 - r) : 2 * p);
+}
+
+// Taps k of PG row r of an axis: M = h Mgen, D = (1/h) Dgen.
+__device__ __forceinline__ void pg_generic_row(const double* gen, int p, int r, int R, double h, double ih,
+                                               double* m, double* d)
+{
+    const int W = 2 * p + 1, c = pg_row_class(r, R, p);
+    const double* gm = gen + (size_t)c * W;
+    const double* gd = gen + (size_t)(4 * p + 1) * W + (size_t)c * W;
+    for (int k = 0; k < W; ++k) {
+        m[k] = h * gm[k];
+        d[k] = ih * gd[k];
+    }
+}
+
 // Per-axis device tables.  Layout of one axis (all doubles unless noted):
 //   cls[ncls*nq*3*(p+1)]      cls[((c*nq+q)*3 + m)*(p+1) + a] = B^{(m)}_{e+a} at point q of
 //                             an element e of class c
@@ -128,6 +194,8 @@ __device__ void basis_ders(int p, int ne, int e, double s, double inv_h,
 //   gm[N*W], gl[N*W], gb[N*W] Galerkin int B_i B_j, int B_i B_j'', -int B_i' B_j'
 //   fs_g[N]                   int B_i sin(pi x)  (Gauss rule)
 //   first[R], last[R] (int)   PG spans
+// pgen points at the element-unit PG rows of (p, nq) (below) when the axis' PG factors are
+// taken from them, else it is null.
 struct AxisTables {
     int p, ne, nq, N, R, W;
     double lo, hi;
@@ -136,6 +204,7 @@ struct AxisTables {
     double *pm, *pd, *inv_len, *fs_pg;
     double *gm, *gl, *gb, *fs_g;
     int *first, *last;
+    const double* pgen;
 };
 
 // The tables of every axis of a context, filled by three launches in all.
@@ -193,15 +262,14 @@ __global__ void element_tables_kernel(AxisSet set)
     if (e >= t.ne) return;
     const int np1 = t.p + 1, nb = 3 * np1;
     const int c = class_of(e, t.p, t.ne);
-    double es = 0.0, eg[kMaxP + 1] = {};
+    double eg[kMaxP + 1] = {};
     for (int q = 0; q < t.nq; ++q) {
         const double x = t.lo + (t.hi - t.lo) * (((double)e + t.gs[q]) / (double)t.ne);
         const double sx = sin(M_PI * x), w = t.gw[q];
         const double* B = t.cls + ((size_t)c * t.nq + q) * nb;
-        es += w * sx;
         for (int a = 0; a <= t.p; ++a) eg[a] += w * B[a] * sx;
     }
-    t.es[e] = es;
+    t.es[e] = elem_sine_sum(t.lo, t.hi, t.ne, e, t.nq, t.gw, t.gs);
     for (int a = 0; a <= t.p; ++a) t.eg[(size_t)e * np1 + a] = eg[a];
 }
 
@@ -225,8 +293,7 @@ __global__ void band_tables_kernel(AxisSet set)
     if (r < t.R) {
         int s, l;
         if (kind == 0) {
-            s = r - p > 0 ? r - p : 0;
-            l = r < t.ne - 1 ? r : t.ne - 1;
+            support_span(r, p, t.ne, &s, &l);
             t.first[r] = s;
             t.last[r] = l;
         } else if (kind == 1) {
@@ -237,25 +304,34 @@ __global__ void band_tables_kernel(AxisSet set)
             s = t.first[r];
             l = t.last[r];
         }
-        for (int k = 0; k < W; ++k) {
-            const int j = r + k - p;
-            double m0 = 0.0, d0 = 0.0;
-            for (int e = s; e <= l; ++e) {
-                const int a = j - e;
-                if (a < 0 || a > p) continue;
-                const double* B = scls + (size_t)class_of(e, p, t.ne) * nq * nb;
-                for (int q = 0; q < nq; ++q) {
-                    m0 += sgw[q] * B[q * nb + a];
-                    d0 += sgw[q] * B[q * nb + 2 * np1 + a];
-                }
+        if (t.pgen) {   // support spans, at least 3p+1 elements: scaled element-unit rows
+            double m[2 * kMaxP + 1], d[2 * kMaxP + 1];
+            pg_generic_row(t.pgen, p, r, t.R, elem_len(t.lo, t.hi, t.ne), elem_inv_len(t.lo, t.hi, t.ne), m, d);
+            for (int k = 0; k < W; ++k) {
+                t.pm[(size_t)r * W + k] = m[k];
+                t.pd[(size_t)r * W + k] = d[k];
             }
-            t.pm[(size_t)r * W + k] = m0;
-            t.pd[(size_t)r * W + k] = d0;
+        } else {
+            for (int k = 0; k < W; ++k) {
+                const int j = r + k - p;
+                double m0 = 0.0, d0 = 0.0;
+                for (int e = s; e <= l; ++e) {
+                    const int a = j - e;
+                    if (a < 0 || a > p) continue;
+                    const double* B = scls + (size_t)class_of(e, p, t.ne) * nq * nb;
+                    for (int q = 0; q < nq; ++q) {
+                        m0 += sgw[q] * B[q * nb + a];
+                        d0 += sgw[q] * B[q * nb + 2 * np1 + a];
+                    }
+                }
+                t.pm[(size_t)r * W + k] = m0;
+                t.pd[(size_t)r * W + k] = d0;
+            }
         }
         double fs = 0.0;
         for (int e = s; e <= l; ++e) fs += t.es[e];
         t.fs_pg[r] = fs;
-        t.inv_len[r] = (double)t.ne / ((double)(l - s + 1) * (t.hi - t.lo));
+        t.inv_len[r] = span_scale(s, l, t.ne, t.lo, t.hi);
     }
     if (r < t.N) {
         const int e0 = r - p < 0 ? 0 : r - p;
@@ -281,6 +357,58 @@ __global__ void band_tables_kernel(AxisSet set)
         double fs = 0.0;
         for (int e = e0; e <= e1; ++e) fs += t.eg[(size_t)e * np1 + (r - e)];
         t.fs_g[r] = fs;
+    }
+}
+
+// The 4p+1 distinct element-unit PG rows of (p, nq), computed on the axis of 3p+1
+// elements, where each occurs once (row 2p is its only interior row): one workgroup, one
+// thread per (row, tap).  Every sum runs over the row's span elements, then the Gauss
+// points, in the order of the per-axis kernel above.
+__global__ void pg_generic_kernel(double* gen, int p, int nq)
+{
+    __shared__ double sw[kMaxNq], ss[kMaxNq];
+    __shared__ double scls[(2 * kMaxP + 1) * kMaxNq * 3 * (kMaxP + 1)];
+    const int np1 = p + 1, nb = 3 * np1, W = 2 * p + 1;
+    const int ne = pg_generic_min_ne(p), nc = n_classes(p, ne);
+    const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
+    for (int q = tid; q < nq; q += nt) {
+        double xi, w;
+        gauss_node(nq, q, &xi, &w);
+        sw[q] = w;
+        ss[q] = 0.5 * (xi + 1.0);
+    }
+    __syncthreads();
+    for (int i = tid; i < nc * nq; i += nt) {
+        const int c = i / nq, q = i - c * nq;
+        double B[3][kMaxP + 1];
+        basis_ders(p, ne, class_element(c, p, ne), ss[q], 1.0, B);
+        for (int m = 0; m < 3; ++m)
+            for (int a = 0; a <= p; ++a) scls[((size_t)i * 3 + m) * np1 + a] = B[m][a];
+    }
+    __syncthreads();
+    for (int i = tid; i < (4 * p + 1) * W; i += nt) {
+        const int rc = i / W, k = i - rc * W;
+        const int r = rc;   // R = 4p+1 rows: row rc is distinct row rc
+        int s, l;
+        support_span(r, p, ne, &s, &l);
+        const int j = r + k - p;
+        double m0 = 0.0, d0 = 0.0;
+        for (int e = s; e <= l; ++e) {
+            const int a = j - e;
+            if (a < 0 || a > p) continue;
+            const double* B = scls + (size_t)class_of(e, p, ne) * nq * nb;
+            for (int q = 0; q < nq; ++q) {
+                const double w = 0.5 * sw[q];
+                m0 += w * B[q * nb + a];
+                d0 += w * B[q * nb + 2 * np1 + a];
+            }
+        }
+        gen[i] = m0;
+        gen[(size_t)(4 * p + 1) * W + i] = d0;
+    }
+    for (int q = tid; q < nq; q += nt) {
+        gen[2 * (size_t)(4 * p + 1) * W + q] = sw[q];
+        gen[2 * (size_t)(4 * p + 1) * W + nq + q] = ss[q];
     }
 }
 

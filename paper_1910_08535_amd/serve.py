@@ -1,8 +1,10 @@
 """Continuous-batching server for right-hand-side and explicit-step requests.
 
 The request loop itself is native (iga_server_* in the library, see include/iga.h):
-admission by device memory, a context cache bound to a pool of streams, 2D RHS requests
-riding the next persistent batch launch, event-based completion.  This module replays
+admission by device memory; iterations in which every admitted request with axes of at
+least 3p+1 elements advances together (a right-hand side once, an explicit step by one
+step per iteration); a context cache bound to a pool of streams for the other requests;
+event-based completion.  This module replays
 arrivals in wall-clock time, hands each arriving group of requests to the library in one
 call, and records latencies:
 
@@ -15,8 +17,8 @@ call, and records latencies:
   and allocated at submission.
 * Latency of a request = time its completion is observed - its arrival time.
 
-Results do not depend on the mix: a request runs the same kernels with the same
-launch geometry alone and among others (tests check equality bit for bit).
+Results do not depend on the mix: a request gives the bits it gives alone on a context
+(the same row arithmetic and the same band rows; tests check equality bit for bit).
 """
 from __future__ import annotations
 
@@ -107,13 +109,29 @@ class MeshCache:
         self.bytes = 0
 
 
+def batched(req: Request) -> bool:
+    """Whether the library's batched iterations take the request: every axis has at least
+    3p+1 elements (the size limits of a mesh context aside)."""
+    return all(n >= 3 * req.p + 1 for n in req.ne)
+
+
 def footprint(req: Request) -> int:
-    """Bytes a request holds while in flight: coefficients plus both outputs (RHS), or
-    coefficients plus the step's work buffer."""
+    """Bytes a request holds while in flight, as the library counts them against its
+    budget: coefficients plus both outputs (RHS), or coefficients plus the step's work
+    buffer; for a batched request also its own band tables (M and D rows per axis, and the
+    step's scale and source rows; in 1D only the step's source rows)."""
     n = 1
     for d in request_shape(req):
         n *= d
-    return (3 if req.kind == "rhs" else 2) * 8 * n
+    b = (3 if req.kind == "rhs" else 2) * 8 * n
+    if batched(req):
+        w = 2 * req.p + 1
+        step = req.kind != "rhs"
+        if req.dim == 1:
+            b += 8 * (req.ne[0] + req.p) if step else 0
+        else:
+            b += 8 * sum((m + req.p) * (2 * w + (2 if step else 0)) for m in req.ne)
+    return b
 
 
 class Server:
