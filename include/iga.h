@@ -380,17 +380,23 @@ int iga_batch_destroy(iga_batch *b);
  *                 source sin_amp * prod_a sin(pi x_a),
  * on dim axes of ne[a] elements on [0, 1], degree p, p+1 Gauss points per axis.
  * Requests are admitted in submission order while the bytes of the requests in flight
- * (u and both outputs, or u and the step's work buffer) stay within the budget.  An
- * admitted request runs at once on the stream of its mesh's context: contexts are cached
- * (least recently used first out while the device memory the cached contexts hold -- their
- * tables and scratch, such as an explicit step's work buffer -- exceeds cache_bytes; the
- * most recently used one always stays) and bound round-robin to
- * the server's streams.  2D RHS requests instead join the queue of the persistent batch
- * launch of iga_batch: whenever no launch is running, one launch takes every queued
- * 2D RHS request (continuous batching).  Completion is observed from HIP events; no call
- * blocks except iga_server_destroy.  Results equal those of the same request run alone
- * through iga_apply / iga_explicit_step, bit for bit.  All buffers are caller-owned
- * device memory and must stay valid until the request is reported done.
+ * stay within the budget: u and both outputs, or u and the step's work buffer, plus a
+ * batched request's own band tables (M and D rows per axis and the step's scale and
+ * source rows; in 1D only the step's source rows).  A request whose every axis has at
+ * least 3p+1 elements is batched: it needs no context, and all admitted batched requests
+ * advance together in iterations, each one descriptor copy and one launch per kind of
+ * request (1D, 2D, 3D per degree and kind) on the server's own streams, at most two
+ * iterations in flight.  A right-hand side runs in one iteration, a step request takes
+ * one step per iteration (continuous batching at the granularity of a step); a request
+ * admitted while iterations run joins the next one.  Any other request runs at once on
+ * the stream of its mesh's context: contexts are cached (least recently used first out
+ * while the device memory the cached contexts hold -- their tables and scratch, such as
+ * an explicit step's work buffer -- exceeds cache_bytes; the most recently used one
+ * always stays) and bound round-robin to the server's streams.  Completion is observed
+ * from HIP events; no call blocks except iga_server_destroy.  Results equal those of the
+ * same request run alone through iga_apply / iga_explicit_step, bit for bit.  All
+ * buffers are caller-owned device memory and must stay valid until the request is
+ * reported done.
  * ------------------------------------------------------------------------------ */
 #define IGA_REQ_RHS 0
 #define IGA_REQ_STEP 1
@@ -417,15 +423,16 @@ int iga_server_create(int32_t nstreams, size_t mem_budget_bytes, size_t cache_by
    [n]) receive their ids.  Errors: IGA_E_INVAL (bad request), IGA_E_UNSUPPORTED (dim or
    p), IGA_E_NOMEM (a request larger than the whole budget). */
 int iga_server_submit(iga_server *s, const iga_request *reqs, int32_t n, uint64_t *tickets);
-/* Harvests completions, admits queued requests that now fit and starts a batch launch
-   if none runs; then reports up to cap completed requests (host arrays): ticket, time in
-   seconds since the server was created (when the completion was observed), state
-   (IGA_JOB_DONE or IGA_JOB_FAILED) and, if done_launch is not NULL, the index of the
-   batch launch that ran it (-1 for none).  *ndone receives the count.  Never blocks. */
+/* Harvests completions, admits queued requests that now fit and enqueues iterations while
+   fewer than two are in flight and batched requests have work left; then reports up to
+   cap completed requests (host arrays): ticket, time in seconds since the server was
+   created (when the completion was observed), state (IGA_JOB_DONE or IGA_JOB_FAILED) and,
+   if done_launch is not NULL, the index of the iteration that ran its last kernel (-1 for
+   a request run on a context).  *ndone receives the count.  Never blocks. */
 int iga_server_progress(iga_server *s, uint64_t *done, double *done_time, int32_t *done_state,
                         int64_t *done_launch, int32_t cap, int32_t *ndone);
-/* Bytes in flight, their peak, batch launches so far, and the server's clock (seconds
-   since creation); every output is nullable. */
+/* Bytes in flight, their peak, iterations enqueued so far (batch_launches), and the
+   server's clock (seconds since creation); every output is nullable. */
 int iga_server_stats(const iga_server *s, size_t *used, size_t *peak, int64_t *batch_launches,
                      double *now);
 /* Device bytes held by the cached contexts (tables and scratch, as counted against

@@ -9,7 +9,8 @@
 // the loop enqueues the next iteration on a stream of its own: the descriptors of the
 // iteration (one host-to-device copy), the set-up of the jobs admitted since the last
 // one, then one launch per kind of job (1D, 2D, 3D per degree and output mode) over all
-// jobs.  A right-hand-side job runs in one iteration, a step job in one per step.
+// jobs, the kinds side by side on streams forked from that stream and joined back.  A
+// right-hand-side job runs in one iteration, a step job in one per step.
 // Completion is observed from HIP events, never waited for.
 #pragma once
 
@@ -88,6 +89,10 @@ struct iga_server {
     };
     Slot slot[2];
     hipStream_t bstream = nullptr;
+    // the kinds of job of an iteration (1D, 2D, 3D) run side by side on streams of their
+    // own, forked from and joined back into bstream
+    hipStream_t fstream[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     const double* gen[iga::kMaxP + 1] = {};   // element-unit PG rows of (p, p+1)
     int grid2d = 0;                           // workgroups of the persistent 2D launch
     int64_t launches = 0;                     // iterations enqueued
@@ -536,29 +541,47 @@ int server_iterate(iga_server* s)
     if (!eu.empty())
         hipLaunchKernelGGL(serve_expand_kernel, dim3(nbe), dim3(kServeBlock), 0, st, (const ExpandUnit*)(dv + L.eu),
                            (const int*)(dv + L.eb), (int)eu.size());
-    if (!j1.empty())
-        hipLaunchKernelGGL(serve1d_kernel, dim3(nb1), dim3(kServeBlock), 0, st, (const Job1D*)(dv + L.j1),
+    const bool has[3] = {!j1.empty(), !j2.empty(), !(j3[0].empty() && j3[1].empty() && j3[2].empty() && j3[3].empty())};
+    const bool forked = (int)has[0] + (int)has[1] + (int)has[2] > 1;
+    hipStream_t ks[3] = {st, st, st};
+    if (forked) {
+        IGA_HIP(hipEventRecord(s->fork, st));
+        for (int f = 0; f < 3; ++f)
+            if (has[f]) {
+                ks[f] = s->fstream[f];
+                IGA_HIP(hipStreamWaitEvent(ks[f], s->fork, 0));
+            }
+    }
+    if (has[0])
+        hipLaunchKernelGGL(serve1d_kernel, dim3(nb1), dim3(kServeBlock), 0, ks[0], (const Job1D*)(dv + L.j1),
                            (const int*)(dv + L.b1), (int)j1.size());
-    if (!j2.empty())
-        hipLaunchKernelGGL((batch2d_kernel<kTY, true>), dim3(s->grid2d), dim3(64), 0, st, (BatchCtl*)(dv + L.ctl),
+    if (has[1])
+        hipLaunchKernelGGL((batch2d_kernel<kTY, true>), dim3(s->grid2d), dim3(64), 0, ks[1], (BatchCtl*)(dv + L.ctl),
                            (const BatchJobDev*)(dv + L.j2));
     for (int q = 0; q < 4; ++q) {
         if (j3[q].empty()) continue;
         const Job3D* jd = (const Job3D*)(dv + L.j3[q]);
         const int* bd = (const int*)(dv + L.b3[q]);
         const int n = (int)j3[q].size();
+        hipStream_t k3 = ks[2];
         if (q == 0)
-            hipLaunchKernelGGL((serve3d_kernel<2, kOut | kMass>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd, n);
+            hipLaunchKernelGGL((serve3d_kernel<2, kOut | kMass>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], k3, jd, bd, n);
         else if (q == 1)
-            hipLaunchKernelGGL((serve3d_kernel<2, kOut | kScaleSrc>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd,
+            hipLaunchKernelGGL((serve3d_kernel<2, kOut | kScaleSrc>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], k3, jd, bd,
                                n);
         else if (q == 2)
-            hipLaunchKernelGGL((serve3d_kernel<3, kOut | kMass>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd, n);
+            hipLaunchKernelGGL((serve3d_kernel<3, kOut | kMass>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], k3, jd, bd, n);
         else
-            hipLaunchKernelGGL((serve3d_kernel<3, kOut | kScaleSrc>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], st, jd, bd,
+            hipLaunchKernelGGL((serve3d_kernel<3, kOut | kScaleSrc>), dim3(nb3[q]), dim3(kMaxNT3), lds3[q], k3, jd, bd,
                                n);
     }
     IGA_HIP(hipGetLastError());
+    if (forked)
+        for (int f = 0; f < 3; ++f)
+            if (has[f]) {
+                IGA_HIP(hipEventRecord(s->join[f], ks[f]));
+                IGA_HIP(hipStreamWaitEvent(st, s->join[f], 0));
+            }
     IGA_HIP(hipEventRecord(sl->ev, st));
     sl->busy = true;
     sl->iter = s->launches++;
@@ -657,6 +680,10 @@ int iga_server_create(int32_t nstreams, size_t mem_budget_bytes, size_t cache_by
     s->inflight.resize(s->streams.size());
     ok = ok && hipStreamCreateWithFlags(&s->bstream, hipStreamNonBlocking) == hipSuccess;
     for (auto& sl : s->slot) ok = ok && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&s->fork, hipEventDisableTiming) == hipSuccess;
+    for (int f = 0; f < 3; ++f)
+        ok = ok && hipStreamCreateWithFlags(&s->fstream[f], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&s->join[f], hipEventDisableTiming) == hipSuccess;
     if (ok) {   // the persistent 2D launch fills the chip once
         int dev = 0, ncu = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -746,6 +773,8 @@ int iga_server_destroy(iga_server* s)
 {
     if (!s) return IGA_E_INVAL;
     for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+    for (int f = 0; f < 3; ++f)
+        if (s->fstream[f]) (void)hipStreamSynchronize(s->fstream[f]);
     if (s->bstream) (void)hipStreamSynchronize(s->bstream);
     for (auto& kv : s->cache) iga_destroy(kv.second.c);
     for (auto& q : s->inflight)
@@ -762,6 +791,11 @@ int iga_server_destroy(iga_server* s)
         if (sl.host) (void)hipHostFree(sl.host);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->bstream) (void)hipStreamDestroy(s->bstream);
+    for (int f = 0; f < 3; ++f) {
+        if (s->fstream[f]) (void)hipStreamDestroy(s->fstream[f]);
+        if (s->join[f]) (void)hipEventDestroy(s->join[f]);
+    }
+    if (s->fork) (void)hipEventDestroy(s->fork);
     delete s;
     return IGA_OK;
 }
