@@ -51,9 +51,9 @@ def copy_probe(mib: int) -> None:
     del a, b
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str = None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources (and on the named kernel); else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     try:
         with open(path) as fh:
@@ -61,6 +61,8 @@ def measured_traffic(workload: str):
     except OSError:
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash(rec.get("family", "apply2d")):
+        return None
+    if kernel is not None and kernel not in rec.get("kernel", ""):
         return None
     return rec.get("bytes_per_launch")
 
@@ -139,6 +141,11 @@ def run_c2(args):
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     mesh = iga.Mesh(2, c.p, c.ne, c.nq, stream=stream)
+    # the library's autotuner picks the tile (strip width, chunk rows, chunk order)
+    tune_us = mesh.autotune(iga.TUNE_APPLY, reps=20)
+    tile = mesh.tile()
+    kernel = (f"iga::apply2d_kernel<2, {tile['rows']}, 3, true>" if tile["strip"] == 128
+              else f"iga::apply2d1_kernel<2, {tile['rows']}, 3>")
     u0 = torch.from_numpy(c.coefs()).to("cuda")
     set_bytes = BYTES_C2
     nsets = max(1, -(-args.rotate_mb * 2**20 // set_bytes))
@@ -201,7 +208,7 @@ def run_c2(args):
     assert torch.equal(sets[0][1], sets[0][0]) and torch.equal(sets[0][2], sets[0][0])
 
     achieved = BYTES_C2 / per_launch_s / 1e9
-    traffic = measured_traffic("apply2d_p2_1024")
+    traffic = measured_traffic("apply2d_p2_1024", kernel)
     out = {
         "metric": "RHS Gauss-points/s (PG fused mass+Laplacian apply)",
         "value": GP_C2 * args.steps / wall,
@@ -224,7 +231,8 @@ def run_c2(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "iga::apply2d_kernel<2, 8, 3, true>",
+                     "kernel": kernel, "tile": tile,
+                     "tile_candidates_us": [round(float(t), 3) for t in tune_us],
                      "algorithmic_bytes_per_launch": BYTES_C2,
                      "avg_launch_us": per_launch_s * 1e6},
         "copy_floor": {"kernel": "iga::copy2_kernel (read once, two streamed writes)",
@@ -254,6 +262,10 @@ def run_c3(args) -> dict:
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     mesh = iga.Mesh(3, c.p, c.ne, c.nq, stream=stream)
+    # the library's autotuner picks the tile (z-chunk planes, tile rows and columns); the
+    # 16 meshes of the rotated run below start from the same choice
+    tune_us = mesh.autotune(iga.TUNE_STEP, reps=20)
+    tile = mesh.tile()
     u0 = torch.from_numpy(c.coefs()).to("cuda")
     u = u0.clone()
     for _ in range(2):   # the second identical call captures the graph
@@ -303,7 +315,8 @@ def run_c3(args) -> dict:
             "roofline": {"bound": "hbm", "achieved": bytes_step / rot_s / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": bytes_step / rot_s / (HBM_PEAK_GBS * 1e9),
                          "traffic": measured_traffic("heat3d_p3_128"),
-                         "kernel": "iga::apply3d_kernel<3, 9>",
+                         "kernel": "iga::apply3d_kernel<3, 9>", "tile": tile,
+                         "tile_candidates_us": [round(float(t), 3) for t in tune_us],
                          "algorithmic_bytes_per_launch": bytes_step, "avg_launch_us": rot_s * 1e6}}
 
 

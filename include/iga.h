@@ -300,6 +300,8 @@ int iga_dirichlet_rows(iga_ctx *ctx, int32_t form, int32_t side_mask, const doub
      IGA_TILE_3D_ROWS    output rows per 3D tile: even, 2..32, 0 = automatic (default;
                          fewer when the tile's footprint would not fit a workgroup)
      IGA_TILE_3D_COLS    output columns per 3D tile: even, 8..96, 0 = automatic (default)
+     IGA_TILE_2D_STRIP   2D strip width: 128 columns, two per lane (default), or 64, one
+                         per lane (same bits)
    Changing a setting drops the context's cached graph.
    Errors: IGA_E_INVAL (unknown key or value). */
 #define IGA_TILE_2D_ROWS 1
@@ -307,8 +309,32 @@ int iga_dirichlet_rows(iga_ctx *ctx, int32_t form, int32_t side_mask, const doub
 #define IGA_TILE_3D_ROWS 4
 #define IGA_TILE_2D_ORDER 5
 #define IGA_TILE_3D_COLS 6
+#define IGA_TILE_2D_STRIP 7
 int iga_set_tile(iga_ctx *ctx, int32_t key, int32_t value);
 int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);
+
+/* Autotuning of a 2D or 3D context's tile setting.  Times every candidate setting of the
+   hot kernel of op -- IGA_TUNE_APPLY: the fused PG apply (mass and Laplacian rows, as
+   iga_apply); IGA_TUNE_STEP: one lumped explicit step with a sine source (as
+   iga_explicit_step) -- with reps >= 1 launches each after two warm-up launches, on
+   buffers of its own, timed with HIP events on the context's stream.  The fastest setting
+   becomes the context's, and the process remembers it: contexts created later with the
+   same dim, p, span kind and size class (the bit length of every axis' row count) start
+   from it.  Candidates, in this order (times_us follows it):
+     2D: IGA_TILE_2D_STRIP in {128, 64} x IGA_TILE_2D_ROWS in {4, 8, 16}
+         x IGA_TILE_2D_ORDER in {0, 1}                                   (12)
+     3D: IGA_TILE_3D_PLANES in {0, 6, 12} x IGA_TILE_3D_ROWS in {0, 8}
+         x IGA_TILE_3D_COLS in {0, 32}                                   (12)
+   Every candidate forms every sum in the same order, so the results do not depend on the
+   choice.  Blocks until its launches are done.  A 1D context has nothing to tune: IGA_OK
+   with *ntimed = 0.  times_us (nullable, IGA_TUNE_MAX entries) receives the average
+   microseconds per launch of each candidate, *ntimed (nullable) their number.
+   Errors: IGA_E_INVAL (bad op or reps, stream capture, a span kind without the op),
+   IGA_E_NOMEM, IGA_E_DEVICE. */
+#define IGA_TUNE_APPLY 0
+#define IGA_TUNE_STEP 1
+#define IGA_TUNE_MAX 16
+int iga_autotune(iga_ctx *ctx, int32_t op, int32_t reps, float *times_us, int32_t *ntimed);
 
 /* Bandwidth reference of the fused 2D apply (not part of the method): reads the n doubles
    of src once and writes them to dst_a and dst_b (device, caller-owned, no overlap), with

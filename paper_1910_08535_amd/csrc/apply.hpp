@@ -361,6 +361,134 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     }
 }
 
+// The same chunk with one column per lane: a strip of 64 output columns, 8-byte accesses.
+// Twice the waves for the same rows, each with half the arithmetic; the sums are formed
+// in the same order, so both strip widths give the same bits.
+template <int P, int TY>
+struct Chunk2D1 {
+    static constexpr int W = 2 * P + 1;
+    static constexpr int NR = TY + 2 * P;
+    static constexpr int SW = 64;
+    static constexpr int RBW = SW + 2 * P + 2;
+    static constexpr int CW = 2 * W + 2;
+    static constexpr int NCV = (TY * CW + 63) / 64;
+    static constexpr int LDS = NR * RBW + NCV * 64;
+};
+
+template <int P, int TY, int MODE>
+__device__ __forceinline__ void apply2d_chunk1(const ApplyArgs& g, int bx, int by, double* lds)
+{
+    using C = Chunk2D1<P, TY>;
+    constexpr int W = C::W, NR = C::NR, SW = C::SW, RBW = C::RBW, CW = C::CW, NCV = C::NCV;
+    double (*rb)[RBW] = reinterpret_cast<double (*)[RBW]>(lds);
+    double* cy = lds + NR * RBW;
+    const AxisOp &X = g.ax[0], &Y = g.ax[1];
+    const int x0 = bx * SW, y0 = by * TY;
+    const int lane = threadIdx.x;
+    const int Nx = X.N, Ny = Y.N;
+    const int c0 = x0 + lane;
+    const auto rxm = buf(X.M, (size_t)X.R * W), rxd = buf(X.D, (size_t)X.R * W);
+    double m0[W], d0[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        m0[k] = bload(rxm, c0 < X.R ? (unsigned)(c0 * W + k) * 8u : kOOB);
+        d0[k] = bload(rxd, c0 < X.R ? (unsigned)(c0 * W + k) * 8u : kOOB);
+    }
+    double sx0 = 1.0, fx0 = 1.0;
+    if constexpr ((MODE & kScaleSrc) != 0) {
+        const auto rxs = buf(X.S, X.R), rxf = buf(X.F, X.R);
+        sx0 = bload(rxs, c0 < X.R ? (unsigned)c0 * 8u : kOOB);
+        fx0 = bload(rxf, c0 < X.R ? (unsigned)c0 * 8u : kOOB);
+    }
+    {
+        const auto rym = buf(Y.M, (size_t)Y.R * W), ryd = buf(Y.D, (size_t)Y.R * W);
+        const auto rys = buf(Y.S, Y.R), ryf = buf(Y.F, Y.R);
+        double cv[NCV];
+#pragma unroll
+        for (int c = 0; c < NCV; ++c) {
+            const int i = lane + 64 * c;
+            const int j = i / CW, k = i - j * CW;
+            const int yr = y0 + j;
+            const bool ok = i < TY * CW && yr < Y.R;
+            const unsigned om = ok && k < W ? (unsigned)(yr * W + k) * 8u : kOOB;
+            const unsigned od = ok && k >= W && k < 2 * W ? (unsigned)(yr * W + k - W) * 8u : kOOB;
+            const unsigned os = ok && k == 2 * W ? (unsigned)yr * 8u : kOOB;
+            const unsigned of = ok && k == 2 * W + 1 ? (unsigned)yr * 8u : kOOB;
+            cv[c] = bload(rym, om) + bload(ryd, od) + bload(rys, os) + bload(ryf, of);
+        }
+#pragma unroll
+        for (int c = 0; c < NCV; ++c) cy[lane + 64 * c] = cv[c];
+    }
+    const auto ru = buf(g.u, (size_t)Nx * Ny);
+    const int ch = lane < P ? x0 - P + lane : x0 + SW + lane - P;
+    const bool ok0 = c0 < Nx, okh = lane < 2 * P && ch >= 0 && ch < Nx;
+    double v0[NR], vh[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int yi = y0 - P + i;
+        const bool rowok = yi >= 0 && yi < Ny;
+        const unsigned rowoff = (unsigned)yi * (unsigned)Nx;
+        v0[i] = bload(ru, rowok && ok0 ? (rowoff + c0) * 8u : kOOB);
+        vh[i] = bload(ru, rowok && okh ? (rowoff + ch) * 8u : kOOB);
+    }
+    const int hidx = lane < P ? lane : (lane < 2 * P ? SW + lane : SW + 2 * P + (lane & 1));
+    const auto ro = buf(g.out, (size_t)X.R * Y.R);
+    const auto rm = buf(g.omass, (MODE & kMass) ? (size_t)X.R * Y.R : 0);
+    const auto rf = buf(g.farr, (MODE & kFarr) ? (size_t)X.R * Y.R : 0);
+    const bool okc0 = c0 < X.R;
+    double ra0[W], rb0[W];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        rb[i][P + lane] = v0[i];
+        rb[i][hidx] = vh[i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double t[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) t[q] = rb[i][lane + q];
+        double a0 = 0.0, b0 = 0.0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            a0 = fma(m0[k], t[k], a0);
+            b0 = fma(d0[k], t[k], b0);
+        }
+        ra0[i % W] = a0;
+        rb0[i % W] = b0;
+        if (i >= 2 * P) {
+            const int j = i - 2 * P;
+            const double* cr = &cy[j * CW];
+            double ms0 = 0.0, ly0 = 0.0, lx0 = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const double my = cr[k], dy = cr[W + k];
+                const int sl = (j + k) % W;
+                ms0 = fma(my, ra0[sl], ms0);
+                ly0 = fma(dy, ra0[sl], ly0);
+                lx0 = fma(my, rb0[sl], lx0);
+            }
+            const bool rowok = y0 + j < Y.R;
+            const unsigned o0 = rowok && okc0 ? (unsigned)((y0 + j) * X.R + c0) * 8u : kOOB;
+            if constexpr ((MODE & kMass) != 0) bstore<kStream>(rm, o0, ms0);
+            double w0 = fma(g.alpha, ms0, g.beta * (lx0 + ly0));
+            if constexpr ((MODE & kScaleSrc) != 0) w0 = fma(g.gsep, fx0 * cr[2 * W + 1], w0);
+            if constexpr ((MODE & kFarr) != 0) w0 = fma(g.garr, bload(rf, o0), w0);
+            if constexpr ((MODE & kScaleSrc) != 0) w0 *= sx0 * cr[2 * W];
+            bstore<kStream>(ro, o0, w0);
+        }
+    }
+}
+
+template <int P, int TY, int MODE>
+__global__ __launch_bounds__(64) void apply2d1_kernel(ApplyArgs g, TileGrid tg)
+{
+    __shared__ __attribute__((aligned(16))) double lds[Chunk2D1<P, TY>::LDS];
+    const int L = tg.TZ == 2 ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, tg.nblk);
+    const int bx = tg.TZ == 1 ? L / tg.ty : L % tg.tx;
+    const int by = tg.TZ == 1 ? L % tg.ty : L / tg.tx;
+    apply2d_chunk1<P, TY, MODE>(g, bx, by, lds);
+}
+
 template <int P, int TY, int MODE, bool VEC>
 __global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
 {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -102,6 +103,7 @@ struct iga_ctx {
     // tile configuration
     int ty2d = 8;
     int order2d = 0;
+    int strip2d = 128;   // 2D strip width: 128 (two columns per lane) or 64 (one)
     int tz3d = 0;   // 3D planes per z-chunk, 0 = automatic
     int ty3d = 0;   // 3D rows per tile, 0 = automatic
     int tx3d = 0;   // 3D columns per tile, 0 = automatic
@@ -248,16 +250,18 @@ ApplyArgs make_args(const iga_ctx* c, int form, bool step, bool sep_source)
 }
 
 template <int P, int TY, int MODE>
-void launch_2d(const ApplyArgs& g, hipStream_t s, int order)
+void launch_2d(const ApplyArgs& g, hipStream_t s, int order, int strip)
 {
     TileGrid tg;
-    tg.tx = (g.ax[0].R + 127) / 128;
+    tg.tx = (g.ax[0].R + strip - 1) / strip;
     tg.ty = (g.ax[1].R + TY - 1) / TY;
     tg.tz = 1;
     tg.TZ = order;
     tg.nblk = tg.tx * tg.ty;
+    if (strip == 64)
+        hipLaunchKernelGGL((iga::apply2d1_kernel<P, TY, MODE>), dim3(tg.nblk), dim3(64), 0, s, g, tg);
     // 128-bit row accesses when every row of u and of the rows starts 16-byte aligned
-    if (g.ax[0].N % 2 == 0 && g.ax[0].R % 2 == 0)
+    else if (g.ax[0].N % 2 == 0 && g.ax[0].R % 2 == 0)
         hipLaunchKernelGGL((iga::apply2d_kernel<P, TY, MODE, true>), dim3(tg.nblk), dim3(64), 0, s, g,
                            tg);
     else
@@ -346,13 +350,13 @@ void launch_apply_pm(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
         hipLaunchKernelGGL((iga::apply1d_kernel<P, MODE>), dim3(grid), dim3(kBlock), 0, s, g);
     } else if (c->dim == 2) {
         if (c->ty2d == 2)
-            launch_2d<P, 2, MODE>(g, s, c->order2d);
+            launch_2d<P, 2, MODE>(g, s, c->order2d, c->strip2d);
         else if (c->ty2d == 8)
-            launch_2d<P, 8, MODE>(g, s, c->order2d);
+            launch_2d<P, 8, MODE>(g, s, c->order2d, c->strip2d);
         else if (c->ty2d == 16)
-            launch_2d<P, 16, MODE>(g, s, c->order2d);
+            launch_2d<P, 16, MODE>(g, s, c->order2d, c->strip2d);
         else
-            launch_2d<P, 4, MODE>(g, s, c->order2d);
+            launch_2d<P, 4, MODE>(g, s, c->order2d, c->strip2d);
     } else {
         launch_3d<P, MODE>(c, g, s);
     }
@@ -1328,6 +1332,67 @@ int launch_solve(iga_ctx* c, const double* b, double* x, hipStream_t s, bool pg 
 
 }  // namespace
 
+namespace {
+
+// Tile settings the autotuner chose, per (dim, p, span kind, bit length of each axis'
+// row count), for contexts created later.
+struct TuneCache {
+    std::mutex mu;
+    std::map<std::array<int, 6>, std::array<int, 6>> best;   // ty2d, order2d, strip2d, tz3d, ty3d, tx3d
+};
+TuneCache g_tune;
+
+int bit_length(int v)
+{
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+std::array<int, 6> tune_key(const iga_ctx* c)
+{
+    return {c->dim, c->p, c->spans, bit_length(c->R[0]), c->dim > 1 ? bit_length(c->R[1]) : 0,
+            c->dim > 2 ? bit_length(c->R[2]) : 0};
+}
+
+void tune_apply(iga_ctx* c, const std::array<int, 6>& v)
+{
+    c->ty2d = v[0];
+    c->order2d = v[1];
+    c->strip2d = v[2];
+    c->tz3d = v[3];
+    c->ty3d = v[4];
+    c->tx3d = v[5];
+}
+
+// The candidate settings of a dimension (the order of the header's list).
+std::vector<std::array<int, 6>> tune_candidates(const iga_ctx* c)
+{
+    std::vector<std::array<int, 6>> v;
+    if (c->dim == 2) {
+        for (int strip : {128, 64})
+            for (int ty : {4, 8, 16})
+                for (int order : {0, 1}) v.push_back({ty, order, strip, c->tz3d, c->ty3d, c->tx3d});
+    } else if (c->dim == 3) {
+        for (int tz : {0, 6, 12})
+            for (int ty : {0, 8})
+                for (int tx : {0, 32}) v.push_back({c->ty2d, c->order2d, c->strip2d, tz, ty, tx});
+    }
+    return v;
+}
+
+// A deterministic, bounded coefficient pattern for timing.
+__global__ void tune_fill_kernel(double* u, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        u[i] = (double)((i * 2654435761u) % 1997u) / 1997.0 - 0.5;
+}
+
+}  // namespace
+
 extern "C" {
 
 int iga_copy_probe(const double* src, double* dst_a, double* dst_b, size_t n, void* hip_stream)
@@ -1476,6 +1541,11 @@ int iga_create(const iga_mesh_desc* desc, void* hip_stream, iga_ctx** out)
         iga_destroy(c);
         return rc;
     }
+    {   // a setting the autotuner chose for contexts like this one
+        std::lock_guard<std::mutex> lock(g_tune.mu);
+        auto it = g_tune.best.find(tune_key(c));
+        if (it != g_tune.best.end()) tune_apply(c, it->second);
+    }
     *out = c;
     return IGA_OK;
 }
@@ -1531,6 +1601,10 @@ int iga_set_tile(iga_ctx* c, int32_t key, int32_t value)
         if (value != 0 && (value < 8 || value > 96 || (value & 1))) return IGA_E_INVAL;
         c->tx3d = value;
         break;
+    case IGA_TILE_2D_STRIP:
+        if (value != 64 && value != 128) return IGA_E_INVAL;
+        c->strip2d = value;
+        break;
     default:
         return IGA_E_INVAL;
     }
@@ -1547,8 +1621,79 @@ int iga_get_tile(const iga_ctx* c, int32_t key, int32_t* value)
     case IGA_TILE_3D_PLANES: *value = c->tz3d; break;
     case IGA_TILE_3D_ROWS: *value = c->ty3d; break;
     case IGA_TILE_3D_COLS: *value = c->tx3d; break;
+    case IGA_TILE_2D_STRIP: *value = c->strip2d; break;
     default: return IGA_E_INVAL;
     }
+    return IGA_OK;
+}
+
+int iga_autotune(iga_ctx* c, int32_t op, int32_t reps, float* times_us, int32_t* ntimed)
+{
+    if (ntimed) *ntimed = 0;
+    if (!c || reps < 1 || (op != IGA_TUNE_APPLY && op != IGA_TUNE_STEP) || capturing(c)) return IGA_E_INVAL;
+    if (op == IGA_TUNE_STEP && c->spans != IGA_SPANS_SUPPORT) return IGA_E_INVAL;
+    const std::vector<std::array<int, 6>> cand = tune_candidates(c);
+    if (cand.empty()) return IGA_OK;
+    const size_t n = prod3(c->N), nr = nrows(c, IGA_PG);
+    double* buf = nullptr;
+    const size_t total = n + 2 * std::max(n, nr);
+    IGA_HIP(hipMallocAsync((void**)&buf, total * sizeof(double), c->stream));
+    const std::array<int, 6> keep = {c->ty2d, c->order2d, c->strip2d, c->tz3d, c->ty3d, c->tx3d};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = IGA_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = IGA_E_DEVICE;
+    if (rc == IGA_OK)
+        hipLaunchKernelGGL(tune_fill_kernel, dim3(256), dim3(kBlock), 0, c->stream, buf, total);
+    ApplyArgs g;
+    if (op == IGA_TUNE_APPLY) {
+        g = make_args(c, IGA_PG, false, false);
+        g.u = buf;
+        g.out = buf + n;
+        g.omass = buf + n + std::max(n, nr);
+        g.alpha = 0.0;
+        g.beta = 1.0;
+    } else {
+        g = make_args(c, IGA_PG, true, true);
+        g.u = buf;
+        g.out = buf + n;
+        g.alpha = 1.0;
+        g.beta = 1e-9;
+        g.gsep = 1e-9;
+    }
+    float best = 1e30f;
+    std::array<int, 6> pick = keep;
+    for (size_t k = 0; k < cand.size() && rc == IGA_OK; ++k) {
+        tune_apply(c, cand[k]);
+        for (int w = 0; w < 2 && rc == IGA_OK; ++w) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
+        if (rc != IGA_OK) break;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) rc = IGA_E_DEVICE;
+        for (int r = 0; r < reps && rc == IGA_OK; ++r) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
+        float ms = 0.0f;
+        if (rc == IGA_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = IGA_E_DEVICE;
+        if (rc != IGA_OK) break;
+        const float us = ms * 1000.0f / (float)reps;
+        if (times_us && k < IGA_TUNE_MAX) times_us[k] = us;
+        if (us < best) {
+            best = us;
+            pick = cand[k];
+        }
+    }
+    (void)hipFreeAsync(buf, c->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != IGA_OK) {
+        tune_apply(c, keep);
+        return rc;
+    }
+    tune_apply(c, pick);
+    free_graph(c);
+    {
+        std::lock_guard<std::mutex> lock(g_tune.mu);
+        g_tune.best[tune_key(c)] = pick;
+    }
+    if (ntimed) *ntimed = (int32_t)std::min<size_t>(cand.size(), IGA_TUNE_MAX);
     return IGA_OK;
 }
 

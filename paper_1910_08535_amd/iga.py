@@ -24,7 +24,9 @@ NOALLOC_MAX_DOUBLES = 1 << 23   # coefficients iga_explicit_step_noalloc takes a
 GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM, SPANS_REFINED = 0, 1, 2, 3
-TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_ROWS, TILE_2D_ORDER, TILE_3D_COLS = 1, 2, 4, 5, 6
+TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_ROWS, TILE_2D_ORDER, TILE_3D_COLS, TILE_2D_STRIP = 1, 2, 4, 5, 6, 7
+TUNE_APPLY, TUNE_STEP, TUNE_MAX = 0, 1, 16
+TILE_KEYS = {2: (TILE_2D_STRIP, TILE_2D_ROWS, TILE_2D_ORDER), 3: (TILE_3D_PLANES, TILE_3D_ROWS, TILE_3D_COLS)}
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 _P64 = C.POINTER(C.c_int64)
@@ -89,6 +91,7 @@ _SIGS = {
     "iga_copy_probe": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
     "iga_set_tile": [C.c_void_p, C.c_int32, C.c_int32],
     "iga_get_tile": [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)],
+    "iga_autotune": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)],
     "iga_batch_create": [C.c_void_p, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
     "iga_batch_submit": [C.c_void_p, C.POINTER(Job), C.c_int32, C.POINTER(C.c_uint64)],
     "iga_batch_flush": [C.c_void_p],
@@ -220,6 +223,15 @@ def iga_set_tile(h, key: int, value: int) -> None:
     _check(lib().iga_set_tile(h, key, value), "iga_set_tile")
 
 
+def iga_autotune(h, op: int, reps: int):
+    """Times the candidate tiles (the list of include/iga.h); returns their microseconds."""
+    import numpy as np
+    times = np.zeros(TUNE_MAX, dtype=np.float32)
+    n = C.c_int32(0)
+    _check(lib().iga_autotune(h, op, reps, times.ctypes.data, C.byref(n)), "iga_autotune")
+    return times[: n.value].copy()
+
+
 def iga_get_tile(h, key: int) -> int:
     v = C.c_int32()
     _check(lib().iga_get_tile(h, key, C.byref(v)), "iga_get_tile")
@@ -307,6 +319,18 @@ class Mesh:
 
     def get_tile(self, key: int) -> int:
         return iga_get_tile(self.h, key)
+
+    def tile(self) -> dict:
+        """The context's tile setting (the keys its dimension uses)."""
+        names = {TILE_2D_STRIP: "strip", TILE_2D_ROWS: "rows", TILE_2D_ORDER: "order",
+                 TILE_3D_PLANES: "planes", TILE_3D_ROWS: "rows", TILE_3D_COLS: "cols"}
+        return {names[k]: self.get_tile(k) for k in TILE_KEYS.get(self.dim, ())}
+
+    def autotune(self, op: int = TUNE_APPLY, reps: int = 20):
+        """Picks the fastest candidate tile for op (TUNE_APPLY or TUNE_STEP) and keeps it for
+        this context and later ones of the same size class; returns the candidates'
+        microseconds per launch."""
+        return iga_autotune(self.h, op, reps)
 
     def shape(self, form: int) -> Tuple[int, ...]:
         rows, _ = iga_shape(self.h, form)

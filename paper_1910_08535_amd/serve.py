@@ -23,6 +23,7 @@ Results do not depend on the mix: a request gives the bits it gives alone on a c
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from dataclasses import dataclass
 from typing import Dict, List, Tuple
@@ -236,17 +237,25 @@ class Server:
         for rec, a in zip(records, arrive):
             rec.t_arrive = start + a
         nxt = 0
-        t0 = time.perf_counter()
-        while len(self.done) < total:
-            now = time.perf_counter() - t0
-            end = nxt
-            while end < len(order) and arrive[end] <= now:
-                end += 1
-            if end > nxt:
-                self._submit(recs[nxt:end], records[nxt:end])
-                nxt = end
-            self._progress()
-        wall = time.perf_counter() - t0
+        # no collector passes inside the loop: with many live objects one pass takes
+        # milliseconds, which would show up as request latency
+        collect = gc.isenabled()
+        gc.disable()
+        try:
+            t0 = time.perf_counter()
+            while len(self.done) < total:
+                now = time.perf_counter() - t0
+                end = nxt
+                while end < len(order) and arrive[end] <= now:
+                    end += 1
+                if end > nxt:
+                    self._submit(recs[nxt:end], records[nxt:end])
+                    nxt = end
+                self._progress()
+            wall = time.perf_counter() - t0
+        finally:
+            if collect:
+                gc.enable()
         return self.summary(wall)
 
     def summary(self, wall: float) -> Dict[str, float]:
