@@ -141,8 +141,15 @@ def run_c2(args):
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     mesh = iga.Mesh(2, c.p, c.ne, c.nq, stream=stream)
-    # the library's autotuner picks the tile (strip width, chunk rows, chunk order)
-    tune_us = mesh.autotune(iga.TUNE_APPLY, reps=20)
+    # the library's autotuner picks the tile (strip width, chunk rows, chunk order), unless
+    # --tile2d fixes it (profiling runs: a profiler's own overhead can reorder the
+    # candidates, so the profiled run is given the choice of the unprofiled one)
+    tune_us = []
+    if args.tile2d:
+        for key, v in zip((iga.TILE_2D_STRIP, iga.TILE_2D_ROWS, iga.TILE_2D_ORDER), args.tile2d.split(",")):
+            mesh.set_tile(key, int(v))
+    else:
+        tune_us = mesh.autotune(iga.TUNE_APPLY, reps=20)
     tile = mesh.tile()
     kernel = (f"iga::apply2d_kernel<2, {tile['rows']}, 3, true>" if tile["strip"] == 128
               else f"iga::apply2d1_kernel<2, {tile['rows']}, 3>")
@@ -231,7 +238,7 @@ def run_c2(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": kernel, "tile": tile,
+                     "kernel": kernel, "tile": tile, "tile_source": "fixed" if args.tile2d else "autotuned",
                      "tile_candidates_us": [round(float(t), 3) for t in tune_us],
                      "algorithmic_bytes_per_launch": BYTES_C2,
                      "avg_launch_us": per_launch_s * 1e6},
@@ -262,9 +269,16 @@ def run_c3(args) -> dict:
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     mesh = iga.Mesh(3, c.p, c.ne, c.nq, stream=stream)
-    # the library's autotuner picks the tile (z-chunk planes, tile rows and columns); the
-    # 16 meshes of the rotated run below start from the same choice
-    tune_us = mesh.autotune(iga.TUNE_STEP, reps=20)
+    # the library's autotuner picks the tile (z-chunk planes, tile rows and columns), unless
+    # --tile3d fixes it; the 16 meshes of the rotated run below take the same setting
+    tune_us = []
+    if args.tile3d:
+        tkeys = (iga.TILE_3D_PLANES, iga.TILE_3D_ROWS, iga.TILE_3D_COLS)
+        tvals = [int(v) for v in args.tile3d.split(",")]
+        for key, v in zip(tkeys, tvals):
+            mesh.set_tile(key, v)
+    else:
+        tune_us = mesh.autotune(iga.TUNE_STEP, reps=20)
     tile = mesh.tile()
     u0 = torch.from_numpy(c.coefs()).to("cuda")
     u = u0.clone()
@@ -283,6 +297,10 @@ def run_c3(args) -> dict:
     # own cached 2-step graph; u and the work buffer ping-pong, no copy)
     nprob = 16
     meshes = [iga.Mesh(3, c.p, c.ne, c.nq, stream=stream) for _ in range(nprob)]
+    if args.tile3d:
+        for m in meshes:
+            for key, v in zip(tkeys, tvals):
+                m.set_tile(key, v)
     us = [u0.clone() for _ in range(nprob)]
     for _ in range(2):
         for m, x in zip(meshes, us):
@@ -316,6 +334,7 @@ def run_c3(args) -> dict:
                          "unit": "GB/s", "frac": bytes_step / rot_s / (HBM_PEAK_GBS * 1e9),
                          "traffic": measured_traffic("heat3d_p3_128"),
                          "kernel": "iga::apply3d_kernel<3, 9>", "tile": tile,
+                         "tile_source": "fixed" if args.tile3d else "autotuned",
                          "tile_candidates_us": [round(float(t), 3) for t in tune_us],
                          "algorithmic_bytes_per_launch": bytes_step, "avg_launch_us": rot_s * 1e6}}
 
@@ -634,6 +653,10 @@ def main():
     ap.add_argument("--ads-reps", type=int, default=10)
     ap.add_argument("--no-laplace", action="store_true", help="skip the mixed Laplace leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--tile2d", default="",
+                    help="STRIP,ROWS,ORDER: fix the 2D tile instead of autotuning it")
+    ap.add_argument("--tile3d", default="",
+                    help="PLANES,ROWS,COLS: fix the 3D tile instead of autotuning it")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter scaling)")
     args = ap.parse_args()

@@ -1660,26 +1660,32 @@ int iga_autotune(iga_ctx* c, int32_t op, int32_t reps, float* times_us, int32_t*
         g.beta = 1e-9;
         g.gsep = 1e-9;
     }
-    float best = 1e30f;
-    std::array<int, 6> pick = keep;
-    for (size_t k = 0; k < cand.size() && rc == IGA_OK; ++k) {
-        tune_apply(c, cand[k]);
-        for (int w = 0; w < 2 && rc == IGA_OK; ++w) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
-        if (rc != IGA_OK) break;
-        if (hipEventRecord(e0, c->stream) != hipSuccess) rc = IGA_E_DEVICE;
-        for (int r = 0; r < reps && rc == IGA_OK; ++r) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
-        float ms = 0.0f;
-        if (rc == IGA_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            rc = IGA_E_DEVICE;
-        if (rc != IGA_OK) break;
-        const float us = ms * 1000.0f / (float)reps;
-        if (times_us && k < IGA_TUNE_MAX) times_us[k] = us;
-        if (us < best) {
-            best = us;
-            pick = cand[k];
+    // two rounds over the candidates, each candidate's best round counts
+    std::vector<float> t(cand.size(), 1e30f);
+    for (int round = 0; round < 2 && rc == IGA_OK; ++round) {
+        for (size_t k = 0; k < cand.size() && rc == IGA_OK; ++k) {
+            tune_apply(c, cand[k]);
+            for (int w = 0; w < 2 && rc == IGA_OK; ++w) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
+            if (rc != IGA_OK) break;
+            if (hipEventRecord(e0, c->stream) != hipSuccess) rc = IGA_E_DEVICE;
+            for (int r = 0; r < reps && rc == IGA_OK; ++r) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
+            float ms = 0.0f;
+            if (rc == IGA_OK &&
+                (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = IGA_E_DEVICE;
+            if (rc == IGA_OK) t[k] = std::min(t[k], ms * 1000.0f / (float)reps);
         }
     }
+    // the fastest candidate, unless the setting the context had is within 3% of it
+    size_t kb = 0;
+    for (size_t k = 1; k < cand.size(); ++k)
+        if (t[k] < t[kb]) kb = k;
+    std::array<int, 6> pick = cand[kb];
+    for (size_t k = 0; k < cand.size(); ++k)
+        if (cand[k] == keep && t[k] <= 1.03f * t[kb]) pick = keep;
+    if (times_us)
+        for (size_t k = 0; k < cand.size() && k < IGA_TUNE_MAX; ++k) times_us[k] = t[k];
     (void)hipFreeAsync(buf, c->stream);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

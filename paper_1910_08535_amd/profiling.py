@@ -3,6 +3,8 @@
 Used by hand after a profiling run:
 
     python -m paper_1910_08535_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
+        [<per launch shape csv>]
+    python -m paper_1910_08535_amd.profiling grid <kernel_trace.csv> <per launch shape csv>
     python -m paper_1910_08535_amd.profiling traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> <kernel substring> <copy MiB> <workload> "<commands>"
     python -m paper_1910_08535_amd.profiling pmc <out.md> <kernel substring> "<commands>"
@@ -44,7 +46,9 @@ def kernel_source_hash(kernel: str = "apply2d") -> str:
     return h.hexdigest()[:16]
 
 
-def stats_markdown(stats_csv: str, out_md: str, command: str) -> None:
+def stats_markdown(stats_csv: str, out_md: str, command: str, grid_csv: str = "") -> None:
+    """rocprofv3 --stats summary; grid_csv (optional): per (kernel, grid size) call counts
+    and average durations from the same run's kernel trace."""
     rows = list(csv.DictReader(open(stats_csv)))
     lines = ["# rocprofv3 kernel statistics", "", "Command (from the repository root, after "
              "`cd /tmp && export TMPDIR=/tmp` as the profiler needs):", "", "```", command, "```",
@@ -55,10 +59,33 @@ def stats_markdown(stats_csv: str, out_md: str, command: str) -> None:
                      f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
                      f"{float(r['Percentage']):.1f}% |")
     lines.append("")
+    if grid_csv:
+        lines += ["Per launch shape (grid size in threads), from the same run's kernel trace:", "",
+                  "| kernel | grid | calls | average (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
+        for r in csv.DictReader(open(grid_csv)):
+            lines.append(f"| `{r['kernel'][:90]}` | {r['grid']} | {r['calls']} | "
+                         f"{float(r['average_ns']) / 1e3:.3f} | {float(r['min_ns']) / 1e3:.3f} | "
+                         f"{float(r['max_ns']) / 1e3:.3f} |")
+        lines.append("")
     for k in KERNEL_SOURCES:
         lines.append(f"Sources hash of {k} ({', '.join(KERNEL_SOURCES[k])}): `{kernel_source_hash(k)}`")
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+
+def grid_table(trace_csv: str, out_csv: str, keep=("apply2d", "apply3d", "batch2d", "copy2_kernel", "serve")) -> None:
+    """Per (kernel, grid size) call counts and durations of a rocprofv3 --kernel-trace CSV,
+    for the kernels whose names contain one of `keep`, largest total time first."""
+    d = {}
+    for r in csv.DictReader(open(trace_csv)):
+        if any(k in r["Kernel_Name"] for k in keep):
+            g = r.get("Grid_Size", r.get("Grid_Size_X"))
+            d.setdefault((r["Kernel_Name"], g), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    with open(out_csv, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["kernel", "grid", "calls", "average_ns", "min_ns", "max_ns"])
+        for (n, g), v in sorted(d.items(), key=lambda x: -sum(x[1])):
+            w.writerow([n, g, len(v), sum(v) / len(v), min(v), max(v)])
 
 
 def _per_dispatch(csv_path: str, counter: str, grid: str = ""):
@@ -81,8 +108,10 @@ def _family(kernel: str) -> str:
 def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, workload: str,
             commands: str) -> dict:
     """HBM bytes per launch of `kernel` ("name" or "name@grid size", the grid size in
-    threads picking one launch shape of a kernel that runs at several)."""
+    threads picking one launch shape of a kernel that runs at several; without one, the
+    shape most dispatches have)."""
     kernel, _, grid = kernel.partition("@")
+    grid = grid or _common_grid([fetch_csv], kernel)
     fetch_all = _per_dispatch(fetch_csv, "FETCH_SIZE")
     write_all = _per_dispatch(write_csv, "WRITE_SIZE")
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE", grid)
@@ -104,7 +133,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, worklo
     kw, wv = pick(write, kernel)
     fb = statistics.median(fv) * 1024.0 * f_scale
     wb = statistics.median(wv) * 1024.0 * w_scale
-    rec = {"workload": workload, "kernel": kf, "grid_size": grid or None, "dispatches": [len(fv), len(wv)],
+    rec = {"workload": workload, "kernel": kf, "grid_size": grid, "dispatches": [len(fv), len(wv)],
            "fetch_kib_per_dispatch_median": statistics.median(fv),
            "write_kib_per_dispatch_median": statistics.median(wv),
            "copy_probe_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
@@ -131,14 +160,29 @@ _RATIOS = (
 )
 
 
+def _common_grid(csvs, kernel: str) -> str:
+    """The grid size (threads) most dispatches of the kernels matching `kernel` have."""
+    seen = {}
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            if kernel in r["Kernel_Name"]:
+                seen.setdefault(r["Grid_Size"], set()).add(r["Dispatch_Id"])
+    if not seen:
+        raise SystemExit(f"no dispatch of a kernel matching {kernel!r}")
+    return max(seen, key=lambda g: len(seen[g]))
+
+
 def pmc_markdown(out_md: str, kernel: str, command: str, csvs) -> dict:
     """Median per dispatch of every counter collected for the kernels matching `kernel`
-    (rocprofv3 --pmc CSV files, one per pass), and the ratios above."""
+    ("name" or "name@grid size"; without a grid size, the launch shape most dispatches
+    have) in rocprofv3 --pmc CSV files (one per pass), and the ratios above."""
+    kernel, _, grid = kernel.partition("@")
+    grid = grid or _common_grid(csvs, kernel)
     vals = {}
     name = None
     for path in csvs:
         for r in csv.DictReader(open(path)):
-            if kernel not in r["Kernel_Name"]:
+            if kernel not in r["Kernel_Name"] or r["Grid_Size"] != grid:
                 continue
             name = r["Kernel_Name"]
             vals.setdefault(r["Counter_Name"], {}).setdefault(r["Dispatch_Id"], 0.0)
@@ -146,7 +190,7 @@ def pmc_markdown(out_md: str, kernel: str, command: str, csvs) -> dict:
     if not vals:
         raise SystemExit(f"no dispatch of a kernel matching {kernel!r}")
     med = {c: statistics.median(d.values()) for c, d in vals.items()}
-    lines = ["# rocprofv3 counters", "", f"Kernel: `{name}`", "",
+    lines = ["# rocprofv3 counters", "", f"Kernel: `{name}`, grid of {grid} threads", "",
              "Commands (from the repository root, after `cd /tmp && export TMPDIR=/tmp` as the "
              "profiler needs), one per pass:", "", "```", command, "```", "",
              "| counter | median per dispatch | dispatches |", "|---|---|---|"]
@@ -171,7 +215,9 @@ if __name__ == "__main__":
     if sys.argv[1] == "pmc":
         print(json.dumps(pmc_markdown(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:]), indent=1))
     elif sys.argv[1] == "stats":
-        stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
+        stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else "")
+    elif sys.argv[1] == "grid":
+        grid_table(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),
                                  sys.argv[6], sys.argv[7]), indent=1))

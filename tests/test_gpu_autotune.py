@@ -55,10 +55,14 @@ def test_every_candidate_same_bits(iga, dim, p, ne):
 @pytest.mark.parametrize("dim,p,ne,op", [(2, 2, (200, 180), 0), (3, 3, (24, 20, 22), 1)])
 def test_tuner_keeps_fastest_and_remembers(iga, dim, p, ne, op):
     mesh = iga.Mesh(dim, p, ne, (p + 1,) * dim)
+    before = {k: mesh.get_tile(k) for k in _candidates(iga, dim)[0]}
     times = mesh.autotune(op, reps=5)
     cands = _candidates(iga, dim)
     assert len(times) == len(cands) and np.all(times > 0)
-    best = cands[int(np.argmin(times))]
+    fastest = int(np.argmin(times))
+    kept = cands.index(before)
+    # the fastest candidate, or the setting the context had when within 3% of it
+    best = cands[kept] if times[kept] <= 1.03 * times[fastest] else cands[fastest]
     assert all(mesh.get_tile(k) == v for k, v in best.items())
     # same size class (bit length of every axis' row count): the tuned setting carries over
     other = iga.Mesh(dim, p, tuple(n + 1 for n in ne), (p + 1,) * dim)
