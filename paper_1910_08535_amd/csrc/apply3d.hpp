@@ -20,8 +20,10 @@
 //     keeping lanes on distinct banks) and one x task (two output columns of one row, from
 //     128-bit reads of a stage Y row, stored with one 16-byte access); the tasks are fixed
 //     per thread for the whole chunk, so their addresses are computed once;
-//   * tasks of interior rows (columns) come first, padded to whole waves, so that each
-//     wave takes one branch of the tap choice; interior taps are read with uniform
+//   * y tasks are numbered from the first wave up and x tasks from the last wave down, so
+//     that the waves holding both are few; within each kind, tasks of interior rows
+//     (columns) come first, padded to whole waves, so that each wave takes one branch of
+//     the tap choice; interior taps are read with uniform
 //     (scalar) loads, the rows at the ends of an axis read their own taps, staged in LDS
 //     once per workgroup.  Taps of the z pass are uniform per plane;
 //   * each step issues the same memory operations in every thread (the ring prefetch and
@@ -289,15 +291,16 @@ __device__ __forceinline__ void apply3d_tile(const ApplyArgs& g, const Plan3D& p
     const int nXI = TYv * nI, nXIp = (nXI + 63) & ~63, nXB = TYv * nB;
     bool xv, xint;
     int xr, xi;
-    if (tid < nXIp) {
+    const int xid = kMaxNT3 - 1 - tid;   // x tasks from the last wave down, y tasks from the first up
+    if (xid < nXIp) {
         xint = true;
-        xv = tid < nXI;
-        const int t = xv ? tid : 0;
+        xv = xid < nXI;
+        const int t = xv ? xid : 0;
         xr = nI > 0 ? t / nI : 0;
         xi = ia + (t - xr * nI);
     } else {
         xint = false;
-        const int t0 = tid - nXIp;
+        const int t0 = xid - nXIp;
         xv = t0 < nXB;
         const int t = xv ? t0 : 0;
         xr = nB > 0 ? t / nB : 0;
