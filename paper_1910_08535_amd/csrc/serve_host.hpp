@@ -89,6 +89,11 @@ struct iga_server {
     };
     Slot slot[2];
     hipStream_t bstream = nullptr;
+    // memory of batched jobs: a pool of the server's own (kept, not released), so that its
+    // allocations never wait on memory that other streams freed into the device's default
+    // pool (with the default pool, the real-time p99 rose from 1.3 to 5 ms after a
+    // workload that had freed large buffers on other streams)
+    hipMemPool_t pool = nullptr;
     // the kinds of job of an iteration (1D, 2D, 3D) run side by side on streams of their
     // own, forked from and joined back into bstream
     hipStream_t fstream[3] = {nullptr, nullptr, nullptr};
@@ -338,7 +343,7 @@ int server_iterate(iga_server* s)
     int blk = -1;
     if (total > 0) {
         void* mem = nullptr;
-        if (hipMallocAsync(&mem, total, s->bstream) != hipSuccess) {
+        if (hipMallocFromPoolAsync(&mem, total, s->pool, s->bstream) != hipSuccess) {
             (void)hipGetLastError();
             for (auto it : s->fresh) server_finish_job(s, it, IGA_JOB_FAILED, -1);
             s->fresh.clear();
@@ -679,6 +684,18 @@ int iga_server_create(int32_t nstreams, size_t mem_budget_bytes, size_t cache_by
     }
     s->inflight.resize(s->streams.size());
     ok = ok && hipStreamCreateWithFlags(&s->bstream, hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        int dev = 0;
+        hipMemPoolProps props;
+        std::memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        ok = hipGetDevice(&dev) == hipSuccess;
+        props.location.id = dev;
+        ok = ok && hipMemPoolCreate(&s->pool, &props) == hipSuccess;
+        uint64_t keep = UINT64_MAX;
+        ok = ok && hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess;
+    }
     for (auto& sl : s->slot) ok = ok && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&s->fork, hipEventDisableTiming) == hipSuccess;
     for (int f = 0; f < 3; ++f)
@@ -789,6 +806,7 @@ int iga_server_destroy(iga_server* s)
     if (s->bstream) (void)hipStreamSynchronize(s->bstream);
     for (auto& sl : s->slot)
         if (sl.host) (void)hipHostFree(sl.host);
+    if (s->pool) (void)hipMemPoolDestroy(s->pool);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->bstream) (void)hipStreamDestroy(s->bstream);
     for (int f = 0; f < 3; ++f) {
