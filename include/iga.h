@@ -317,7 +317,9 @@ int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);
    hot kernel of op -- IGA_TUNE_APPLY: the fused PG apply (mass and Laplacian rows, as
    iga_apply); IGA_TUNE_STEP: one lumped explicit step with a sine source (as
    iga_explicit_step) -- with reps >= 1 launches each after two warm-up launches, on
-   buffers of its own, timed with HIP events on the context's stream (two rounds over the
+   buffers of its own (enough sets, used in turn, to exceed twice the 256 MB Infinity Cache,
+   at most 32: the launches read and write HBM), timed with HIP events on the context's
+   stream (two rounds over the
    candidates, the better round of each counting).  The fastest setting becomes the
    context's -- unless the setting the context had is a candidate within 3% of it, which
    then stays -- and the process remembers it: contexts created later with the

@@ -1635,8 +1635,12 @@ int iga_autotune(iga_ctx* c, int32_t op, int32_t reps, float* times_us, int32_t*
     const std::vector<std::array<int, 6>> cand = tune_candidates(c);
     if (cand.empty()) return IGA_OK;
     const size_t n = prod3(c->N), nr = nrows(c, IGA_PG);
+    // enough buffer sets, used in turn, that together they exceed the 256 MB Infinity Cache
+    // twice over: every timed launch then reads and writes HBM, as a large workload does
+    const size_t set = n + 2 * std::max(n, nr);
+    const size_t nsets = std::min<size_t>(32, std::max<size_t>(1, ((size_t)512 << 20) / (set * sizeof(double)) + 1));
+    const size_t total = set * nsets;
     double* buf = nullptr;
-    const size_t total = n + 2 * std::max(n, nr);
     IGA_HIP(hipMallocAsync((void**)&buf, total * sizeof(double), c->stream));
     const std::array<int, 6> keep = {c->ty2d, c->order2d, c->strip2d, c->tz3d, c->ty3d, c->tx3d};
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1647,28 +1651,32 @@ int iga_autotune(iga_ctx* c, int32_t op, int32_t reps, float* times_us, int32_t*
     ApplyArgs g;
     if (op == IGA_TUNE_APPLY) {
         g = make_args(c, IGA_PG, false, false);
-        g.u = buf;
-        g.out = buf + n;
-        g.omass = buf + n + std::max(n, nr);
         g.alpha = 0.0;
         g.beta = 1.0;
     } else {
         g = make_args(c, IGA_PG, true, true);
-        g.u = buf;
-        g.out = buf + n;
         g.alpha = 1.0;
         g.beta = 1e-9;
         g.gsep = 1e-9;
     }
+    // launch r works on buffer set r mod nsets
+    size_t next = 0;
+    auto launch = [&]() {
+        double* b = buf + (next++ % nsets) * set;
+        g.u = b;
+        g.out = b + n;
+        g.omass = op == IGA_TUNE_APPLY ? b + n + std::max(n, nr) : nullptr;
+        return launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
+    };
     // two rounds over the candidates, each candidate's best round counts
     std::vector<float> t(cand.size(), 1e30f);
     for (int round = 0; round < 2 && rc == IGA_OK; ++round) {
         for (size_t k = 0; k < cand.size() && rc == IGA_OK; ++k) {
             tune_apply(c, cand[k]);
-            for (int w = 0; w < 2 && rc == IGA_OK; ++w) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
+            for (int w = 0; w < 2 && rc == IGA_OK; ++w) rc = launch();
             if (rc != IGA_OK) break;
             if (hipEventRecord(e0, c->stream) != hipSuccess) rc = IGA_E_DEVICE;
-            for (int r = 0; r < reps && rc == IGA_OK; ++r) rc = launch_apply(c, g, c->stream, op == IGA_TUNE_STEP);
+            for (int r = 0; r < reps && rc == IGA_OK; ++r) rc = launch();
             float ms = 0.0f;
             if (rc == IGA_OK &&
                 (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
