@@ -7,28 +7,28 @@
 //
 // A workgroup owns an output tile of TX x TY rows of every plane of a z-chunk of TZ
 // planes and streams through the chunk plane by plane:
-//   * every thread owns fixed (x, y) points of the tile's input footprint (the tile plus
-//     p-wide halos, clipped to the array); their coefficients of the planes zo-p .. zo+p
-//     sit in a register ring (2p slots rotating, the newest plane in its own register), so
-//     each coefficient is loaded once per chunk and the z-halo planes cost loads only;
 //   * the three passes are software-pipelined over the planes: step k runs the z pass of
 //     plane k (registers -> LDS stage Z), the y pass of plane k-1 (stage Z -> stage Y) and
 //     the x pass of plane k-2 (stage Y -> memory), each stage double-buffered, so a plane
 //     costs ONE workgroup barrier and the work of three planes is in flight together;
-//   * every thread has at most one y task (two output rows of one footprint column, from
-//     the 2p + 2 values of that column: stage Z is stored by columns, an odd column stride
-//     keeping lanes on distinct banks) and one x task (two output columns of one row, from
-//     128-bit reads of a stage Y row, stored with one 16-byte access); the tasks are fixed
-//     per thread for the whole chunk, so their addresses are computed once;
-//   * y tasks are numbered from the first wave up and x tasks from the last wave down, so
-//     that the waves holding both are few; within each kind, tasks of interior rows
-//     (columns) come first, padded to whole waves, so that each wave takes one branch of
-//     the tap choice; interior taps are read with uniform
-//     (scalar) loads, the rows at the ends of an axis read their own taps, staged in LDS
-//     once per workgroup.  Taps of the z pass are uniform per plane;
-//   * each step issues the same memory operations in every thread (the ring prefetch and
-//     the x task's stores, out of the buffer's range where there is nothing to store), so
-//     the waits for the prefetched plane never have to drain the stores.
+//   * each wave has one role for the whole chunk (Roles3D): the first waves run the z
+//     pass, the next the y pass, the last the x pass, each role in a loop of its own with
+//     the same steps and barriers.  The passes of one step then run side by side on
+//     different waves instead of one after the other in every wave, each role keeps only
+//     its own registers live, and only the z waves load and only the x waves store;
+//   * a z thread owns fixed (x, y) points of the tile's input footprint (the tile plus
+//     p-wide halos, clipped to the array); their coefficients of the planes zo-p .. zo+p
+//     sit in a register ring (2p slots rotating, the newest plane in its own register), so
+//     each coefficient is loaded once per chunk and the z-halo planes cost loads only;
+//   * a y task is two output rows of one footprint column, from the 2p + 2 values of that
+//     column (stage Z is stored by columns, an odd column stride keeping lanes on distinct
+//     banks); an x task is two output columns of one row, from 128-bit reads of a stage Y
+//     row, stored with one 16-byte access.  A thread's tasks are fixed for the whole chunk,
+//     so their addresses are computed once;
+//   * tasks of interior rows (columns) come first, padded to whole waves, so that each
+//     wave takes one branch of the tap choice; interior taps are read with uniform
+//     (scalar) loads once per step, the rows at the ends of an axis read their own taps,
+//     staged in LDS once per workgroup.  Taps of the z pass are uniform per plane.
 // Without mass output the y pass folds the operator weights into one array,
 // B = alpha Y1 + beta Y2, so the x pass forms  alpha mass + beta lap = Mx B + beta Dx Y1
 // with two stencils instead of three.
@@ -51,11 +51,26 @@ struct Plan3D {
 constexpr int kRY3 = 2;        // output rows per y task
 constexpr int kMaxNT3 = 512;   // threads per workgroup, at most
 
-// footprint points per thread (z pass): the register ring holds (2p+1) x npz values
-__host__ __device__ constexpr int npz(int P)
-{
-    return P == 3 ? 2 : 3;
-}
+// Waves of a workgroup by role: the first WZ waves run the z pass (NZ footprint points per
+// thread), the next WY the y pass (up to NY tasks per thread), the last WX the x pass (up
+// to NX tasks per thread).  Sized so that each role carries about the same arithmetic
+// (for p = 3: 6 points x 14, 2 tasks x 42, 3 tasks x 28 FMAs per thread and step).
+template <int P>
+struct Roles3D {
+    static constexpr int WZ = 3, NZ = 6, WY = 3, NY = P == 3 ? 2 : 3, WX = 2, NX = P == 3 ? 3 : 4;
+    static_assert(WZ + WY + WX == kMaxNT3 / 64, "every wave has a role");
+};
+
+// Footprint points, y tasks and x tasks a workgroup can hold.
+template <int P>
+__host__ __device__ constexpr int z_cap3() { return Roles3D<P>::NZ * 64 * Roles3D<P>::WZ; }
+template <int P>
+__host__ __device__ constexpr int y_cap3() { return Roles3D<P>::NY * 64 * Roles3D<P>::WY; }
+template <int P>
+__host__ __device__ constexpr int x_cap3() { return Roles3D<P>::NX * 64 * Roles3D<P>::WX; }
+__host__ __device__ constexpr int z_cap3(int P) { return P == 3 ? z_cap3<3>() : z_cap3<2>(); }
+__host__ __device__ constexpr int y_cap3(int P) { return P == 3 ? y_cap3<3>() : y_cap3<2>(); }
+__host__ __device__ constexpr int x_cap3(int P) { return P == 3 ? x_cap3<3>() : x_cap3<2>(); }
 
 // LDS of a plan, in doubles: stage Z (two buffers of Z1 | Z2, LW columns of (LH | 1)),
 // stage Y (two buffers of A | B, TY rows of LS), then, staged once per workgroup, the band rows
@@ -191,8 +206,10 @@ __device__ __forceinline__ void xcol(const double (&a)[2 * P + 2], const double 
 template <int P, int MODE>
 __device__ __forceinline__ void apply3d_tile(const ApplyArgs& g, const Plan3D& pl, int L)
 {
+    using RL = Roles3D<P>;
     constexpr int W = 2 * P + 1;
-    constexpr int kNPZ = npz(P);
+    constexpr int NZ = RL::NZ, NY = RL::NY, NX = RL::NX;
+    constexpr int TZT = 64 * RL::WZ, TYT = 64 * RL::WY, TXT = 64 * RL::WX;   // threads per role
     constexpr bool kFold = (MODE & kMass) == 0;   // B = alpha Y1 + beta Y2
     extern __shared__ __attribute__((aligned(16))) double lds3[];
     const AxisOp &X = g.ax[0], &Y = g.ax[1], &Z = g.ax[2];
@@ -223,120 +240,49 @@ __device__ __forceinline__ void apply3d_tile(const ApplyArgs& g, const Plan3D& p
         sfy[i] = Y.S[y];
         sfy[pl.TY + i] = Y.F[y];
     }
-
-    // ---- footprint points of this thread (z pass): input columns xa..xb-1, rows ya..yb-1
-    const int NX = X.N, NYc = Y.N, NZ = Z.N;
-    const int xa = max(x0 - P, 0), xb = min(x1 + P, NX);
+    const int NX_ = X.N, NYc = Y.N, NZc = Z.N;
+    const int xa = max(x0 - P, 0), xb = min(x1 + P, NX_);
     const int ya = max(y0 - P, 0), yb = min(y1 + P, NYc);
     const int RW = xb - xa, npt = RW * (yb - ya);
     const int lc0 = xa - (x0 - P);   // stage column of input column xa
-    unsigned goff[kNPZ];
-    int loff[kNPZ];
-#pragma unroll
-    for (int i = 0; i < kNPZ; ++i) {
-        const int j = tid + i * kMaxNT3;
-        const int r = j / RW, cc = j - r * RW;
-        const bool ok = j < npt;
-        goff[i] = ok ? (unsigned)((ya + r) * NX + xa + cc) * 8u : kOOB;
-        loff[i] = ok ? (lc0 + cc) * LHc + (ya + r - (y0 - P)) : -1;
-    }
-    const size_t plane = (size_t)NX * NYc;
-    auto plane_buf = [&](int zi) {
-        const bool ok = zi >= 0 && zi < NZ && zi < z1 + P;
-        return buf(g.u + (ok ? (size_t)zi * plane : 0), ok ? plane : 0);
-    };
-
-    // ---- the y task of this thread: output rows 2q, 2q+1 of footprint column c; tasks of
-    // interior row pairs first, padded to whole waves, so that every wave takes one branch
     const int TYv = y1 - y0, TXv = x1 - x0, TZv = z1 - z0;
-    const int nqy = (TYv + 1) >> 1;
-    int qa = Y.ilo - y0;
-    qa = qa <= 0 ? 0 : (qa + 1) >> 1;                  // first pair with y0 + 2q >= ilo
-    int qb = Y.ihi - y0 - 1;
-    qb = qb < 0 ? 0 : (qb >> 1) + 1;                   // pairs with y0 + 2q + 1 <= ihi
-    qa = min(qa, nqy);
-    qb = min(max(qb, qa), nqy);
-    const int nYI = (qb - qa) * RW, nYIp = (nYI + 63) & ~63, nYB = (nqy - (qb - qa)) * RW;
-    bool yv, yint;
-    int yq, yc;
-    if (tid < nYIp) {
-        yint = true;
-        yv = tid < nYI;
-        const int t = yv ? tid : 0;
-        yq = qa + t / RW;
-        yc = t - (t / RW) * RW;
-    } else {
-        yint = false;
-        const int t0 = tid - nYIp;
-        yv = t0 < nYB;
-        const int t = yv ? t0 : 0;
-        const int j = t / RW;
-        yq = j < qa ? j : j + (qb - qa);
-        yc = t - j * RW;
-    }
-    const int ylc = lc0 + yc;
-    const int yrd = ylc * LHc + 2 * yq;                // stage offset of footprint row 2q
-    const bool ytwo = 2 * yq + 1 < TYv;
-
-    // ---- the x task of this thread: output columns 2i, 2i+1 of tile row r; interior
-    // pairs first, padded to whole waves
-    const int npx = (TXv + 1) >> 1;
-    int ia = X.ilo - x0;
-    ia = ia <= 0 ? 0 : (ia + 1) >> 1;
-    int ib = X.ihi - x0 - 1;
-    ib = ib < 0 ? 0 : (ib >> 1) + 1;
-    ia = min(ia, npx);
-    ib = min(max(ib, ia), npx);
-    const int nI = ib - ia, nB = npx - nI;
-    const int nXI = TYv * nI, nXIp = (nXI + 63) & ~63, nXB = TYv * nB;
-    bool xv, xint;
-    int xr, xi;
-    const int xid = kMaxNT3 - 1 - tid;   // x tasks from the last wave down, y tasks from the first up
-    if (xid < nXIp) {
-        xint = true;
-        xv = xid < nXI;
-        const int t = xv ? xid : 0;
-        xr = nI > 0 ? t / nI : 0;
-        xi = ia + (t - xr * nI);
-    } else {
-        xint = false;
-        const int t0 = xid - nXIp;
-        xv = t0 < nXB;
-        const int t = xv ? t0 : 0;
-        xr = nB > 0 ? t / nB : 0;
-        const int j = t - xr * nB;
-        xi = j < ia ? j : j + nI;
-    }
-    xi = min(xi, npx - 1);
-    const int xrd = xr * LS + 2 * xi;                  // stage offset of the task's first input
-    const int gx = x0 + 2 * xi, gy = y0 + xr;
-    const bool xtwo = gx + 1 < x1;
-    const unsigned pin = (unsigned)(gy * X.R + gx) * 8u;   // byte offset inside an output plane
-    const unsigned opair = xv && xtwo ? pin : kOOB, osing = xv && !xtwo ? pin : kOOB;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     __syncthreads();   // stages zeroed, taps and factors staged
 
-
-    // ring: planes z0 - P .. z0 + P - 1 in slots 0 .. 2P-1 (slot s holds plane zo - P + s
-    // shifted by the phase), plane z0 + P in `nv`
-    double rz[2 * P][kNPZ], nv[kNPZ];
+    // Every role runs TZv + 2 steps with one barrier each: step k is the z pass of plane
+    // z0 + k, the y pass of plane z0 + k - 1 and the x pass of plane z0 + k - 2.
+    if (wave < RL::WZ) {
+        // ---- z pass: footprint points j = tid + i TZT of this thread; their coefficients
+        // of the planes zo-p .. zo+p in a register ring (2p slots rotating, the newest in nv)
+        unsigned goff[NZ];
+        int loff[NZ];
 #pragma unroll
-    for (int s2 = 0; s2 < 2 * P; ++s2) {
-        const auto rb = plane_buf(z0 - P + s2);
+        for (int i = 0; i < NZ; ++i) {
+            const int j = tid + i * TZT;
+            const int r = j / RW, cc = j - r * RW;
+            const bool ok = j < npt;
+            goff[i] = ok ? (unsigned)((ya + r) * NX_ + xa + cc) * 8u : kOOB;
+            loff[i] = ok ? (lc0 + cc) * LHc + (ya + r - (y0 - P)) : -1;
+        }
+        const size_t plane = (size_t)NX_ * NYc;
+        auto plane_buf = [&](int zi) {
+            const bool ok = zi >= 0 && zi < NZc && zi < z1 + P;
+            return buf(g.u + (ok ? (size_t)zi * plane : 0), ok ? plane : 0);
+        };
+        double rz[2 * P][NZ], nv[NZ];
 #pragma unroll
-        for (int i = 0; i < kNPZ; ++i) rz[s2][i] = bload(rb, goff[i]);
-    }
-    {
-        const auto rb = plane_buf(z0 + P);
+        for (int s2 = 0; s2 < 2 * P; ++s2) {
+            const auto rb = plane_buf(z0 - P + s2);
 #pragma unroll
-        for (int i = 0; i < kNPZ; ++i) nv[i] = bload(rb, goff[i]);
-    }
-    const size_t oplane = (size_t)X.R * Y.R;
-
-    int cur = 0;   // ring slot of plane zo - P
-    for (int k = 0; k < TZv + 2; ++k) {
-        // ---- z pass of plane z0 + k into stage Z buffer (k & 1) (past the chunk: harmless
-        // values into a buffer no later pass reads) ----
+            for (int i = 0; i < NZ; ++i) rz[s2][i] = bload(rb, goff[i]);
+        }
         {
+            const auto rb = plane_buf(z0 + P);
+#pragma unroll
+            for (int i = 0; i < NZ; ++i) nv[i] = bload(rb, goff[i]);
+        }
+        int cur = 0;   // ring slot of plane zo - P
+        for (int k = 0; k < TZv + 2; ++k) {
             const int zo = min(z0 + k, z1 - 1);
             double* const z1s = sZ + (k & 1) * 2 * zsz;
             double* const z2s = z1s + zsz;
@@ -346,7 +292,7 @@ __device__ __forceinline__ void apply3d_tile(const ApplyArgs& g, const Plan3D& p
             for (int ph = 0; ph < 2 * P; ++ph) {
                 if (ph == cur) {
 #pragma unroll
-                    for (int i = 0; i < kNPZ; ++i) {
+                    for (int i = 0; i < NZ; ++i) {
                         if (k < TZv && loff[i] >= 0) {   // the last two steps only rotate
                             double s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -367,134 +313,223 @@ __device__ __forceinline__ void apply3d_tile(const ApplyArgs& g, const Plan3D& p
             cur = cur == 2 * P - 1 ? 0 : cur + 1;
             const auto rb = plane_buf(z0 + k + P + 1);
 #pragma unroll
-            for (int i = 0; i < kNPZ; ++i) nv[i] = bload(rb, goff[i]);
+            for (int i = 0; i < NZ; ++i) nv[i] = bload(rb, goff[i]);
+            __syncthreads();
         }
-
-        // ---- y pass of plane z0 + k - 1: stage Z buffer ((k-1) & 1) -> stage Y ----
-        if (yv && k >= 1 && k <= TZv) {
-            const double* const c1 = sZ + ((k - 1) & 1) * 2 * zsz + yrd;
-            const double* const c2 = c1 + zsz;
-            double* const ya_ = sY + ((k - 1) & 1) * 2 * ysz + 2 * yq * LS + ylc;
-            double* const yb_ = ya_ + ysz;
-            double y10 = 0.0, y20 = 0.0, y11 = 0.0, y21 = 0.0;
-            if (yint) {
+    } else if (wave < RL::WZ + RL::WY) {
+        // ---- y pass: tasks t = tid' + i TYT (two output rows 2q, 2q+1 of footprint column
+        // c); tasks of interior row pairs first, padded to whole waves
+        const int tyd = tid - TZT;
+        const int nqy = (TYv + 1) >> 1;
+        int qa = Y.ilo - y0;
+        qa = qa <= 0 ? 0 : (qa + 1) >> 1;                  // first pair with y0 + 2q >= ilo
+        int qb = Y.ihi - y0 - 1;
+        qb = qb < 0 ? 0 : (qb >> 1) + 1;                   // pairs with y0 + 2q + 1 <= ihi
+        qa = min(qa, nqy);
+        qb = min(max(qb, qa), nqy);
+        const int nYI = (qb - qa) * RW, nYIp = (nYI + 63) & ~63, nYB = (nqy - (qb - qa)) * RW;
+        int tq[NY], tc[NY];   // pair q (flags in the high bits: interior, two rows, valid), column
+#pragma unroll
+        for (int i = 0; i < NY; ++i) {
+            const int t = tyd + i * TYT;
+            bool yv, yint;
+            int yq, yc;
+            if (t < nYIp) {
+                yint = true;
+                yv = t < nYI;
+                const int u = yv ? t : 0;
+                yq = qa + u / RW;
+                yc = u - (u / RW) * RW;
+            } else {
+                yint = false;
+                const int t0 = t - nYIp;
+                yv = t0 < nYB;
+                const int u = yv ? t0 : 0;
+                const int j = u / RW;
+                yq = j < qa ? j : j + (qb - qa);
+                yc = u - j * RW;
+            }
+            const bool ytwo = 2 * yq + 1 < TYv;
+            tq[i] = yq | (yint ? 1 << 16 : 0) | (ytwo ? 1 << 17 : 0) | (yv ? 1 << 18 : 0);
+            tc[i] = lc0 + yc;
+        }
+        for (int k = 0; k < TZv + 2; ++k) {
+            if (k >= 1 && k <= TZv) {
                 double yim[W], yid[W];
                 uniform_row<W>(yim, yid, Y.M, Y.D, opaque(Y.ilo <= Y.ihi ? Y.ilo : 0));
 #pragma unroll
-                for (int kk = 0; kk < 2 * P + 2; ++kk) {
-                    const double av = c1[kk], bv = c2[kk];
-                    if (kk <= 2 * P) {
-                        y10 = fma(yim[kk], av, y10);
-                        y20 = fma(yid[kk], av, y20);
-                        y20 = fma(yim[kk], bv, y20);
-                    }
-                    if (kk >= 1) {
-                        y11 = fma(yim[kk - 1], av, y11);
-                        y21 = fma(yid[kk - 1], av, y21);
-                        y21 = fma(yim[kk - 1], bv, y21);
-                    }
-                }
-            } else {
-                double m[W], d[W];
-                lds_taps<W>(m, d, ty_ + (2 * yq) * 2 * W);
+                for (int i = 0; i < NY; ++i) {
+                    const int yq = tq[i] & 0xffff, ylc = tc[i];
+                    if (!(tq[i] & (1 << 18))) continue;
+                    const bool yint = (tq[i] & (1 << 16)) != 0, ytwo = (tq[i] & (1 << 17)) != 0;
+                    const double* const c1 = sZ + ((k - 1) & 1) * 2 * zsz + ylc * LHc + 2 * yq;
+                    const double* const c2 = c1 + zsz;
+                    double* const ya_ = sY + ((k - 1) & 1) * 2 * ysz + 2 * yq * LS + ylc;
+                    double* const yb_ = ya_ + ysz;
+                    double y10 = 0.0, y20 = 0.0, y11 = 0.0, y21 = 0.0;
+                    if (yint) {
 #pragma unroll
-                for (int kk = 0; kk < W; ++kk) {
-                    const double av = c1[kk], bv = c2[kk];
-                    y10 = fma(m[kk], av, y10);
-                    y20 = fma(d[kk], av, y20);
-                    y20 = fma(m[kk], bv, y20);
-                }
-                lds_taps<W>(m, d, ty_ + (2 * yq + 1) * 2 * W);
+                        for (int kk = 0; kk < 2 * P + 2; ++kk) {
+                            const double av = c1[kk], bv = c2[kk];
+                            if (kk <= 2 * P) {
+                                y10 = fma(yim[kk], av, y10);
+                                y20 = fma(yid[kk], av, y20);
+                                y20 = fma(yim[kk], bv, y20);
+                            }
+                            if (kk >= 1) {
+                                y11 = fma(yim[kk - 1], av, y11);
+                                y21 = fma(yid[kk - 1], av, y21);
+                                y21 = fma(yim[kk - 1], bv, y21);
+                            }
+                        }
+                    } else {
+                        double m[W], d[W];
+                        lds_taps<W>(m, d, ty_ + (2 * yq) * 2 * W);
 #pragma unroll
-                for (int kk = 0; kk < W; ++kk) {
-                    const double av = c1[kk + 1], bv = c2[kk + 1];
-                    y11 = fma(m[kk], av, y11);
-                    y21 = fma(d[kk], av, y21);
-                    y21 = fma(m[kk], bv, y21);
+                        for (int kk = 0; kk < W; ++kk) {
+                            const double av = c1[kk], bv = c2[kk];
+                            y10 = fma(m[kk], av, y10);
+                            y20 = fma(d[kk], av, y20);
+                            y20 = fma(m[kk], bv, y20);
+                        }
+                        lds_taps<W>(m, d, ty_ + (2 * yq + 1) * 2 * W);
+#pragma unroll
+                        for (int kk = 0; kk < W; ++kk) {
+                            const double av = c1[kk + 1], bv = c2[kk + 1];
+                            y11 = fma(m[kk], av, y11);
+                            y21 = fma(d[kk], av, y21);
+                            y21 = fma(m[kk], bv, y21);
+                        }
+                    }
+                    ya_[0] = y10;
+                    yb_[0] = kFold ? fma(g.alpha, y10, g.beta * y20) : y20;
+                    if (ytwo) {
+                        ya_[LS] = y11;
+                        yb_[LS] = kFold ? fma(g.alpha, y11, g.beta * y21) : y21;
+                    }
                 }
             }
-            ya_[0] = y10;
-            yb_[0] = kFold ? fma(g.alpha, y10, g.beta * y20) : y20;
-            if (ytwo) {
-                ya_[LS] = y11;
-                yb_[LS] = kFold ? fma(g.alpha, y11, g.beta * y21) : y21;
-            }
+            __syncthreads();
         }
-
-        // ---- x pass of plane z0 + k - 2: stage Y buffer (k & 1) -> rows; the stores are
-        // issued by every thread in every step (out of the buffer's range when there is
-        // nothing to store), so each step has the same memory operations ----
-        {
+    } else {
+        // ---- x pass: tasks t = tid'' + i TXT (output columns 2i, 2i+1 of tile row r);
+        // interior pairs first, padded to whole waves
+        const int txd = tid - TZT - TYT;
+        const int npx = (TXv + 1) >> 1;
+        int ia = X.ilo - x0;
+        ia = ia <= 0 ? 0 : (ia + 1) >> 1;
+        int ib = X.ihi - x0 - 1;
+        ib = ib < 0 ? 0 : (ib >> 1) + 1;
+        ia = min(ia, npx);
+        ib = min(max(ib, ia), npx);
+        const int nI = ib - ia, nB = npx - nI;
+        const int nXI = TYv * nI, nXIp = (nXI + 63) & ~63, nXB = TYv * nB;
+        int ti[NX], tr[NX];   // column pair xi (flags in the high bits: interior, valid), row
+        unsigned tp[NX];      // byte offset of the pair inside an output plane
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            const int t = txd + i * TXT;
+            bool xv, xint;
+            int xr, xi;
+            if (t < nXIp) {
+                xint = true;
+                xv = t < nXI;
+                const int u = xv ? t : 0;
+                xr = nI > 0 ? u / nI : 0;
+                xi = ia + (u - xr * nI);
+            } else {
+                xint = false;
+                const int t0 = t - nXIp;
+                xv = t0 < nXB;
+                const int u = xv ? t0 : 0;
+                xr = nB > 0 ? u / nB : 0;
+                const int j = u - xr * nB;
+                xi = j < ia ? j : j + nI;
+            }
+            xi = min(xi, npx - 1);
+            ti[i] = xi | (xint ? 1 << 16 : 0) | (xv ? 1 << 17 : 0);
+            tr[i] = xr;
+            tp[i] = (unsigned)((y0 + xr) * X.R + x0 + 2 * xi) * 8u;
+        }
+        const size_t oplane = (size_t)X.R * Y.R;
+        for (int k = 0; k < TZv + 2; ++k) {
             const bool live = k >= 2;
             const int oz = max(z0 + k - 2, 0);
-            const dv2* p1 = reinterpret_cast<const dv2*>(sY + (k & 1) * 2 * ysz + xrd);
-            const dv2* p2 = reinterpret_cast<const dv2*>(sY + (k & 1) * 2 * ysz + ysz + xrd);
-            double a[2 * P + 2], b[2 * P + 2];
-#pragma unroll
-            for (int kk = 0; kk < P + 1; ++kk) {
-                const dv2 va = p1[kk], vb = p2[kk];
-                a[2 * kk] = va.x;
-                a[2 * kk + 1] = va.y;
-                b[2 * kk] = vb.x;
-                b[2 * kk + 1] = vb.y;
-            }
-            double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
-            if (!xv || !live) {
-            } else if (xint) {
-                double xim[W], xid[W];
-                uniform_row<W>(xim, xid, X.M, X.D, opaque(X.ilo <= X.ihi ? X.ilo : 0));
-                xcol<P, kFold>(a, b, 0, xim, xid, o0, o1);
-                xcol<P, kFold>(a, b, 1, xim, xid, o2, o3);
-            } else {
-                double m[W], d[W];
-                lds_taps<W>(m, d, tx_ + (2 * xi) * 2 * W);
-                xcol<P, kFold>(a, b, 0, m, d, o0, o1);
-                lds_taps<W>(m, d, tx_ + (2 * xi + 1) * 2 * W);
-                xcol<P, kFold>(a, b, 1, m, d, o2, o3);
-            }
-            // uniform scalar loads: a vector load here would be waited for with the
-            // coefficient prefetch issued before it
+            // uniform scalar loads of the plane's scale and source factors
             const double sz = ((cdptr)Z.S)[oz], fz = ((cdptr)Z.F)[oz];
             const size_t pb = live ? (size_t)oz * oplane : 0;
             const size_t pn = live ? oplane : 0;
             const auto ro = buf(g.out + pb, pn);
-            double v0, v1;
-            if constexpr (kFold) {
-                v0 = fma(g.beta, o1, o0);
-                v1 = fma(g.beta, o3, o2);
-            } else {
-                const auto rm = buf(g.omass + pb, pn);
-                bstore2<kKeep>(rm, opair, o0, o2);
-                bstore<kKeep>(rm, osing, o0);
-                v0 = fma(g.alpha, o0, g.beta * o1);
-                v1 = fma(g.alpha, o2, g.beta * o3);
+            double xim[W], xid[W];
+            uniform_row<W>(xim, xid, X.M, X.D, opaque(X.ilo <= X.ihi ? X.ilo : 0));
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                const int xi = ti[i] & 0xffff, xr = tr[i];
+                const bool xint = (ti[i] & (1 << 16)) != 0, xv = (ti[i] & (1 << 17)) != 0;
+                const bool xtwo = x0 + 2 * xi + 1 < x1;
+                const unsigned opair = xv && xtwo ? tp[i] : kOOB, osing = xv && !xtwo ? tp[i] : kOOB;
+                const int xrd = xr * LS + 2 * xi;
+                const dv2* p1 = reinterpret_cast<const dv2*>(sY + (k & 1) * 2 * ysz + xrd);
+                const dv2* p2 = reinterpret_cast<const dv2*>(sY + (k & 1) * 2 * ysz + ysz + xrd);
+                double a[2 * P + 2], b[2 * P + 2];
+#pragma unroll
+                for (int kk = 0; kk < P + 1; ++kk) {
+                    const dv2 va = p1[kk], vb = p2[kk];
+                    a[2 * kk] = va.x;
+                    a[2 * kk + 1] = va.y;
+                    b[2 * kk] = vb.x;
+                    b[2 * kk + 1] = vb.y;
+                }
+                double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
+                if (!xv || !live) {
+                } else if (xint) {
+                    xcol<P, kFold>(a, b, 0, xim, xid, o0, o1);
+                    xcol<P, kFold>(a, b, 1, xim, xid, o2, o3);
+                } else {
+                    double m[W], d[W];
+                    lds_taps<W>(m, d, tx_ + (2 * xi) * 2 * W);
+                    xcol<P, kFold>(a, b, 0, m, d, o0, o1);
+                    lds_taps<W>(m, d, tx_ + (2 * xi + 1) * 2 * W);
+                    xcol<P, kFold>(a, b, 1, m, d, o2, o3);
+                }
+                double v0, v1;
+                if constexpr (kFold) {
+                    v0 = fma(g.beta, o1, o0);
+                    v1 = fma(g.beta, o3, o2);
+                } else {
+                    const auto rm = buf(g.omass + pb, pn);
+                    bstore2<kKeep>(rm, opair, o0, o2);
+                    bstore<kKeep>(rm, osing, o0);
+                    v0 = fma(g.alpha, o0, g.beta * o1);
+                    v1 = fma(g.alpha, o2, g.beta * o3);
+                }
+                // the products in the order of the 2D kernel's epilogue
+                dv2 sxv = {1.0, 1.0}, fxv = {1.0, 1.0};
+                double syz = 1.0;
+                if constexpr ((MODE & kScaleSrc) != 0) {
+                    sxv = *reinterpret_cast<const dv2*>(sfx + 2 * xi);
+                    fxv = *reinterpret_cast<const dv2*>(sfx + pl.TX + 2 * xi);
+                    syz = sfy[xr] * sz;
+                    const double fyz = sfy[pl.TY + xr] * fz;
+                    v0 = fma(g.gsep, fxv.x * fyz, v0);
+                    v1 = fma(g.gsep, fxv.y * fyz, v1);
+                }
+                if constexpr ((MODE & kFarr) != 0) {
+                    const auto rf = buf(g.farr + pb, pn);
+                    const dv2 fa = bload2(rf, opair);
+                    const double fs = bload(rf, osing);
+                    v0 = fma(g.garr, xtwo ? fa.x : fs, v0);
+                    v1 = fma(g.garr, fa.y, v1);
+                }
+                if constexpr ((MODE & kScaleSrc) != 0) {
+                    v0 *= sxv.x * syz;
+                    v1 *= sxv.y * syz;
+                }
+                bstore2<kKeep>(ro, opair, v0, v1);
+                bstore<kKeep>(ro, osing, v0);
             }
-            // the products in the order of the 2D kernel's epilogue
-            dv2 sxv = {1.0, 1.0}, fxv = {1.0, 1.0};
-            double syz = 1.0;
-            if constexpr ((MODE & kScaleSrc) != 0) {
-                sxv = *reinterpret_cast<const dv2*>(sfx + 2 * xi);
-                fxv = *reinterpret_cast<const dv2*>(sfx + pl.TX + 2 * xi);
-                syz = sfy[xr] * sz;
-                const double fyz = sfy[pl.TY + xr] * fz;
-                v0 = fma(g.gsep, fxv.x * fyz, v0);
-                v1 = fma(g.gsep, fxv.y * fyz, v1);
-            }
-            if constexpr ((MODE & kFarr) != 0) {
-                const auto rf = buf(g.farr + pb, pn);
-                const dv2 fa = bload2(rf, opair);
-                const double fs = bload(rf, osing);
-                v0 = fma(g.garr, xtwo ? fa.x : fs, v0);
-                v1 = fma(g.garr, fa.y, v1);
-            }
-            if constexpr ((MODE & kScaleSrc) != 0) {
-                v0 *= sxv.x * syz;
-                v1 *= sxv.y * syz;
-            }
-            bstore2<kKeep>(ro, opair, v0, v1);
-            bstore<kKeep>(ro, osing, v0);
+            __syncthreads();
         }
-        __syncthreads();   // LDS stage operations only: stores and prefetches stay in flight
     }
 }
 

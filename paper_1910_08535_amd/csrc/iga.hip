@@ -288,10 +288,11 @@ iga::Plan3D plan_3d_rows(int P, int Rx, int Ry, int Rz, int tx3d, int ty3d, int 
     pl.LW = pl.TX + 2 * P;
     pl.LS = pl.LW + (pl.LW & 1);
     const int NT = kMaxNT3;
-    const int kNPZ = npz(P);
+    // the footprint fits the z waves' rings, the y and x tasks (with a wave of padding each)
+    // fit the y and x waves
     auto fits = [&](int ty) {
-        return (ty + 2 * P) * pl.LW <= kNPZ * NT && (ty / kRY3) * pl.LW + 63 <= NT &&
-               ty * (pl.TX / 2) + 63 <= NT &&
+        return (ty + 2 * P) * pl.LW <= z_cap3(P) && (ty / kRY3) * pl.LW + 63 <= y_cap3(P) &&
+               ty * (pl.TX / 2) + 63 <= x_cap3(P) &&
                lds3d_doubles(pl.TX, ty, pl.LS, ty + 2 * P, P) * sizeof(double) <= 64 * 1024;
     };
     int TY = kRY3;
