@@ -458,7 +458,8 @@ int iga_server_submit(iga_server *s, const iga_request *reqs, int32_t n, uint64_
    cap completed requests (host arrays): ticket, time in seconds since the server was
    created (when the completion was observed), state (IGA_JOB_DONE or IGA_JOB_FAILED) and,
    if done_launch is not NULL, the index of the iteration that ran its last kernel (-1 for
-   a request run on a context).  *ndone receives the count.  Never blocks. */
+   a request run on a context).  *ndone receives the count.  Never blocks.  Errors:
+   IGA_E_INVAL; IGA_E_DEVICE (a HIP call failed: the server can only be destroyed). */
 int iga_server_progress(iga_server *s, uint64_t *done, double *done_time, int32_t *done_state,
                         int64_t *done_launch, int32_t cap, int32_t *ndone);
 /* Bytes in flight, their peak, iterations enqueued so far (batch_launches), and the

@@ -368,7 +368,6 @@ int server_iterate(iga_server* s)
             j.block = blk;
             off += b;
         }
-        if (!s->gen[r.p]) IGA_TRY(pg_generic(s->bstream, r.p, r.p + 1, &s->gen[r.p]));
         const bool step = r.kind == IGA_REQ_STEP;
         size_t toff = 0;
         for (int a = 0; a < r.dim; ++a) {
@@ -423,9 +422,11 @@ int server_iterate(iga_server* s)
     std::vector<int> b3[4];
     int nb3[4] = {0, 0, 0, 0};
     size_t lds3[4] = {0, 0, 0, 0};
+    std::vector<std::list<iga_server::Job>::iterator> advanced;   // jobs with a kernel in this iteration
     for (auto it = s->jobs.begin(); it != s->jobs.end(); ++it) {
         iga_server::Job& j = *it;
         if (j.left == 0) continue;
+        advanced.push_back(it);
         const iga_request& r = j.r;
         const bool step = r.kind == IGA_REQ_STEP;
         const double *src = r.u;
@@ -489,11 +490,6 @@ int server_iterate(iga_server* s)
                 nb3[q] += j.pl.nblk;
                 lds3[q] = std::max(lds3[q], j.lds3);
             }
-        }
-        if (step) ++j.k;
-        if (--j.left == 0) {
-            --s->pending;
-            sl->finishing.push_back(it);
         }
     }
     // descriptors: one host-to-device copy
@@ -588,6 +584,14 @@ int server_iterate(iga_server* s)
                 IGA_HIP(hipStreamWaitEvent(st, s->join[f], 0));
             }
     IGA_HIP(hipEventRecord(sl->ev, st));
+    // the iteration is enqueued: every job it carries has taken its next step
+    for (auto it : advanced) {
+        if (it->r.kind == IGA_REQ_STEP) ++it->k;
+        if (--it->left == 0) {
+            --s->pending;
+            sl->finishing.push_back(it);
+        }
+    }
     sl->busy = true;
     sl->iter = s->launches++;
     return IGA_OK;
@@ -623,7 +627,10 @@ int server_progress(iga_server* s)
         if (s->used + it.bytes > s->budget) break;
         const iga_request& r = it.r;
         s->used += it.bytes;
-        if (batchable(r)) {
+        if (batchable(r) && !s->gen[r.p] && pg_generic(s->bstream, r.p, r.p + 1, &s->gen[r.p]) != IGA_OK) {
+            (void)hipGetLastError();
+            server_finish(s, it, IGA_JOB_FAILED, -1);   // the element-unit rows could not be built
+        } else if (batchable(r)) {
             iga_server::Job j;
             std::memset(&j.pl, 0, sizeof(j.pl));
             j.ticket = it.ticket;
