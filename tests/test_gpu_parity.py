@@ -282,3 +282,30 @@ def test_shared_axis_tables_across_streams(iga, orc):
     pb = orc.Problem(dim=2, p=p, ne=ne[:2], nq=(4, 4))
     assert relerr(host(l2), orc.rhs(pb, orc.PG, u2.cpu().numpy(), beta=1.0)) <= TOL
     assert relerr(host(m2), orc.rhs(pb, orc.PG, u2.cpu().numpy(), alpha=1.0)) <= TOL
+
+
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("nq_extra", [0, -1, 2])
+def test_pg_rows_around_element_unit_threshold(iga, orc, p, nq_extra):
+    """PG band rows of support spans come from the element-unit rows of (p, nq) scaled by
+    h and 1/h when an axis has at least 3p+1 elements, from direct Gauss sums below that:
+    both sides of the switch, on a non-unit domain and with several rules, match the
+    oracle's point-wise integrals, and rows equidistant from the nearer end are equal
+    to rounding in the expanded case."""
+    nq = p + 1 + nq_extra
+    for ne in (3 * p - 1, 3 * p, 3 * p + 1, 3 * p + 2, 5 * p + 3):
+        mesh = iga.Mesh(1, p, (ne,), (nq,), lo=[-0.5], hi=[1.75])
+        bands = host(mesh.assemble(iga.PG, iga.OP_LAPLACE))
+        R = N = ne + p
+        for f, kind in ((0, orc.MAT_PG_MASS), (1, orc.MAT_PG_LAP)):
+            dense = iga.bands_to_dense(bands[0, f], R, N, p)
+            ref = orc.matrix_1d(p, ne, nq, kind, lo=-0.5, hi=1.75)
+            assert relerr(dense, ref) <= TOL, (ne, nq, f)
+        if ne >= 3 * p + 1:
+            # the expansion: row r and the mirrored row R-1-r hold the mirrored taps, and
+            # interior rows are bitwise equal
+            for f in range(2):
+                b = bands[0, f, :R]
+                assert (b[2 * p:R - 2 * p] == b[2 * p]).all(), (ne, f)
+                np.testing.assert_allclose(b[::-1, ::-1], b, rtol=1e-13, atol=1e-13 * np.abs(b).max())
+        mesh.close()
