@@ -21,6 +21,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "tables.hpp"
 
 namespace iga {
 
@@ -100,6 +101,30 @@ __global__ __launch_bounds__(kBlock) void apply1d_kernel(ApplyArgs g)
         const double uj = (j >= 0 && j < X.N) ? g.u[j] : 0.0;
         m = fma(X.M[(size_t)r * W + k], uj, m);
         d = fma(X.D[(size_t)r * W + k], uj, d);
+    }
+    finish_row<MODE>(g, r, m, d, X.S[r], X.F[r]);
+}
+
+// 1D PG rows of support spans on an axis of at least 3p+1 elements: the taps are formed
+// from the element-unit rows of (p, nq) (tables.hpp), the values the axis' own band
+// tables hold, so the rows are those of apply1d_kernel bit for bit while each row reads
+// 8 bytes of coefficients (and its scale and source factors) instead of 2(2p+1) taps.
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void apply1d_gen_kernel(ApplyArgs g, const double* gen, double h, double ih)
+{
+    constexpr int W = 2 * P + 1;
+    const AxisOp X = g.ax[0];
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= X.R) return;
+    double mt[2 * kMaxP + 1], dt[2 * kMaxP + 1];
+    pg_generic_row(gen, P, r, X.R, h, ih, mt, dt);
+    double m = 0.0, d = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int j = r + k - P;
+        const double uj = (j >= 0 && j < X.N) ? g.u[j] : 0.0;
+        m = fma(mt[k], uj, m);
+        d = fma(dt[k], uj, d);
     }
     finish_row<MODE>(g, r, m, d, X.S[r], X.F[r]);
 }

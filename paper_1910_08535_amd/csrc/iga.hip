@@ -348,7 +348,12 @@ void launch_apply_pm(const iga_ctx* c, const ApplyArgs& g, hipStream_t s)
 {
     if (c->dim == 1) {
         const int grid = (g.ax[0].R + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL((iga::apply1d_kernel<P, MODE>), dim3(grid), dim3(kBlock), 0, s, g);
+        const AxisTables& t = c->t[0];
+        if (t.pgen && g.ax[0].M == t.pm)   // PG rows scaled from the element-unit rows
+            hipLaunchKernelGGL((iga::apply1d_gen_kernel<P, MODE>), dim3(grid), dim3(kBlock), 0, s, g, t.pgen,
+                               iga::elem_len(t.lo, t.hi, t.ne), iga::elem_inv_len(t.lo, t.hi, t.ne));
+        else
+            hipLaunchKernelGGL((iga::apply1d_kernel<P, MODE>), dim3(grid), dim3(kBlock), 0, s, g);
     } else if (c->dim == 2) {
         if (c->ty2d == 2)
             launch_2d<P, 2, MODE>(g, s, c->order2d, c->strip2d);
