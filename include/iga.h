@@ -214,8 +214,9 @@ int iga_explicit_step_noalloc(iga_ctx *ctx, double *u, double dt, const iga_sour
    neighbouring chunk boundaries is below 2^-64 (it decays geometrically along a chunk),
    the block system is taken as block diagonal; deciding this reads one small table back
    to the host at the context's first solve along the axis (one synchronisation of its
-   stream; with the environment variable IGA_PART_EXACT set to a value other than 0, the
-   full block system is used; iga_solve_info reports the choice).
+   stream; with the context setting IGA_TILE_SOLVE_EXACT = 1 (iga_set_tile) the full
+   block system is always used and nothing is read back; iga_solve_info reports the
+   choice).
    The first solve of a context allocates and builds these tables, so it must not be
    captured into a graph (IGA_E_INVAL while the context's stream is capturing); once it
    has run, solves can be captured and replayed.
@@ -302,14 +303,19 @@ int iga_dirichlet_rows(iga_ctx *ctx, int32_t form, int32_t side_mask, const doub
      IGA_TILE_3D_COLS    output columns per 3D tile: even, 8..96, 0 = automatic (default)
      IGA_TILE_2D_STRIP   2D strip width: 128 columns, two per lane (default), or 64, one
                          per lane (same bits)
-   Changing a setting drops the context's cached graph.
-   Errors: IGA_E_INVAL (unknown key or value). */
+     IGA_TILE_SOLVE_EXACT  partitioned solves (iga_solve): 0 = the block system that couples
+                         the chunks taken as block diagonal where its dropped coupling is
+                         below 2^-64 (default), 1 = always solved whole (no read-back at the
+                         first solve); accepted only before the context's first solve
+   Changing a launch setting drops the context's cached graph.
+   Errors: IGA_E_INVAL (unknown key or value; IGA_TILE_SOLVE_EXACT after a solve). */
 #define IGA_TILE_2D_ROWS 1
 #define IGA_TILE_3D_PLANES 2
 #define IGA_TILE_3D_ROWS 4
 #define IGA_TILE_2D_ORDER 5
 #define IGA_TILE_3D_COLS 6
 #define IGA_TILE_2D_STRIP 7
+#define IGA_TILE_SOLVE_EXACT 8
 int iga_set_tile(iga_ctx *ctx, int32_t key, int32_t value);
 int iga_get_tile(const iga_ctx *ctx, int32_t key, int32_t *value);
 

@@ -85,6 +85,7 @@ struct iga_ctx {
     double* part[3] = {nullptr, nullptr, nullptr};
     bool part_trunc[3] = {false, false, false};   // the reduced system is block diagonal to rounding
     bool part_long[3] = {false, false, false};    // short chunks of a single line were refused
+    bool part_exact = false;   // IGA_TILE_SOLVE_EXACT: always solve the reduced system whole
     double* part_z = nullptr;
     size_t part_z_n = 0;
     double* part_w = nullptr;   // chunk solutions of the block-diagonal reduced system
@@ -614,6 +615,7 @@ struct AxisCache {
     // constants shared by every context of the device: {1, 0 x 7} | two int zeros | ones
     double* consts = nullptr;
     size_t nones = 0;
+    hipEvent_t consts_ev = nullptr;   // the fill of consts, until it is known to be complete
     // this device's copy of `scratch` (below): the address of the symbol on the device
     double* scratch = nullptr;
     // element-unit PG rows per (p, nq), built once per device and kept: the table and the
@@ -660,7 +662,9 @@ __global__ void fill_consts_kernel(double* base, size_t n)
 }
 
 // The device's shared constants with at least n ones.  Growing them replaces the buffer
-// (older ones stay allocated: contexts may still point at them) and waits for the fill.
+// (older ones stay allocated: contexts may still point at them); the fill runs on the
+// context's stream, and contexts created on other streams while it may still run wait
+// for it on theirs (no host synchronisation).
 int shared_consts(iga_ctx* c, size_t n)
 {
     AxisCache* g = device_cache();
@@ -673,11 +677,29 @@ int shared_consts(iga_ctx* c, size_t n)
             (void)hipGetLastError();
             return IGA_E_NOMEM;
         }
+        hipEvent_t ev = nullptr;
         hipLaunchKernelGGL(fill_consts_kernel, dim3(256), dim3(kBlock), 0, c->stream, (double*)p, m);
-        IGA_HIP(hipGetLastError());
-        IGA_HIP(hipStreamSynchronize(c->stream));
+        if (hipGetLastError() != hipSuccess || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev, c->stream) != hipSuccess) {
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(p);
+            if (ev) (void)hipEventDestroy(ev);
+            return IGA_E_DEVICE;
+        }
+        if (g->consts_ev) (void)hipEventDestroy(g->consts_ev);   // the newer fill supersedes it
         g->consts = (double*)p;
         g->nones = m;
+        g->consts_ev = ev;
+    } else if (g->consts_ev) {
+        const hipError_t q = hipEventQuery(g->consts_ev);
+        if (q == hipSuccess) {
+            (void)hipEventDestroy(g->consts_ev);
+            g->consts_ev = nullptr;
+        } else if (q == hipErrorNotReady) {
+            IGA_HIP(hipStreamWaitEvent(c->stream, g->consts_ev, 0));
+        } else {
+            return IGA_E_DEVICE;
+        }
     }
     c->unit = g->consts;
     c->zero = (int*)(g->consts + 8);
@@ -1043,8 +1065,8 @@ constexpr double kTruncTip = 0x1p-64;
 // `lines` lines.  The chunk factors F, B have kFactorPad zero rows after row n, as the
 // segment kernel reads them.  The tables are F | B | V | Wt | Gamma | Delta^-1 | D^-1 | tip.
 // The host reads the largest dropped spike entry back (one synchronisation per context
-// and axis) to choose the truncated reduced system; during stream capture, or with
-// IGA_PART_EXACT set in the environment, the exact block sweeps run.  kPartReplan: the
+// and axis) to choose the truncated reduced system; during stream capture, or on a context
+// set to IGA_TILE_SOLVE_EXACT = 1, the exact block sweeps run.  kPartReplan: the
 // exact sweeps are needed and do not fit this geometry (short chunks); the context then
 // keeps to long chunks along this axis.
 constexpr int kPartReplan = 1;
@@ -1082,9 +1104,8 @@ int ensure_part(iga_ctx* c, int a, const iga::PartGeom& g, long long lines)
         IGA_HIP(hipGetLastError());
         bool trunc = false;
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        const char* exact = std::getenv("IGA_PART_EXACT");
-        if ((!exact || !*exact || std::strcmp(exact, "0") == 0) &&
-            hipStreamIsCapturing(c->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+        if (!c->part_exact && hipStreamIsCapturing(c->stream, &cs) == hipSuccess &&
+            cs == hipStreamCaptureStatusNone) {
             std::vector<double> h((size_t)(K - 1));
             IGA_HIP(hipMemcpyAsync(h.data(), tip, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             IGA_HIP(hipStreamSynchronize(c->stream));
@@ -1611,6 +1632,12 @@ int iga_set_tile(iga_ctx* c, int32_t key, int32_t value)
         if (value != 64 && value != 128) return IGA_E_INVAL;
         c->strip2d = value;
         break;
+    case IGA_TILE_SOLVE_EXACT:   // chosen at an axis' first solve: fixed once a solve has run
+        if (value != 0 && value != 1) return IGA_E_INVAL;
+        for (int a = 0; a < c->dim; ++a)
+            if (c->part[a] || c->chol[a] || c->lu[a]) return IGA_E_INVAL;
+        c->part_exact = value != 0;
+        return IGA_OK;
     default:
         return IGA_E_INVAL;
     }
@@ -1628,6 +1655,7 @@ int iga_get_tile(const iga_ctx* c, int32_t key, int32_t* value)
     case IGA_TILE_3D_ROWS: *value = c->ty3d; break;
     case IGA_TILE_3D_COLS: *value = c->tx3d; break;
     case IGA_TILE_2D_STRIP: *value = c->strip2d; break;
+    case IGA_TILE_SOLVE_EXACT: *value = c->part_exact ? 1 : 0; break;
     default: return IGA_E_INVAL;
     }
     return IGA_OK;

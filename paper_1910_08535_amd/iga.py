@@ -25,6 +25,7 @@ GALERKIN_BYPARTS, GALERKIN_LAPLACIAN, PG = 0, 1, 2
 OP_MASS, OP_LAPLACE = 0, 1
 SPANS_SUPPORT, SPANS_ELEMENT, SPANS_CUSTOM, SPANS_REFINED = 0, 1, 2, 3
 TILE_2D_ROWS, TILE_3D_PLANES, TILE_3D_ROWS, TILE_2D_ORDER, TILE_3D_COLS, TILE_2D_STRIP = 1, 2, 4, 5, 6, 7
+TILE_SOLVE_EXACT = 8   # partitioned solves: the reduced system always taken whole
 TUNE_APPLY, TUNE_STEP, TUNE_MAX = 0, 1, 16
 TILE_KEYS = {2: (TILE_2D_STRIP, TILE_2D_ROWS, TILE_2D_ORDER), 3: (TILE_3D_PLANES, TILE_3D_ROWS, TILE_3D_COLS)}
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3

@@ -291,7 +291,8 @@ def test_pg_rows_around_element_unit_threshold(iga, orc, p, nq_extra):
     h and 1/h when an axis has at least 3p+1 elements, from direct Gauss sums below that:
     both sides of the switch, on a non-unit domain and with several rules, match the
     oracle's point-wise integrals, and rows equidistant from the nearer end are equal
-    to rounding in the expanded case."""
+    to rounding in the expanded case.  The apply and the lumped step on such an axis
+    match the oracle on both sides as well."""
     nq = p + 1 + nq_extra
     for ne in (3 * p - 1, 3 * p, 3 * p + 1, 3 * p + 2, 5 * p + 3):
         mesh = iga.Mesh(1, p, (ne,), (nq,), lo=[-0.5], hi=[1.75])
@@ -308,4 +309,14 @@ def test_pg_rows_around_element_unit_threshold(iga, orc, p, nq_extra):
                 b = bands[0, f, :R]
                 assert (b[2 * p:R - 2 * p] == b[2 * p]).all(), (ne, f)
                 np.testing.assert_allclose(b[::-1, ::-1], b, rtol=1e-13, atol=1e-13 * np.abs(b).max())
+        # the fused apply and a lumped step on the same axis: from 3p+1 elements on, the 1D
+        # kernels form their taps from the element-unit rows instead of reading the tables
+        pb = orc.Problem(dim=1, p=p, ne=(ne,), nq=(nq,), lo=(-0.5,), hi=(1.75,))
+        u = inputs.normal_coefs((ne,), p, seed=40 + ne)
+        m, l = mesh.apply(iga.PG, cuda(u))
+        assert relerr(host(m), orc.rhs(pb, orc.PG, u, alpha=1.0)) <= TOL, ne
+        assert relerr(host(l), orc.rhs(pb, orc.PG, u, beta=1.0)) <= TOL, ne
+        ud = cuda(u)
+        mesh.explicit_step(ud, 1e-4, sin_amp=1.0, nsteps=3)
+        assert relerr(host(ud), orc.explicit_step(pb, u, 1e-4, sin_amp=1.0, nsteps=3)) <= TOL, ne
         mesh.close()

@@ -119,11 +119,12 @@ PART_CASES = [
 
 
 @pytest.mark.parametrize("dim,p,ne,lo,hi,schemes", PART_CASES)
-def test_solve_exact_reduced_system(orc, torch, iga, monkeypatch, dim, p, ne, lo, hi, schemes):
-    """The partitioned solve with its reduced system taken whole (IGA_PART_EXACT set: block
-    sweeps along each line) and by default (block diagonal where every dropped spike
-    entry is below 2^-64): both agree with the oracle and with each other to rounding,
-    and each axis reports the scheme it took."""
+def test_solve_exact_reduced_system(orc, torch, iga, dim, p, ne, lo, hi, schemes):
+    """The partitioned solve with its reduced system taken whole (the context setting
+    TILE_SOLVE_EXACT = 1: block sweeps along each line) and by default (block diagonal
+    where every dropped spike entry is below 2^-64): both agree with the oracle and with
+    each other to rounding, and each axis reports the scheme it took.  The setting is
+    refused once a solve has run."""
     print(f"solve exact reduced dim={dim} p={p} ne={ne}", flush=True)
     pb = orc.Problem(dim, p, ne, [p + 1] * dim, lo or [0.0] * dim, hi or [1.0] * dim)
     b = np.random.default_rng(23).standard_normal(pb.coef_shape())
@@ -135,10 +136,14 @@ def test_solve_exact_reduced_system(orc, torch, iga, monkeypatch, dim, p, ne, lo
     got = tuple(mesh.solve_info(a)[0] for a in range(dim))
     mesh.close()
     assert got == schemes, (got, schemes)
-    monkeypatch.setenv("IGA_PART_EXACT", "1")
     mesh = _mesh(iga, dim, p, ne, lo, hi)
+    assert mesh.get_tile(iga.TILE_SOLVE_EXACT) == 0
+    mesh.set_tile(iga.TILE_SOLVE_EXACT, 1)
     xe = mesh.solve(bd).cpu().numpy()
     got_e = tuple(mesh.solve_info(a)[0] for a in range(dim))
+    assert mesh.get_tile(iga.TILE_SOLVE_EXACT) == 1
+    with pytest.raises(iga.IGAError):
+        mesh.set_tile(iga.TILE_SOLVE_EXACT, 0)
     mesh.close()
     assert got_e == tuple(E if s == B else s for s in schemes), got_e
     print(f"  errors: default {_rel(x, ref):.2e} exact {_rel(xe, ref):.2e} "
