@@ -619,6 +619,56 @@ def run_laplace(args) -> dict:
     return out
 
 
+def run_reduced(args) -> dict:
+    """Reduced quadrature in the PG form (Section 4.1): the 2-point Gauss rule on every axis
+    against the (p+1)-point rule.  The rows of the u terms come from band factors built
+    at set-up, whatever the rule, so per call the rule changes only what a source given
+    at the Gauss points costs: its table holds 2^d instead of (p+1)^d values per element.
+    Times rhs(PG, u, alpha = beta = gamma = 1, f_table) per rule for 2D 1024^2, p = 2 and
+    3D 128^3, p = 3, HIP events on the mesh's stream; the tables (seeded uniform values
+    in [-1, 1)) are used in turn, enough of them to exceed 600 MB, so each call reads its
+    table from HBM.  Algorithmic bytes: the table, u and the output rows."""
+    import math
+    import torch
+    from paper_1910_08535_amd import iga, inputs
+
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for dim, p, n in ((2, 2, 1024), (3, 3, 128)):
+        ne = (n,) * dim
+        case = {}
+        for nq in (p + 1, 2):
+            mesh = iga.Mesh(dim, p, ne, (nq,) * dim, stream=stream)
+            u = torch.from_numpy(inputs.normal_coefs(ne, p, 6)).cuda()
+            shape = inputs.gauss_shape(ne, (nq,) * dim)
+            tbytes = math.prod(shape) * 8
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(7)
+            tabs = [torch.empty(shape, dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=gen)
+                    for _ in range(max(1, math.ceil(600e6 / tbytes)))]
+            b = torch.empty(mesh.shape(iga.PG), dtype=torch.float64, device="cuda")
+            for t in tabs[:2]:
+                mesh.rhs(iga.PG, u, 1.0, 1.0, 1.0, f_table=t, out=b)
+            reps = max(10, len(tabs))
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(reps):
+                mesh.rhs(iga.PG, u, 1.0, 1.0, 1.0, f_table=tabs[i % len(tabs)], out=b)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            nbytes = tbytes + u.numel() * 8 + b.numel() * 8
+            case[f"nq{nq}"] = {"us_rhs": us, "table_bytes": tbytes, "algorithmic_bytes": nbytes,
+                               "GBs": nbytes / us * 1e-3, "hbm_frac": nbytes / us * 1e-3 / 8000.0}
+            del tabs
+            mesh.close()
+        case["speedup_2pt"] = case[f"nq{p + 1}"]["us_rhs"] / case["nq2"]["us_rhs"]
+        out[f"{dim}d_{n}_p{p}"] = case
+    return out
+
+
 def stage_requests(reqs) -> int:
     """Puts every request's coefficients (seeded N(0,1), as the request's seed draws them)
     and, for RHS requests, its two output arrays on the device, so that the timed serving
@@ -699,6 +749,8 @@ def main():
     ap.add_argument("--no-ads", action="store_true", help="skip the Galerkin projection/solve leg")
     ap.add_argument("--ads-reps", type=int, default=10)
     ap.add_argument("--no-laplace", action="store_true", help="skip the mixed Laplace leg")
+    ap.add_argument("--no-reduced", action="store_true",
+                    help="skip the 2-point against (p+1)-point PG right-hand-side leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--tile2d", default="",
                     help="STRIP,ROWS,ORDER: fix the 2D tile instead of autotuning it")
@@ -721,6 +773,8 @@ def main():
         out["ads"] = run_ads(args)
     if not args.no_laplace:
         out["laplace2d"] = run_laplace(args)
+    if not args.no_reduced:
+        out["reduced_quadrature"] = run_reduced(args)
     if not args.no_batched:
         out["batched"] = run_c4(args)
     if not args.no_serving:

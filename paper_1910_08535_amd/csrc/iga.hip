@@ -425,6 +425,24 @@ int launch_rows_only(const iga_ctx* c, const ApplyArgs& g, size_t n, hipStream_t
     return IGA_OK;
 }
 
+// Doubles of c->elem that the rows of a Gauss-table source need.  Galerkin: the element
+// results, np1^d per element.  PG: [A | B] with A = max(elements, ne_z R_y R_x) (the
+// element sums, then the y-pass sums of a 3D mesh) and B = ne_z ne_y R_x (the x-pass
+// sums of a 2D or 3D mesh).
+size_t src_scratch_doubles(const iga_ctx* c, int form)
+{
+    size_t nel = 1, np1 = 1;
+    for (int a = 0; a < c->dim; ++a) {
+        nel *= (size_t)c->t[a].ne;
+        np1 *= (size_t)(c->t[a].p + 1);
+    }
+    if (form != IGA_PG) return nel * np1;
+    size_t A = nel, B = 0;
+    if (c->dim >= 2) B = nel / (size_t)c->t[0].ne * (size_t)c->t[0].R;
+    if (c->dim == 3) A = std::max(A, (size_t)c->t[2].ne * c->t[1].R * c->t[0].R);
+    return A + B;
+}
+
 // Rows of a Gauss-table source into c->farr (unscaled F_r).
 int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
 {
@@ -456,8 +474,8 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
         }
     }
     const size_t nr = nrows(c, form);
-    const size_t nelem_vals = form == IGA_PG ? nel : nel * (size_t)np1;
-    IGA_TRY(ensure_scratch(c, &c->elem, &c->elem_n, nelem_vals));
+    const size_t nscr = src_scratch_doubles(c, form);
+    IGA_TRY(ensure_scratch(c, &c->elem, &c->elem_n, nscr));
     IGA_TRY(ensure_scratch(c, &c->farr, &c->farr_n, nr));
     sa.table = table;
     sa.elem = c->elem;
@@ -465,8 +483,40 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
     const unsigned ge = (unsigned)((nel + kBlock - 1) / kBlock);
     const unsigned gr = (unsigned)((nr + kBlock - 1) / kBlock);
     if (form == IGA_PG) {
-        hipLaunchKernelGGL(iga::pg_src_elem_kernel, dim3(ge), dim3(kBlock), 0, s, sa, nel);
-        hipLaunchKernelGGL(iga::pg_src_rows_kernel, dim3(gr), dim3(kBlock), 0, s, sa, nr);
+        // element sums into A
+        const iga::SrcAxis& X = sa.ax[0];
+        const size_t others = nel / (size_t)X.ne;
+        auto units = [&](int e) { return (size_t)((X.ne + e - 1) / e) * others; };
+        auto blocks = [](size_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
+        if (X.nq == 2)
+            hipLaunchKernelGGL(iga::pg_src_elem_vec_kernel<2>, blocks(units(1)), dim3(kBlock), 0, s, sa, units(1));
+        else if (X.nq == 3)
+            hipLaunchKernelGGL(iga::pg_src_elem_vec_kernel<3>, blocks(units(2)), dim3(kBlock), 0, s, sa, units(2));
+        else if (X.nq == 4)
+            hipLaunchKernelGGL(iga::pg_src_elem_vec_kernel<4>, blocks(units(1)), dim3(kBlock), 0, s, sa, units(1));
+        else
+            hipLaunchKernelGGL(iga::pg_src_elem_kernel, dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        // span sums along x, y, z: A -> B -> A -> farr, the last pass into farr
+        const size_t A = nscr - (c->dim >= 2 ? others * (size_t)X.R : 0);
+        double* const bufA = c->elem;
+        double* const bufB = c->elem + A;
+        const double* in = bufA;
+        size_t outer = nel, inner = 1;
+        for (int a = 0; a < c->dim; ++a) {
+            const iga::SrcAxis& x = sa.ax[a];
+            outer /= (size_t)x.ne;
+            double* const out = a == c->dim - 1 ? c->farr : (a == 0 ? bufB : bufA);
+            const size_t total = outer * (size_t)x.R * inner;
+            const size_t span_in = outer * (size_t)x.ne * inner;   // entries of the pass' input
+            if (std::max(total, span_in) < ((size_t)1 << 32))
+                hipLaunchKernelGGL(iga::src_span_sum_kernel<unsigned>, blocks(total), dim3(kBlock), 0, s, in, out,
+                                   x.first, x.last, x.ne, x.R, (unsigned)inner, (unsigned)total);
+            else
+                hipLaunchKernelGGL(iga::src_span_sum_kernel<size_t>, blocks(total), dim3(kBlock), 0, s, in, out,
+                                   x.first, x.last, x.ne, x.R, inner, total);
+            in = out;
+            inner *= (size_t)x.R;
+        }
     } else {
         hipLaunchKernelGGL(iga::gal_src_elem_kernel, dim3(ge), dim3(kBlock), 0, s, sa, nel);
         hipLaunchKernelGGL(iga::gal_src_rows_kernel, dim3(gr), dim3(kBlock), 0, s, sa, nr);
@@ -1822,9 +1872,7 @@ int iga_explicit_step(iga_ctx* c, double* u, double dt, const iga_source* f, int
     const size_t n = prod3(c->N);
     IGA_TRY(ensure_scratch(c, &c->work, &c->work_n, n));
     if (table) {   // make sure the source scratch exists before any capture
-        size_t nel = 1;
-        for (int a = 0; a < c->dim; ++a) nel *= (size_t)c->ne[a];
-        IGA_TRY(ensure_scratch(c, &c->elem, &c->elem_n, nel));
+        IGA_TRY(ensure_scratch(c, &c->elem, &c->elem_n, src_scratch_doubles(c, IGA_PG)));
         IGA_TRY(ensure_scratch(c, &c->farr, &c->farr_n, n));
     }
     auto enqueue = [&](hipStream_t s) -> int {

@@ -7,8 +7,9 @@
 //
 // Both run in two steps: a per-element reduction over the element's Gauss points
 // (PG: one number; Galerkin: one number per local test function), then a gather of
-// the element results into rows.  The gather reads each element result from the
-// rows it feeds, so no atomics are used and the result does not depend on timing.
+// the element results into rows (PG: span sums one axis at a time).  Every gather reads
+// the element results a row needs, so no atomics are used and the result does not
+// depend on timing.
 #pragma once
 
 #include "common.hpp"
@@ -66,21 +67,96 @@ __global__ void pg_src_elem_kernel(SrcArgs s, size_t nel)
     s.elem[idx] = acc;
 }
 
-// PG step 2: F_r = sum over the tensor span of the element integrals.
-__global__ void pg_src_rows_kernel(SrcArgs s, size_t nrows)
+// PG step 1 for NQ Gauss points along x (the common rules): the same sums in the same
+// order, with the table read by 16-byte accesses.  A thread takes E consecutive elements
+// of an x-line, E = 2 for odd NQ so that its share of a table row is a whole number of
+// 16-byte pairs; consecutive threads read consecutive pairs of every row (a wave reads
+// contiguous memory).  nunits: threads = ceil(ne_x / E) * ne_y * ne_z.
+typedef double src_pair __attribute__((ext_vector_type(2), aligned(8)));
+
+template <int NQ>
+__global__ __launch_bounds__(kBlock) void pg_src_elem_vec_kernel(SrcArgs s, size_t nunits)
 {
+    constexpr int E = (NQ & 1) ? 2 : 1;
+    constexpr int V = E * NQ / 2;   // pairs per table row
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nrows) return;
+    if (idx >= nunits) return;
     const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
-    const int rx = (int)(idx % X.R);
-    const int ry = (int)((idx / X.R) % Y.R);
-    const int rz = (int)(idx / ((size_t)X.R * Y.R));
+    const int nux = (X.ne + E - 1) / E;
+    const int ex0 = (int)(idx % (size_t)nux) * E;
+    const size_t t = idx / (size_t)nux;
+    const int ey = (int)(t % (size_t)Y.ne), ez = (int)(t / (size_t)Y.ne);
+    const bool full = ex0 + E <= X.ne;   // else only element ex0 (the last of its line)
+    double w[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) w[q] = X.gw[q];
+    const size_t ngx = (size_t)X.ne * NQ, ngy = (size_t)Y.ne * Y.nq;
+    const size_t gy0 = (size_t)ey * Y.nq, gz0 = (size_t)ez * Z.nq;
+    double acc[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j] = 0.0;
+    for (int qz = 0; qz < Z.nq; ++qz) {
+#pragma unroll 4
+        for (int qy = 0; qy < Y.nq; ++qy) {
+            const double wyz = Z.gw[qz] * Y.gw[qy];
+            const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + (size_t)ex0 * NQ;
+            double v[E * NQ];
+            if (full) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const src_pair pr = *reinterpret_cast<const src_pair*>(row + 2 * k);
+                    v[2 * k] = pr.x;
+                    v[2 * k + 1] = pr.y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < E * NQ; ++k) v[k] = k < NQ ? row[k] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                double tt = 0.0;
+#pragma unroll
+                for (int qx = 0; qx < NQ; ++qx) tt = fma(w[qx], v[j * NQ + qx], tt);
+                acc[j] = fma(wyz, tt, acc[j]);
+            }
+        }
+    }
+    const size_t e0 = ((size_t)ez * Y.ne + ey) * X.ne + ex0;
+    s.elem[e0] = acc[0];
+    if (E == 2 && full) s.elem[e0 + 1] = acc[E - 1];
+}
+
+// PG step 2, one axis at a time (the tensor span is a product of per-axis spans):
+//   out[o][r][i] = sum_{e = first[r]}^{last[r]} in[o][e][i]
+// for o < nouter, r < nout, i < ninner, in holding nin entries along the axis.  Applied
+// along x, then y, then z: F_r = sum_{ez in Sz} sum_{ey in Sy} sum_{ex in Sx} E_e, each
+// sum in ascending element order.  One thread per output; total = nouter nout ninner.
+// I: the index type, 32-bit whenever the arrays allow (its divisions are far cheaper).
+// Blocks are numbered XCD-aware: the outputs of neighbouring blocks share most of their
+// inputs, which then come from one L2.
+template <typename I>
+__global__ __launch_bounds__(kBlock) void src_span_sum_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                              const int* __restrict__ first,
+                                                              const int* __restrict__ last, int nin, int nout,
+                                                              I ninner, I total)
+{
+    const I blk = (I)xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
+    const I idx = blk * (I)blockDim.x + (I)threadIdx.x;
+    if (idx >= total) return;
+    const I i = idx % ninner, t = idx / ninner;
+    const I r = t % (I)nout, o = t / (I)nout;
+    const double* src = in + ((size_t)o * (size_t)nin * (size_t)ninner + i);
+    const int f = first[r], l = last[r];
     double acc = 0.0;
-    for (int ez = Z.first[rz]; ez <= Z.last[rz]; ++ez)
-        for (int ey = Y.first[ry]; ey <= Y.last[ry]; ++ey)
-            for (int ex = X.first[rx]; ex <= X.last[rx]; ++ex)
-                acc += s.elem[((size_t)ez * Y.ne + ey) * X.ne + ex];
-    s.rows[idx] = acc;
+    for (int e0 = f; e0 <= l; e0 += 4) {   // four loads in flight, then the sums in order
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = e0 + k <= l ? src[(size_t)(e0 + k) * ninner] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (e0 + k <= l) acc += v[k];
+    }
+    out[idx] = acc;
 }
 
 // Galerkin step 1: E_{e,a} = sum_q W_q B_{e+a}(x_q) f_q for the np1^dim local tests a.
