@@ -518,7 +518,10 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
             inner *= (size_t)x.R;
         }
     } else {
-        hipLaunchKernelGGL(iga::gal_src_elem_kernel, dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        if (c->p == 2)
+            hipLaunchKernelGGL(iga::gal_src_elem_kernel<2>, dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        else
+            hipLaunchKernelGGL(iga::gal_src_elem_kernel<3>, dim3(ge), dim3(kBlock), 0, s, sa, nel);
         hipLaunchKernelGGL(iga::gal_src_rows_kernel, dim3(gr), dim3(kBlock), 0, s, sa, nr);
     }
     IGA_HIP(hipGetLastError());

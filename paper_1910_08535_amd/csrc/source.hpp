@@ -34,7 +34,7 @@ __device__ __forceinline__ double wbasis(const SrcAxis& A, int e, int q, int a)
 struct SrcArgs {
     SrcAxis ax[3];            // axes beyond dim: ne = nq = np1 = R = 1, unit tables
     const double* table;      // (ne_z nq_z, ne_y nq_y, ne_x nq_x)
-    double* elem;             // PG: [n_el]; Galerkin: [n_el * np1^3]
+    double* elem;             // PG: [n_el] (then span sums); Galerkin: [np1^d][n_el]
     double* rows;             // (R_z, R_y, R_x)
 };
 
@@ -159,32 +159,76 @@ __global__ __launch_bounds__(kBlock) void src_span_sum_kernel(const double* __re
     out[idx] = acc;
 }
 
-// Galerkin step 1: E_{e,a} = sum_q W_q B_{e+a}(x_q) f_q for the np1^dim local tests a.
-__global__ void gal_src_elem_kernel(SrcArgs s, size_t nel)
+// Galerkin step 1: E_{e,a} = sum_q W_q B_{e+a}(x_q) f_q for the np1^dim local tests a,
+// by sum factorization over the element's Gauss points:
+//   tx[ax]          = sum_qx  W_x B_{ax}(x_qx) f_(qz,qy,qx)
+//   sy[ay][ax]      = sum_qy  W_y B_{ay}(y_qy) tx[ax]
+//   E[az][ay][ax]   = sum_qz  W_z B_{az}(z_qz) sy[ay][ax]
+// (nq^d (p+1) + nq^(d-1) (p+1)^2 + ... products instead of nq^d (p+1)^d; the table is read
+// once per element).  P: the degree of the mesh; axes beyond dim have one local function.
+template <int P>
+__global__ __launch_bounds__(kBlock) void gal_src_elem_kernel(SrcArgs s, size_t nel)
 {
+    constexpr int Q = P + 1;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nel) return;
     int e[3];
     elem_index(s, idx, e);
     const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
+    const int nx = X.np1, ny = Y.np1, nz = Z.np1;   // Q or 1
     const size_t gx0 = (size_t)e[0] * X.nq, gy0 = (size_t)e[1] * Y.nq, gz0 = (size_t)e[2] * Z.nq;
     const size_t ngx = (size_t)X.ne * X.nq, ngy = (size_t)Y.ne * Y.nq;
-    const int nloc = X.np1 * Y.np1 * Z.np1;
-    for (int a = 0; a < nloc; ++a) {
-        const int ax = a % X.np1, ay = (a / X.np1) % Y.np1, az = a / (X.np1 * Y.np1);
-        double acc = 0.0;
-        for (int qz = 0; qz < Z.nq; ++qz)
-            for (int qy = 0; qy < Y.nq; ++qy) {
-                const double tz = wbasis(Z, e[2], qz, az);
-                const double ty = wbasis(Y, e[1], qy, ay);
-                const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0;
-                double t = 0.0;
-                for (int qx = 0; qx < X.nq; ++qx)
-                    t = fma(wbasis(X, e[0], qx, ax), row[qx], t);
-                acc = fma(tz * ty, t, acc);
+    double acc[Q][Q][Q];
+#pragma unroll
+    for (int az = 0; az < Q; ++az)
+#pragma unroll
+        for (int ay = 0; ay < Q; ++ay)
+#pragma unroll
+            for (int ax = 0; ax < Q; ++ax) acc[az][ay][ax] = 0.0;
+    for (int qz = 0; qz < Z.nq; ++qz) {
+        double sy[Q][Q];
+#pragma unroll
+        for (int ay = 0; ay < Q; ++ay)
+#pragma unroll
+            for (int ax = 0; ax < Q; ++ax) sy[ay][ax] = 0.0;
+        for (int qy = 0; qy < Y.nq; ++qy) {
+            const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0;
+            double tx[Q];
+#pragma unroll
+            for (int ax = 0; ax < Q; ++ax) tx[ax] = 0.0;
+            for (int qx = 0; qx < X.nq; ++qx) {
+                const double f = row[qx];
+#pragma unroll
+                for (int ax = 0; ax < Q; ++ax)
+                    if (ax < nx) tx[ax] = fma(wbasis(X, e[0], qx, ax), f, tx[ax]);
             }
-        s.elem[idx * nloc + a] = acc;
+#pragma unroll
+            for (int ay = 0; ay < Q; ++ay) {
+                if (ay >= ny) break;
+                const double ty = wbasis(Y, e[1], qy, ay);
+#pragma unroll
+                for (int ax = 0; ax < Q; ++ax) sy[ay][ax] = fma(ty, tx[ax], sy[ay][ax]);
+            }
+        }
+#pragma unroll
+        for (int az = 0; az < Q; ++az) {
+            if (az >= nz) break;
+            const double tz = wbasis(Z, e[2], qz, az);
+#pragma unroll
+            for (int ay = 0; ay < Q; ++ay)
+#pragma unroll
+                for (int ax = 0; ax < Q; ++ax) acc[az][ay][ax] = fma(tz, sy[ay][ax], acc[az][ay][ax]);
+        }
     }
+    // one array per local test (element fastest): neighbouring threads store, and the
+    // gather reads, neighbouring addresses
+#pragma unroll
+    for (int az = 0; az < Q; ++az)
+#pragma unroll
+        for (int ay = 0; ay < Q; ++ay)
+#pragma unroll
+            for (int ax = 0; ax < Q; ++ax)
+                if (az < nz && ay < ny && ax < nx) s.elem[(size_t)((az * ny + ay) * nx + ax) * nel + idx] = acc[az][ay][ax];
 }
 
 // Galerkin step 2: F_i = sum over the elements e = i - a (a local index per axis).
@@ -196,7 +240,7 @@ __global__ void gal_src_rows_kernel(SrcArgs s, size_t nrows)
     const int ix = (int)(idx % X.R);
     const int iy = (int)((idx / X.R) % Y.R);
     const int iz = (int)(idx / ((size_t)X.R * Y.R));
-    const int nloc = X.np1 * Y.np1 * Z.np1;
+    const size_t nel = (size_t)X.ne * Y.ne * Z.ne;
     double acc = 0.0;
     for (int az = 0; az < Z.np1; ++az) {
         const int ez = iz - az;
@@ -208,7 +252,7 @@ __global__ void gal_src_rows_kernel(SrcArgs s, size_t nrows)
                 const int ex = ix - ax;
                 if (ex < 0 || ex >= X.ne) continue;
                 const size_t el = ((size_t)ez * Y.ne + ey) * X.ne + ex;
-                acc += s.elem[el * nloc + (az * Y.np1 + ay) * X.np1 + ax];
+                acc += s.elem[(size_t)((az * Y.np1 + ay) * X.np1 + ax) * nel + el];
             }
         }
     }
