@@ -518,11 +518,20 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
             inner *= (size_t)x.R;
         }
     } else {
-        if (c->p == 2)
-            hipLaunchKernelGGL(iga::gal_src_elem_kernel<2>, dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        // the common rules (x and y alike) with their table values loaded a plane at a time
+        const int nq = sa.ax[0].nq == sa.ax[1].nq ? sa.ax[0].nq : 0;
+        if (c->p == 2 && nq == 3)
+            hipLaunchKernelGGL((iga::gal_src_elem_kernel<2, 3>), dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        else if (c->p == 3 && nq == 4)
+            hipLaunchKernelGGL((iga::gal_src_elem_kernel<3, 4>), dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        else if (c->p == 2)
+            hipLaunchKernelGGL((iga::gal_src_elem_kernel<2, 0>), dim3(ge), dim3(kBlock), 0, s, sa, nel);
         else
-            hipLaunchKernelGGL(iga::gal_src_elem_kernel<3>, dim3(ge), dim3(kBlock), 0, s, sa, nel);
-        hipLaunchKernelGGL(iga::gal_src_rows_kernel, dim3(gr), dim3(kBlock), 0, s, sa, nr);
+            hipLaunchKernelGGL((iga::gal_src_elem_kernel<3, 0>), dim3(ge), dim3(kBlock), 0, s, sa, nel);
+        if (c->p == 2)
+            hipLaunchKernelGGL(iga::gal_src_rows_kernel<2>, dim3(gr), dim3(kBlock), 0, s, sa, nr);
+        else
+            hipLaunchKernelGGL(iga::gal_src_rows_kernel<3>, dim3(gr), dim3(kBlock), 0, s, sa, nr);
     }
     IGA_HIP(hipGetLastError());
     return IGA_OK;

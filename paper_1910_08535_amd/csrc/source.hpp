@@ -166,16 +166,37 @@ __global__ __launch_bounds__(kBlock) void src_span_sum_kernel(const double* __re
 //   E[az][ay][ax]   = sum_qz  W_z B_{az}(z_qz) sy[ay][ax]
 // (nq^d (p+1) + nq^(d-1) (p+1)^2 + ... products instead of nq^d (p+1)^d; the table is read
 // once per element).  P: the degree of the mesh; axes beyond dim have one local function.
-template <int P>
+// NQ > 0: x and y both have NQ Gauss points, and the NQ x NQ table values of a z-plane of
+// the element are loaded together before they are used (one wait per plane); NQ = 0:
+// any rule, loops bounded at run time.
+// The products W_q B_{e+a}(x_q) of every element class of the three axes are staged in
+// LDS once per workgroup ([axis][class][q][a]); a thread reads those of its element's
+// classes.
+template <int P, int NQ>
 __global__ __launch_bounds__(kBlock) void gal_src_elem_kernel(SrcArgs s, size_t nel)
 {
     constexpr int Q = P + 1;
+    constexpr int kAxisW = (2 * kMaxP + 1) * kMaxNq * (kMaxP + 1);
+    __shared__ double wt[3 * kAxisW];
+    for (int a = 0; a < 3; ++a) {
+        const SrcAxis& A = s.ax[a];
+        const int n = n_classes(A.p, A.ne) * A.nq * A.np1;
+        for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+            const int j = i % A.np1, q = (i / A.np1) % A.nq, c = i / (A.np1 * A.nq);
+            wt[a * kAxisW + i] = A.gw[q] * A.cls[(((size_t)c * A.nq + q) * 3) * A.np1 + j];
+        }
+    }
+    __syncthreads();
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nel) return;
     int e[3];
     elem_index(s, idx, e);
     const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
     const int nx = X.np1, ny = Y.np1, nz = Z.np1;   // Q or 1
+    // this element's rows of the staged products: [q][a]
+    const double* const wx = wt + (size_t)class_of(e[0], X.p, X.ne) * X.nq * nx;
+    const double* const wy = wt + kAxisW + (size_t)class_of(e[1], Y.p, Y.ne) * Y.nq * ny;
+    const double* const wz = wt + 2 * kAxisW + (size_t)class_of(e[2], Z.p, Z.ne) * Z.nq * nz;
     const size_t gx0 = (size_t)e[0] * X.nq, gy0 = (size_t)e[1] * Y.nq, gz0 = (size_t)e[2] * Z.nq;
     const size_t ngx = (size_t)X.ne * X.nq, ngy = (size_t)Y.ne * Y.nq;
     double acc[Q][Q][Q];
@@ -191,21 +212,36 @@ __global__ __launch_bounds__(kBlock) void gal_src_elem_kernel(SrcArgs s, size_t 
         for (int ay = 0; ay < Q; ++ay)
 #pragma unroll
             for (int ax = 0; ax < Q; ++ax) sy[ay][ax] = 0.0;
-        for (int qy = 0; qy < Y.nq; ++qy) {
+        constexpr int NF = NQ > 0 ? NQ * NQ : 1;
+        double fp[NF];   // NQ > 0: the plane's table values
+        if constexpr (NQ > 0) {
+#pragma unroll
+            for (int qy = 0; qy < NQ; ++qy)
+#pragma unroll
+                for (int qx = 0; qx < NQ; ++qx)
+                    fp[qy * NQ + qx] = s.table[((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0 + qx];
+        }
+#pragma unroll
+        for (int qy = 0; qy < (NQ > 0 ? NQ : Y.nq); ++qy) {
             const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + gx0;
             double tx[Q];
 #pragma unroll
             for (int ax = 0; ax < Q; ++ax) tx[ax] = 0.0;
-            for (int qx = 0; qx < X.nq; ++qx) {
-                const double f = row[qx];
+#pragma unroll
+            for (int qx = 0; qx < (NQ > 0 ? NQ : X.nq); ++qx) {
+                double f;
+                if constexpr (NQ > 0)
+                    f = fp[qy * NQ + qx];
+                else
+                    f = row[qx];
 #pragma unroll
                 for (int ax = 0; ax < Q; ++ax)
-                    if (ax < nx) tx[ax] = fma(wbasis(X, e[0], qx, ax), f, tx[ax]);
+                    if (ax < nx) tx[ax] = fma(wx[qx * nx + ax], f, tx[ax]);
             }
 #pragma unroll
             for (int ay = 0; ay < Q; ++ay) {
                 if (ay >= ny) break;
-                const double ty = wbasis(Y, e[1], qy, ay);
+                const double ty = wy[qy * ny + ay];
 #pragma unroll
                 for (int ax = 0; ax < Q; ++ax) sy[ay][ax] = fma(ty, tx[ax], sy[ay][ax]);
             }
@@ -213,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void gal_src_elem_kernel(SrcArgs s, size_t 
 #pragma unroll
         for (int az = 0; az < Q; ++az) {
             if (az >= nz) break;
-            const double tz = wbasis(Z, e[2], qz, az);
+            const double tz = wz[qz * nz + az];
 #pragma unroll
             for (int ay = 0; ay < Q; ++ay)
 #pragma unroll
@@ -231,9 +267,13 @@ __global__ __launch_bounds__(kBlock) void gal_src_elem_kernel(SrcArgs s, size_t 
                 if (az < nz && ay < ny && ax < nx) s.elem[(size_t)((az * ny + ay) * nx + ax) * nel + idx] = acc[az][ay][ax];
 }
 
-// Galerkin step 2: F_i = sum over the elements e = i - a (a local index per axis).
-__global__ void gal_src_rows_kernel(SrcArgs s, size_t nrows)
+// Galerkin step 2: F_i = sum over the elements e = i - a (a local index per axis), the
+// terms in the order (az, ay, ax); all loads of a row are issued before the sums.
+// P: the degree of the mesh (axes beyond dim have one local function).
+template <int P>
+__global__ __launch_bounds__(kBlock) void gal_src_rows_kernel(SrcArgs s, size_t nrows)
 {
+    constexpr int Q = P + 1;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nrows) return;
     const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
@@ -241,21 +281,32 @@ __global__ void gal_src_rows_kernel(SrcArgs s, size_t nrows)
     const int iy = (int)((idx / X.R) % Y.R);
     const int iz = (int)(idx / ((size_t)X.R * Y.R));
     const size_t nel = (size_t)X.ne * Y.ne * Z.ne;
-    double acc = 0.0;
-    for (int az = 0; az < Z.np1; ++az) {
-        const int ez = iz - az;
-        if (ez < 0 || ez >= Z.ne) continue;
-        for (int ay = 0; ay < Y.np1; ++ay) {
-            const int ey = iy - ay;
-            if (ey < 0 || ey >= Y.ne) continue;
-            for (int ax = 0; ax < X.np1; ++ax) {
-                const int ex = ix - ax;
-                if (ex < 0 || ex >= X.ne) continue;
-                const size_t el = ((size_t)ez * Y.ne + ey) * X.ne + ex;
-                acc += s.elem[(size_t)((az * Y.np1 + ay) * X.np1 + ax) * nel + el];
+    double v[Q][Q][Q];
+#pragma unroll
+    for (int az = 0; az < Q; ++az)
+#pragma unroll
+        for (int ay = 0; ay < Q; ++ay)
+#pragma unroll
+            for (int ax = 0; ax < Q; ++ax) {
+                const int ez = iz - az, ey = iy - ay, ex = ix - ax;
+                const bool ok = az < Z.np1 && ay < Y.np1 && ax < X.np1 && ez >= 0 && ez < Z.ne && ey >= 0 &&
+                                ey < Y.ne && ex >= 0 && ex < X.ne;
+                v[az][ay][ax] = ok ? s.elem[(size_t)((az * Y.np1 + ay) * X.np1 + ax) * nel +
+                                            ((size_t)ez * Y.ne + ey) * X.ne + ex]
+                                   : 0.0;
             }
-        }
-    }
+    double acc = 0.0;
+#pragma unroll
+    for (int az = 0; az < Q; ++az)
+#pragma unroll
+        for (int ay = 0; ay < Q; ++ay)
+#pragma unroll
+            for (int ax = 0; ax < Q; ++ax) {
+                const int ez = iz - az, ey = iy - ay, ex = ix - ax;
+                if (az < Z.np1 && ay < Y.np1 && ax < X.np1 && ez >= 0 && ez < Z.ne && ey >= 0 && ey < Y.ne &&
+                    ex >= 0 && ex < X.ne)
+                    acc += v[az][ay][ax];
+            }
     s.rows[idx] = acc;
 }
 
