@@ -627,7 +627,10 @@ def run_reduced(args) -> dict:
     Times rhs(PG, u, alpha = beta = gamma = 1, f_table) per rule for 2D 1024^2, p = 2 and
     3D 128^3, p = 3, HIP events on the mesh's stream; the tables (seeded uniform values
     in [-1, 1)) are used in turn, enough of them to exceed 600 MB, so each call reads its
-    table from HBM.  Algorithmic bytes: the table, u and the output rows."""
+    table from HBM.  Algorithmic bytes: the table, u and the output rows.  Beside it, the
+    source rows alone (gamma = 1, no u) in the PG form and, with the (p+1)-point rule, in
+    the Galerkin form (test functions evaluated at every Gauss point): the generation
+    cost of the two methods on the same table (Table 1's comparison)."""
     import math
     import torch
     from paper_1910_08535_amd import iga, inputs
@@ -648,20 +651,29 @@ def run_reduced(args) -> dict:
             gen.manual_seed(7)
             tabs = [torch.empty(shape, dtype=torch.float64, device="cuda").uniform_(-1.0, 1.0, generator=gen)
                     for _ in range(max(1, math.ceil(600e6 / tbytes)))]
-            b = torch.empty(mesh.shape(iga.PG), dtype=torch.float64, device="cuda")
-            for t in tabs[:2]:
-                mesh.rhs(iga.PG, u, 1.0, 1.0, 1.0, f_table=t, out=b)
             reps = max(10, len(tabs))
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for i in range(reps):
-                mesh.rhs(iga.PG, u, 1.0, 1.0, 1.0, f_table=tabs[i % len(tabs)], out=b)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) * 1e3 / reps
-            nbytes = tbytes + u.numel() * 8 + b.numel() * 8
-            case[f"nq{nq}"] = {"us_rhs": us, "table_bytes": tbytes, "algorithmic_bytes": nbytes,
-                               "GBs": nbytes / us * 1e-3, "hbm_frac": nbytes / us * 1e-3 / 8000.0}
+
+            def timed(form, uu, alpha, beta):
+                b = torch.empty(mesh.shape(form), dtype=torch.float64, device="cuda")
+                for t in tabs[:2]:
+                    mesh.rhs(form, uu, alpha, beta, 1.0, f_table=t, out=b)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for i in range(reps):
+                    mesh.rhs(form, uu, alpha, beta, 1.0, f_table=tabs[i % len(tabs)], out=b)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) * 1e3 / reps, b.numel()
+
+            us, nrow = timed(iga.PG, u, 1.0, 1.0)
+            nbytes = tbytes + u.numel() * 8 + nrow * 8
+            rec = {"us_rhs": us, "table_bytes": tbytes, "algorithmic_bytes": nbytes,
+                   "GBs": nbytes / us * 1e-3, "hbm_frac": nbytes / us * 1e-3 / 8000.0,
+                   "us_source_only": timed(iga.PG, None, 0.0, 0.0)[0]}
+            if nq == p + 1:
+                rec["us_source_only_galerkin"] = timed(iga.GALERKIN_BYPARTS, None, 0.0, 0.0)[0]
+                rec["galerkin_over_pg_source"] = rec["us_source_only_galerkin"] / rec["us_source_only"]
+            case[f"nq{nq}"] = rec
             del tabs
             mesh.close()
         case["speedup_2pt"] = case[f"nq{p + 1}"]["us_rhs"] / case["nq2"]["us_rhs"]
