@@ -98,6 +98,18 @@ def _per_dispatch(csv_path: str, counter: str, grid: str = ""):
     return vals
 
 
+def _probe_value(csv_path: str, counter: str, first: int = 8) -> float:
+    """The counter of the copy probe: the largest value among the copy dispatches in the
+    first `first` dispatches of the run (bench.py --copy-probe-mb runs the probe before
+    anything else; later copies or fills of other sizes are not it)."""
+    rows = [r for r in csv.DictReader(open(csv_path)) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    vals = [float(r["Counter_Value"]) for r in rows[:first] if "copy" in r["Kernel_Name"].lower()]
+    if not vals:
+        raise SystemExit(f"no copy dispatch among the first {first} of {csv_path}")
+    return max(vals)
+
+
 def _family(kernel: str) -> str:
     for k in KERNEL_SOURCES:
         if k in kernel:
@@ -112,8 +124,6 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, worklo
     shape most dispatches have)."""
     kernel, _, grid = kernel.partition("@")
     grid = grid or _common_grid([fetch_csv], kernel)
-    fetch_all = _per_dispatch(fetch_csv, "FETCH_SIZE")
-    write_all = _per_dispatch(write_csv, "WRITE_SIZE")
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE", grid)
     write = _per_dispatch(write_csv, "WRITE_SIZE", grid)
 
@@ -124,9 +134,8 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, worklo
         return keys[0], vals[keys[0]]
 
     copy_bytes = copy_mib * 2**20
-    # the copy kernel is the largest-traffic elementwise kernel of the probe
-    cf = max(v for k, vs in fetch_all.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
-    cw = max(v for k, vs in write_all.items() if "elementwise" in k or "copy" in k.lower() for v in vs)
+    cf = _probe_value(fetch_csv, "FETCH_SIZE")
+    cw = _probe_value(write_csv, "WRITE_SIZE")
     f_scale = copy_bytes / (cf * 1024.0)
     w_scale = copy_bytes / (cw * 1024.0)
     kf, fv = pick(fetch, kernel)
