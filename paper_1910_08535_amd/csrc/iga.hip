@@ -483,12 +483,33 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
     const unsigned ge = (unsigned)((nel + kBlock - 1) / kBlock);
     const unsigned gr = (unsigned)((nr + kBlock - 1) / kBlock);
     if (form == IGA_PG) {
-        // element sums into A
         const iga::SrcAxis& X = sa.ax[0];
         const size_t others = nel / (size_t)X.ne;
         auto units = [&](int e) { return (size_t)((X.ne + e - 1) / e) * others; };
         auto blocks = [](size_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
-        if (X.nq == 2)
+        const size_t A = nscr - (c->dim >= 2 ? others * (size_t)X.R : 0);
+        double* const bufA = c->elem;
+        double* const bufB = c->elem + A;
+        // support spans and a 2- or 3-point rule along x: element sums and x-span sums in one
+        // pass into B (into farr in 1D); otherwise the element sums into A and every axis in a
+        // pass (with 4 points, two elements per lane hold too many loads at too low an
+        // occupancy: the separate passes are faster)
+        const bool fused = c->spans == IGA_SPANS_SUPPORT && (X.nq == 2 || X.nq == 3);
+        if (fused) {
+            const int S = 128 - c->p;
+            const int wpl = (X.R + S - 1) / S;
+            const size_t nw = (size_t)wpl * others;
+            double* const xo = c->dim == 1 ? c->farr : bufB;
+            const dim3 gx((unsigned)((nw * 64 + kBlock - 1) / kBlock));
+#define IGA_SRC_X(NQ, P)                                                                                      \
+    hipLaunchKernelGGL((iga::pg_src_elem_x_kernel<NQ, P>), gx, dim3(kBlock), 0, s, sa, xo, wpl, nw)
+            if (c->p == 2) {
+                if (X.nq == 2) IGA_SRC_X(2, 2); else IGA_SRC_X(3, 2);
+            } else {
+                if (X.nq == 2) IGA_SRC_X(2, 3); else IGA_SRC_X(3, 3);
+            }
+#undef IGA_SRC_X
+        } else if (X.nq == 2)
             hipLaunchKernelGGL(iga::pg_src_elem_vec_kernel<2>, blocks(units(1)), dim3(kBlock), 0, s, sa, units(1));
         else if (X.nq == 3)
             hipLaunchKernelGGL(iga::pg_src_elem_vec_kernel<3>, blocks(units(2)), dim3(kBlock), 0, s, sa, units(2));
@@ -496,13 +517,11 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
             hipLaunchKernelGGL(iga::pg_src_elem_vec_kernel<4>, blocks(units(1)), dim3(kBlock), 0, s, sa, units(1));
         else
             hipLaunchKernelGGL(iga::pg_src_elem_kernel, dim3(ge), dim3(kBlock), 0, s, sa, nel);
-        // span sums along x, y, z: A -> B -> A -> farr, the last pass into farr
-        const size_t A = nscr - (c->dim >= 2 ? others * (size_t)X.R : 0);
-        double* const bufA = c->elem;
-        double* const bufB = c->elem + A;
-        const double* in = bufA;
-        size_t outer = nel, inner = 1;
-        for (int a = 0; a < c->dim; ++a) {
+        // span sums along x, y, z: A -> B -> A -> farr, the last pass into farr (from y on
+        // when x was fused with the element sums)
+        const double* in = fused ? bufB : bufA;
+        size_t outer = fused ? others : nel, inner = fused ? (size_t)X.R : 1;
+        for (int a = fused ? 1 : 0; a < c->dim; ++a) {
             const iga::SrcAxis& x = sa.ax[a];
             outer /= (size_t)x.ne;
             double* const out = a == c->dim - 1 ? c->farr : (a == 0 ? bufB : bufA);

@@ -126,6 +126,91 @@ __global__ __launch_bounds__(kBlock) void pg_src_elem_vec_kernel(SrcArgs s, size
     if (E == 2 && full) s.elem[e0 + 1] = acc[E - 1];
 }
 
+// PG steps 1 and 2 along x in one pass, for support spans (every span inside
+// [r - P, r]): the lanes of a wave hold the element sums of 128 consecutive elements of an
+// x-line (two per lane, the same sums in the same order as pg_src_elem_vec_kernel) and
+// form the span sums of the 128 - P rows whose spans lie among them from their own and
+// their right neighbours' values (cross-lane shuffles, each sum in ascending element
+// order, as src_span_sum_kernel forms it); consecutive waves of a line overlap by P
+// elements.  out[line][rx] with line = ez ne_y + ey: the x-pass sums, or F_r in 1D.
+// wpl: waves per x-line, ceil(R_x / (128 - P)); nwaves: wpl times the lines.
+template <int NQ, int P>
+__global__ __launch_bounds__(kBlock) void pg_src_elem_x_kernel(SrcArgs s, double* __restrict__ out, int wpl,
+                                                               size_t nwaves)
+{
+    constexpr int E = 2;                   // elements per lane
+    constexpr int S = 64 * E - P;          // rows per wave
+    constexpr int K = (P + E - 1) / E + 1; // lanes whose values a row may need (itself and K-1 more)
+    const size_t gw = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (gw >= nwaves) return;   // whole waves
+    const int lane = (int)(threadIdx.x & 63);
+    const SrcAxis &X = s.ax[0], &Y = s.ax[1], &Z = s.ax[2];
+    const int w = (int)(gw % (size_t)wpl);
+    const size_t line = gw / (size_t)wpl;
+    const int ey = (int)(line % (size_t)Y.ne), ez = (int)(line / (size_t)Y.ne);
+    const int e0 = w * S - P + lane * E;   // this lane's first element
+    double wx[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) wx[q] = X.gw[q];
+    const size_t ngx = (size_t)X.ne * NQ, ngy = (size_t)Y.ne * Y.nq;
+    const size_t gy0 = (size_t)ey * Y.nq, gz0 = (size_t)ez * Z.nq;
+    const bool full = e0 >= 0 && e0 + E <= X.ne;
+    bool ok[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) ok[j] = e0 + j >= 0 && e0 + j < X.ne;
+    double acc[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j] = 0.0;
+    if (ok[0] || ok[E - 1]) {
+        for (int qz = 0; qz < Z.nq; ++qz) {
+#pragma unroll 4
+            for (int qy = 0; qy < Y.nq; ++qy) {
+                const double wyz = Z.gw[qz] * Y.gw[qy];
+                const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx;
+                double v[E * NQ];
+                if (full) {
+#pragma unroll
+                    for (int k = 0; k < NQ; ++k) {
+                        const src_pair pr = *reinterpret_cast<const src_pair*>(row + (size_t)e0 * NQ + 2 * k);
+                        v[2 * k] = pr.x;
+                        v[2 * k + 1] = pr.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < E; ++j)
+#pragma unroll
+                        for (int k = 0; k < NQ; ++k) v[j * NQ + k] = ok[j] ? row[(size_t)(e0 + j) * NQ + k] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    double tt = 0.0;
+#pragma unroll
+                    for (int qx = 0; qx < NQ; ++qx) tt = fma(wx[qx], v[j * NQ + qx], tt);
+                    acc[j] = fma(wyz, tt, acc[j]);
+                }
+            }
+        }
+    }
+    // the values of this lane and the next K-1: element e0 + o at nb[o]
+    double nb[K * E];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int j = 0; j < E; ++j) nb[k * E + j] = k == 0 ? acc[j] : __shfl_down(acc[j], (unsigned)k);
+    double* const orow = out + line * (size_t)X.R;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int rx = w * S + lane * E + j;   // its span lies in elements e0 + j .. e0 + j + P
+        if (lane * E + j >= S || rx >= X.R) continue;
+        const int f = X.first[rx], l = X.last[rx];
+        double sum = 0.0;
+#pragma unroll
+        for (int o = j; o <= j + P; ++o)
+            if (e0 + o >= f && e0 + o <= l) sum += nb[o];
+        orow[rx] = sum;
+    }
+}
+
 // PG step 2, one axis at a time (the tensor span is a product of per-axis spans):
 //   out[o][r][i] = sum_{e = first[r]}^{last[r]} in[o][e][i]
 // for o < nouter, r < nout, i < ninner, in holding nin entries along the axis.  Applied

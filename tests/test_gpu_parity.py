@@ -154,6 +154,44 @@ def test_custom_spans_2d(iga, orc):
     assert relerr(host(l), orc.rhs(pb, 2, u, beta=1.0)) <= TOL
 
 
+def _custom_spans(p, ne, seed):
+    """Random sub-spans of every row's support (first and last element per axis)."""
+    rng = np.random.default_rng(seed)
+    sp = []
+    for n in ne:
+        first, last = [], []
+        for r in range(n + p):
+            lo_, hi_ = max(0, r - p), min(n - 1, r)
+            a = int(rng.integers(lo_, hi_ + 1))
+            first.append(a)
+            last.append(int(rng.integers(a, hi_ + 1)))
+        sp.append((np.array(first), np.array(last)))
+    return sp
+
+
+@pytest.mark.parametrize("spans", ["element", "custom", "support"])
+@pytest.mark.parametrize("nq", [2, 3, 4])
+def test_pg_table_source_spans(iga, orc, spans, nq):
+    """PG right-hand side with a Gauss-point source on every span kind and rule: support
+    spans with 2 or 3 points take the fused element and x-span kernel, the others the
+    element sums and one span pass per axis; an odd x-line length leaves a lone element
+    at the end of each line."""
+    p, ne = 2, (45, 30)
+    sp = _custom_spans(p, ne, 9) if spans == "custom" else spans
+    mesh = iga.Mesh(2, p, ne, (nq, nq), spans=sp)
+    if spans == "custom":
+        pb = orc.Problem(dim=2, p=p, ne=ne, nq=(nq, nq), custom_spans=sp)
+    else:
+        pb = orc.Problem(dim=2, p=p, ne=ne, nq=(nq, nq), span_kind=spans)
+    u = inputs.normal_coefs(ne, p, seed=41)
+    tab = inputs.uniform_table(inputs.gauss_shape(ne, (nq, nq)), seed=42)
+    got = host(mesh.rhs(iga.PG, cuda(u), 0.5, 0.25, 1.0, f_table=cuda(tab)))
+    assert relerr(got, orc.rhs(pb, orc.PG, u, 0.5, 0.25, 1.0, f_table=tab)) <= TOL, (spans, nq)
+    got = host(mesh.rhs(iga.PG, None, gamma=1.0, f_table=cuda(tab)))
+    assert relerr(got, orc.rhs(pb, orc.PG, None, gamma=1.0, f_table=tab)) <= TOL, (spans, nq)
+    mesh.close()
+
+
 @pytest.mark.parametrize("dim,p,ne", [(1, 2, (500,)), (2, 3, (40, 31)), (3, 3, (20, 17, 23)),
                                       (3, 2, (16, 16, 16))])
 @pytest.mark.parametrize("nsteps", [1, 2, 5])
