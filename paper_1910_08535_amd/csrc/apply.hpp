@@ -249,10 +249,13 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     }
     // band rows of the chunk: cy[j*CW + k]; every lane loads from each table with the
     // offset of the table that holds value k (the others read 0 out of bounds)
+    // kDma (below): the band rows are stored after the input rows are issued, so that no
+    // load waits for another
+    constexpr bool kDma = VEC && (P % 2) == 0;
+    double cv[NCV];
     {
         const auto rym = buf(Y.M, (size_t)Y.R * W), ryd = buf(Y.D, (size_t)Y.R * W);
         const auto rys = buf(Y.S, Y.R), ryf = buf(Y.F, Y.R);
-        double cv[NCV];
 #pragma unroll
         for (int c = 0; c < NCV; ++c) {
             const int i = lane + 64 * c;
@@ -265,8 +268,10 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
             const unsigned of = ok && k == 2 * W + 1 ? (unsigned)yr * 8u : kOOB;
             cv[c] = bload(rym, om) + bload(ryd, od) + bload(rys, os) + bload(ryf, of);
         }
+        if constexpr (!kDma) {
 #pragma unroll
-        for (int c = 0; c < NCV; ++c) cy[lane + 64 * c] = cv[c];
+            for (int c = 0; c < NCV; ++c) cy[lane + 64 * c] = cv[c];
+        }
     }
 
     // 1. input rows (issued after the band loads: the memory counter retires in
@@ -274,13 +279,20 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     const auto ru = buf(g.u, (size_t)Nx * Ny);
     const int ch = lane < P ? x0 - P + lane : x0 + SW + lane - P;
     const bool ok0 = c0 < Nx, ok1 = c0 + 1 < Nx, okh = lane < 2 * P && ch >= 0 && ch < Nx;
-    double v0[NR], v1[NR], vh[NR];
+    // kDma: rows of even length with an even halo width: each lane's pair goes from memory
+    // straight into its 16-byte LDS slot (buffer load to LDS; lane l writes 16 bytes at the
+    // row's slot P + 2l, out-of-range lanes write zeros), so the rows hold no registers
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    double v0[kDma ? 1 : NR], v1[kDma ? 1 : NR], vh[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         const int yi = y0 - P + i;
         const bool rowok = yi >= 0 && yi < Ny;
         const unsigned rowoff = (unsigned)yi * (unsigned)Nx;
-        if constexpr (VEC) {   // rows of even length: the lane's pair is 16-byte aligned
+        if constexpr (kDma) {
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ru, (lds_ptr)&rb[i][P], 16,
+                                                     rowok && ok0 ? (rowoff + c0) * 8u : kOOB, 0, 0, 0);
+        } else if constexpr (VEC) {   // rows of even length: the lane's pair is 16-byte aligned
             const dv2 v = bload2(ru, rowok && ok0 ? (rowoff + c0) * 8u : kOOB);
             v0[i] = v.x;
             v1[i] = v.y;
@@ -303,13 +315,20 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     const auto rf = buf(g.farr, (MODE & kFarr) ? (size_t)X.R * Y.R : 0);
     const bool okc0 = xr0 < X.R, okc1 = xr1 < X.R;
     double ra0[W], rb0[W], ra1[W], rb1[W];
+    if constexpr (kDma) {
+#pragma unroll
+        for (int c = 0; c < NCV; ++c) cy[lane + 64 * c] = cv[c];
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): every row is in LDS
+    }
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         // 2. row i into LDS as soon as its loads are in (later rows keep loading while
         //    this one is computed and stored); LDS operations of one wave execute in
         //    order, the fence only keeps the compiler from reordering them
-        rb[i][P + 2 * lane] = v0[i];
-        rb[i][P + 2 * lane + 1] = v1[i];
+        if constexpr (!kDma) {
+            rb[i][P + 2 * lane] = v0[i];
+            rb[i][P + 2 * lane + 1] = v1[i];
+        }
         rb[i][hidx] = vh[i];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
