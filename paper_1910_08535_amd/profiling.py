@@ -118,10 +118,11 @@ def _family(kernel: str) -> str:
 
 
 def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, workload: str,
-            commands: str) -> dict:
+            commands: str, out_dir: str = "") -> dict:
     """HBM bytes per launch of `kernel` ("name" or "name@grid size", the grid size in
     threads picking one launch shape of a kernel that runs at several; without one, the
-    shape most dispatches have)."""
+    shape most dispatches have), written to traffic_<workload>.json in out_dir (default
+    profiles/)."""
     kernel, _, grid = kernel.partition("@")
     grid = grid or _common_grid([fetch_csv], kernel)
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE", grid)
@@ -150,7 +151,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_mib: float, worklo
            "bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "family": _family(kernel), "kernel_source_hash": kernel_source_hash(_family(kernel)),
            "commands": commands}
-    out = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_{workload}.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
