@@ -192,6 +192,23 @@ def test_pg_table_source_spans(iga, orc, spans, nq):
     mesh.close()
 
 
+@pytest.mark.parametrize("p,nq,ne", [
+    (2, 3, (1,)), (3, 2, (2,)), (2, 2, (1, 1)), (3, 3, (2, 1, 3)),
+    (2, 3, (124, 3)), (2, 3, (125, 2)), (3, 2, (125, 3)), (3, 3, (126, 2, 2)),
+])
+def test_pg_table_source_line_edges(iga, orc, p, nq, ne):
+    """PG Gauss-table source rows (support spans) at the edges of the fused element and
+    x-span kernel: lines of one or two elements, and x-lines whose 128 - p rows per wave
+    end exactly at, or one row past, a wave."""
+    dim = len(ne)
+    mesh = iga.Mesh(dim, p, ne, (nq,) * dim)
+    pb = orc.Problem(dim=dim, p=p, ne=ne, nq=(nq,) * dim)
+    tab = inputs.uniform_table(inputs.gauss_shape(ne, (nq,) * dim), seed=43)
+    got = host(mesh.rhs(iga.PG, None, gamma=1.0, f_table=cuda(tab)))
+    assert relerr(got, orc.rhs(pb, orc.PG, None, gamma=1.0, f_table=tab)) <= TOL, (p, nq, ne)
+    mesh.close()
+
+
 @pytest.mark.parametrize("dim,p,ne", [(1, 2, (500,)), (2, 3, (40, 31)), (3, 3, (20, 17, 23)),
                                       (3, 2, (16, 16, 16))])
 @pytest.mark.parametrize("nsteps", [1, 2, 5])
