@@ -226,8 +226,11 @@ if __name__ == "__main__":
         print(json.dumps(pmc_markdown(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:]), indent=1))
     elif sys.argv[1] == "stats":
         stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else "")
-    elif sys.argv[1] == "grid":
-        grid_table(sys.argv[2], sys.argv[3])
+    elif sys.argv[1] == "grid":   # grid TRACE_CSV OUT_CSV [comma-separated name parts to keep]
+        if len(sys.argv) > 4:
+            grid_table(sys.argv[2], sys.argv[3], tuple(sys.argv[4].split(",")))
+        else:
+            grid_table(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),
                                  sys.argv[6], sys.argv[7]), indent=1))
