@@ -95,31 +95,43 @@ __global__ __launch_bounds__(kBlock) void pg_src_elem_vec_kernel(SrcArgs s, size
     double acc[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) acc[j] = 0.0;
-    for (int qz = 0; qz < Z.nq; ++qz) {
-#pragma unroll 4
-        for (int qy = 0; qy < Y.nq; ++qy) {
-            const double wyz = Z.gw[qz] * Y.gw[qy];
-            const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + (size_t)ex0 * NQ;
-            double v[E * NQ];
-            if (full) {
+    auto plane_row = [&](int qz, int qy) {
+        const double wyz = Z.gw[qz] * Y.gw[qy];
+        const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx + (size_t)ex0 * NQ;
+        double v[E * NQ];
+        if (full) {
 #pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const src_pair pr = *reinterpret_cast<const src_pair*>(row + 2 * k);
-                    v[2 * k] = pr.x;
-                    v[2 * k + 1] = pr.y;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < E * NQ; ++k) v[k] = k < NQ ? row[k] : 0.0;
+            for (int k = 0; k < V; ++k) {
+                const src_pair pr = *reinterpret_cast<const src_pair*>(row + 2 * k);
+                v[2 * k] = pr.x;
+                v[2 * k + 1] = pr.y;
             }
+        } else {
 #pragma unroll
-            for (int j = 0; j < E; ++j) {
-                double tt = 0.0;
-#pragma unroll
-                for (int qx = 0; qx < NQ; ++qx) tt = fma(w[qx], v[j * NQ + qx], tt);
-                acc[j] = fma(wyz, tt, acc[j]);
-            }
+            for (int k = 0; k < E * NQ; ++k) v[k] = k < NQ ? row[k] : 0.0;
         }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            double tt = 0.0;
+#pragma unroll
+            for (int qx = 0; qx < NQ; ++qx) tt = fma(w[qx], v[j * NQ + qx], tt);
+            acc[j] = fma(wyz, tt, acc[j]);
+        }
+    };
+    // the rows in (qz, qy) order; with the rule of x on y (and z) the loops have
+    // compile-time bounds, so the loads of a whole element are issued together
+    if (Y.nq == NQ && Z.nq == NQ) {
+#pragma unroll
+        for (int qz = 0; qz < NQ; ++qz)
+#pragma unroll
+            for (int qy = 0; qy < NQ; ++qy) plane_row(qz, qy);
+    } else if (Y.nq == NQ && Z.nq == 1) {
+#pragma unroll
+        for (int qy = 0; qy < NQ; ++qy) plane_row(0, qy);
+    } else {
+        for (int qz = 0; qz < Z.nq; ++qz)
+#pragma unroll 4
+            for (int qy = 0; qy < Y.nq; ++qy) plane_row(qz, qy);
     }
     const size_t e0 = ((size_t)ez * Y.ne + ey) * X.ne + ex0;
     s.elem[e0] = acc[0];
@@ -161,34 +173,44 @@ __global__ __launch_bounds__(kBlock) void pg_src_elem_x_kernel(SrcArgs s, double
     double acc[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) acc[j] = 0.0;
-    if (ok[0] || ok[E - 1]) {
-        for (int qz = 0; qz < Z.nq; ++qz) {
-#pragma unroll 4
-            for (int qy = 0; qy < Y.nq; ++qy) {
-                const double wyz = Z.gw[qz] * Y.gw[qy];
-                const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx;
-                double v[E * NQ];
-                if (full) {
+    auto plane_row = [&](int qz, int qy) {
+        const double wyz = Z.gw[qz] * Y.gw[qy];
+        const double* row = s.table + ((gz0 + qz) * ngy + gy0 + qy) * ngx;
+        double v[E * NQ];
+        if (full) {
 #pragma unroll
-                    for (int k = 0; k < NQ; ++k) {
-                        const src_pair pr = *reinterpret_cast<const src_pair*>(row + (size_t)e0 * NQ + 2 * k);
-                        v[2 * k] = pr.x;
-                        v[2 * k + 1] = pr.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < E; ++j)
-#pragma unroll
-                        for (int k = 0; k < NQ; ++k) v[j * NQ + k] = ok[j] ? row[(size_t)(e0 + j) * NQ + k] : 0.0;
-                }
-#pragma unroll
-                for (int j = 0; j < E; ++j) {
-                    double tt = 0.0;
-#pragma unroll
-                    for (int qx = 0; qx < NQ; ++qx) tt = fma(wx[qx], v[j * NQ + qx], tt);
-                    acc[j] = fma(wyz, tt, acc[j]);
-                }
+            for (int k = 0; k < NQ; ++k) {
+                const src_pair pr = *reinterpret_cast<const src_pair*>(row + (size_t)e0 * NQ + 2 * k);
+                v[2 * k] = pr.x;
+                v[2 * k + 1] = pr.y;
             }
+        } else {
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+#pragma unroll
+                for (int k = 0; k < NQ; ++k) v[j * NQ + k] = ok[j] ? row[(size_t)(e0 + j) * NQ + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            double tt = 0.0;
+#pragma unroll
+            for (int qx = 0; qx < NQ; ++qx) tt = fma(wx[qx], v[j * NQ + qx], tt);
+            acc[j] = fma(wyz, tt, acc[j]);
+        }
+    };
+    if (ok[0] || ok[E - 1]) {   // the rows in (qz, qy) order, compile-time bounds where the rules allow
+        if (Y.nq == NQ && Z.nq == NQ) {
+#pragma unroll
+            for (int qz = 0; qz < NQ; ++qz)
+#pragma unroll
+                for (int qy = 0; qy < NQ; ++qy) plane_row(qz, qy);
+        } else if (Y.nq == NQ && Z.nq == 1) {
+#pragma unroll
+            for (int qy = 0; qy < NQ; ++qy) plane_row(0, qy);
+        } else {
+            for (int qz = 0; qz < Z.nq; ++qz)
+#pragma unroll 4
+                for (int qy = 0; qy < Y.nq; ++qy) plane_row(qz, qy);
         }
     }
     // the values of this lane and the next K-1: element e0 + o at nb[o]
