@@ -215,7 +215,9 @@ struct Chunk2D {
 
 // One chunk: strip bx (output columns 128 bx ..) and rows TY by .. of one problem.
 // lds: Chunk2D<P, TY>::LDS doubles, 16-byte aligned, private to the calling wave.
-template <int P, int TY, int MODE, bool VEC>
+// DMA: even rows at even P load straight into LDS (below); the persistent batch kernel
+// keeps the register path, which measured faster there.
+template <int P, int TY, int MODE, bool VEC, bool DMA = false>
 __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by, double* lds)
 {
     using C = Chunk2D<P, TY>;
@@ -251,7 +253,7 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     // offset of the table that holds value k (the others read 0 out of bounds)
     // kDma (below): the band rows are stored after the input rows are issued, so that no
     // load waits for another
-    constexpr bool kDma = VEC && (P % 2) == 0;
+    constexpr bool kDma = DMA && VEC && (P % 2) == 0;
     double cv[NCV];
     {
         const auto rym = buf(Y.M, (size_t)Y.R * W), ryd = buf(Y.D, (size_t)Y.R * W);
@@ -542,7 +544,7 @@ __global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
     const int L = tg.TZ == 2 ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, tg.nblk);
     const int bx = tg.TZ == 1 ? L / tg.ty : L % tg.tx;
     const int by = tg.TZ == 1 ? L % tg.ty : L / tg.tx;
-    apply2d_chunk<P, TY, MODE, VEC>(g, bx, by, lds);
+    apply2d_chunk<P, TY, MODE, VEC, true>(g, bx, by, lds);
 }
 
 // Rows without a u-term: out_r = S(r) ( gsep prod_a F_a(r_a) + garr farr_r ).
