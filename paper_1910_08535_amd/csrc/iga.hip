@@ -425,6 +425,14 @@ int launch_rows_only(const iga_ctx* c, const ApplyArgs& g, size_t n, hipStream_t
     return IGA_OK;
 }
 
+// Galerkin sources contract axis by axis when every axis has 2 to 4 Gauss points.
+bool gal_axes_ok(const iga_ctx* c)
+{
+    for (int a = 0; a < c->dim; ++a)
+        if (c->t[a].nq < 2 || c->t[a].nq > 4) return false;
+    return c->p == 2 || c->p == 3;
+}
+
 // Doubles of c->elem that the rows of a Gauss-table source need.  Galerkin: the element
 // results, np1^d per element.  PG: [A | B] with A = max(elements, ne_z R_y R_x) (the
 // element sums, then the y-pass sums of a 3D mesh) and B = ne_z ne_y R_x (the x-pass
@@ -436,7 +444,14 @@ size_t src_scratch_doubles(const iga_ctx* c, int form)
         nel *= (size_t)c->t[a].ne;
         np1 *= (size_t)(c->t[a].p + 1);
     }
-    if (form != IGA_PG) return nel * np1;
+    if (form != IGA_PG) {   // the per-element path, or the axis contractions [G1 | G2]
+        const AxisTables& X = c->t[0];
+        size_t lines = 1;
+        for (int a = 1; a < c->dim; ++a) lines *= (size_t)c->t[a].ne * c->t[a].nq;
+        size_t g = c->dim >= 2 ? lines * X.N : 0;
+        if (c->dim == 3) g += (size_t)c->t[2].ne * c->t[2].nq * c->t[1].N * X.N;
+        return std::max(nel * np1, g);
+    }
     size_t A = nel, B = 0;
     if (c->dim >= 2) B = nel / (size_t)c->t[0].ne * (size_t)c->t[0].R;
     if (c->dim == 3) A = std::max(A, (size_t)c->t[2].ne * c->t[1].R * c->t[0].R);
@@ -535,6 +550,50 @@ int source_rows(iga_ctx* c, int form, const double* table, hipStream_t s)
                                    x.first, x.last, x.ne, x.R, inner, total);
             in = out;
             inner *= (size_t)x.R;
+        }
+    } else if (gal_axes_ok(c)) {
+        // Galerkin: contract the Gauss grid along x (from the table), then y, then z
+        const iga::SrcAxis &X = sa.ax[0], &Y = sa.ax[1], &Z = sa.ax[2];
+        const size_t lines = (size_t)Y.ne * Y.nq * Z.ne * Z.nq;
+        double* const g1 = c->dim == 1 ? c->farr : c->elem;
+        double* const g2 = c->elem + (c->dim >= 2 ? lines * X.R : 0);
+        {
+            const int S = 64 - c->p;
+            const int wpl = (X.R + S - 1) / S;
+            const size_t nw = (size_t)wpl * lines;
+            const dim3 gx((unsigned)((nw * 64 + kBlock - 1) / kBlock));
+#define IGA_GAL_X(P, NQ) hipLaunchKernelGGL((iga::gal_src_x_kernel<P, NQ>), gx, dim3(kBlock), 0, s, sa, g1, wpl, nw)
+            if (c->p == 2) {
+                if (X.nq == 2) IGA_GAL_X(2, 2); else if (X.nq == 3) IGA_GAL_X(2, 3); else IGA_GAL_X(2, 4);
+            } else {
+                if (X.nq == 2) IGA_GAL_X(3, 2); else if (X.nq == 3) IGA_GAL_X(3, 3); else IGA_GAL_X(3, 4);
+            }
+#undef IGA_GAL_X
+        }
+        auto axis = [&](const iga::SrcAxis& A, const double* in, double* out, size_t outer, size_t inner) {
+            const size_t total = outer * (size_t)A.R * inner;
+            const dim3 gb((unsigned)((total + kBlock - 1) / kBlock));
+            const bool small = std::max(total, outer * (size_t)A.ne * A.nq * inner) < ((size_t)1 << 32);
+#define IGA_GAL_AX(P, NQ)                                                                                          \
+    do {                                                                                                           \
+        if (small)                                                                                                 \
+            hipLaunchKernelGGL((iga::gal_src_axis_kernel<P, NQ, unsigned>), gb, dim3(kBlock), 0, s, in, out, A,     \
+                               (unsigned)inner, (unsigned)total);                                                  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((iga::gal_src_axis_kernel<P, NQ, size_t>), gb, dim3(kBlock), 0, s, in, out, A, inner, \
+                               total);                                                                             \
+    } while (0)
+            if (c->p == 2) {
+                if (A.nq == 2) IGA_GAL_AX(2, 2); else if (A.nq == 3) IGA_GAL_AX(2, 3); else IGA_GAL_AX(2, 4);
+            } else {
+                if (A.nq == 2) IGA_GAL_AX(3, 2); else if (A.nq == 3) IGA_GAL_AX(3, 3); else IGA_GAL_AX(3, 4);
+            }
+#undef IGA_GAL_AX
+        };
+        if (c->dim == 2) axis(Y, g1, c->farr, 1, X.R);
+        if (c->dim == 3) {
+            axis(Y, g1, g2, (size_t)Z.ne * Z.nq, X.R);
+            axis(Z, g2, c->farr, 1, (size_t)Y.R * X.R);
         }
     } else {
         // the common rules (x and y alike) with their table values loaded a plane at a time

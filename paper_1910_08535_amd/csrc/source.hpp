@@ -374,6 +374,115 @@ __global__ __launch_bounds__(kBlock) void gal_src_elem_kernel(SrcArgs s, size_t 
                 if (az < nz && ay < ny && ax < nx) s.elem[(size_t)((az * ny + ay) * nx + ax) * nel + idx] = acc[az][ay][ax];
 }
 
+// Galerkin rows by contracting the Gauss grid one axis at a time (x, then y, then z):
+//   out[o][i][k] = sum_{a=0}^{P} [e = i - a in [0, ne)] sum_{q<NQ} W_q B_{e,a}(x_q) in[o][e NQ + q][k]
+// where B_{e,a} is local function a of element e, so B_{e,a} = B_i; after the three axes
+// out = F_i = sum_e sum_q W_q B_i(x_q) f_q.  Each Gauss value is read once (no per-element
+// array of (p+1)^d values), and the weighted basis values of the axis' element classes
+// are staged in LDS per workgroup.  Used when every axis has 2 to 4 Gauss points.
+template <int P, int NQ>
+__device__ __forceinline__ const double* gal_stage_axis(const SrcAxis& A, double* wt)
+{
+    constexpr int Q = P + 1;
+    const int n = n_classes(A.p, A.ne) * NQ * Q;
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+        const int a = i % Q, q = (i / Q) % NQ, c = i / (Q * NQ);
+        wt[i] = A.gw[q] * A.cls[(((size_t)c * NQ + q) * 3) * Q + a];
+    }
+    __syncthreads();
+    return wt;
+}
+
+// The x contraction, straight from the table: a lane forms the P+1 local sums of one
+// element (t[a] = sum_q W_q B_{e,a} f_q, its NQ values read once) and row i takes
+// t_{i-a}[a] from the lane a places to its left (cross-lane shuffles); the waves of a
+// Gauss-point row (line = gz ngy + gy) overlap by P elements.  out[line][i], i < N_x.
+template <int P, int NQ>
+__global__ __launch_bounds__(kBlock) void gal_src_x_kernel(SrcArgs s, double* __restrict__ out, int wpl,
+                                                           size_t nwaves)
+{
+    constexpr int Q = P + 1, S = 64 - P;
+    __shared__ double wt[(2 * kMaxP + 1) * kMaxNq * (kMaxP + 1)];
+    const SrcAxis& X = s.ax[0];
+    const double* const w = gal_stage_axis<P, NQ>(X, wt);
+    const size_t gw = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (gw >= nwaves) return;   // whole waves
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = (int)(gw % (size_t)wpl);
+    const size_t line = gw / (size_t)wpl;
+    const int e = wv * S - P + lane;
+    const bool ok = e >= 0 && e < X.ne;
+    double t[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) t[a] = 0.0;
+    if (ok) {
+        const double* row = s.table + line * (size_t)X.ne * NQ + (size_t)e * NQ;
+        double f[NQ];
+        if constexpr ((NQ & 1) == 0) {
+#pragma unroll
+            for (int k = 0; k < NQ / 2; ++k) {
+                const src_pair pr = *reinterpret_cast<const src_pair*>(row + 2 * k);
+                f[2 * k] = pr.x;
+                f[2 * k + 1] = pr.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) f[q] = row[q];
+        }
+        const double* wc = w + (size_t)class_of(e, X.p, X.ne) * NQ * Q;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int a = 0; a < Q; ++a) t[a] = fma(wc[q * Q + a], f[q], t[a]);
+    }
+    double nb[Q];   // nb[a] = t[a] of the lane a places to the left (element e - a)
+#pragma unroll
+    for (int a = 0; a < Q; ++a) nb[a] = a == 0 ? t[0] : __shfl_up(t[a], (unsigned)a);
+    const int i = e;   // the row of this lane: lanes P .. 63 hold rows wv S .. wv S + S - 1
+    if (lane < P || i >= X.R) return;
+    double sum = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+        if (i - a >= 0 && i - a < X.ne) sum += nb[a];
+    out[line * (size_t)X.R + i] = sum;
+}
+
+// The y or z contraction of an array (outer, ne NQ, ninner) into (outer, N, ninner): one
+// thread per output, all (P+1) NQ loads issued before the sums (in the order a, q).
+template <int P, int NQ, typename I>
+__global__ __launch_bounds__(kBlock) void gal_src_axis_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                              SrcAxis A, I ninner, I total)
+{
+    constexpr int Q = P + 1;
+    __shared__ double wt[(2 * kMaxP + 1) * kMaxNq * (kMaxP + 1)];
+    const double* const w = gal_stage_axis<P, NQ>(A, wt);
+    const I idx = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+    if (idx >= total) return;
+    const I k = idx % ninner, t = idx / ninner;
+    const I i = t % (I)A.R, o = t / (I)A.R;
+    const double* src = in + ((size_t)o * A.ne * NQ) * (size_t)ninner + k;
+    double v[Q][NQ];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const int e = (int)i - a;
+        const bool ok = e >= 0 && e < A.ne;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[a][q] = ok ? src[((size_t)e * NQ + q) * ninner] : 0.0;
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const int e = (int)i - a;
+        if (e < 0 || e >= A.ne) continue;
+        const double* wc = w + (size_t)class_of(e, A.p, A.ne) * NQ * Q;
+        double ta = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ta = fma(wc[q * Q + a], v[a][q], ta);
+        sum += ta;
+    }
+    out[idx] = sum;
+}
+
 // Galerkin step 2: F_i = sum over the elements e = i - a (a local index per axis), the
 // terms in the order (az, ay, ax); all loads of a row are issued before the sums.
 // P: the degree of the mesh (axes beyond dim have one local function).
