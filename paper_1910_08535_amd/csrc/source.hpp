@@ -456,7 +456,9 @@ __global__ __launch_bounds__(kBlock) void gal_src_axis_kernel(const double* __re
     constexpr int Q = P + 1;
     __shared__ double wt[(2 * kMaxP + 1) * kMaxNq * (kMaxP + 1)];
     const double* const w = gal_stage_axis<P, NQ>(A, wt);
-    const I idx = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+    // XCD-aware block numbering: neighbouring rows read overlapping Gauss rows from one L2
+    const I blk = (I)xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
+    const I idx = blk * (I)blockDim.x + (I)threadIdx.x;
     if (idx >= total) return;
     const I k = idx % ninner, t = idx / ninner;
     const I i = t % (I)A.R, o = t / (I)A.R;
