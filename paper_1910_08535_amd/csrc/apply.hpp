@@ -137,6 +137,10 @@ __global__ __launch_bounds__(kBlock) void apply1d_gen_kernel(ApplyArgs g, const 
 typedef int iv2 __attribute__((ext_vector_type(2)));
 constexpr unsigned kOOB = 0xffffffffu;
 
+// Loads through the constant address space: with a wave-uniform address the compiler
+// issues scalar loads.
+typedef const __attribute__((address_space(4))) double* cdp;
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void* p, size_t n_doubles)
 {
     const size_t bytes = n_doubles * sizeof(double);
@@ -234,12 +238,23 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     const int xr0 = c0, xr1 = c0 + 1;
     const auto rxm = buf(X.M, (size_t)X.R * W), rxd = buf(X.D, (size_t)X.R * W);
     double m0[W], d0[W], m1[W], d1[W];
+    if (x0 >= X.ilo && x0 + SW - 1 <= X.ihi) {
+        // every column of the strip is interior: one row for all lanes, read with uniform
+        // (scalar) loads instead of 4W vector loads per lane
+        const cdp um = (cdp)(X.M + (size_t)X.ilo * W), ud = (cdp)(X.D + (size_t)X.ilo * W);
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        m0[k] = bload(rxm, xr0 < X.R ? (unsigned)(xr0 * W + k) * 8u : kOOB);
-        d0[k] = bload(rxd, xr0 < X.R ? (unsigned)(xr0 * W + k) * 8u : kOOB);
-        m1[k] = bload(rxm, xr1 < X.R ? (unsigned)(xr1 * W + k) * 8u : kOOB);
-        d1[k] = bload(rxd, xr1 < X.R ? (unsigned)(xr1 * W + k) * 8u : kOOB);
+        for (int k = 0; k < W; ++k) {
+            m0[k] = m1[k] = um[k];
+            d0[k] = d1[k] = ud[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            m0[k] = bload(rxm, xr0 < X.R ? (unsigned)(xr0 * W + k) * 8u : kOOB);
+            d0[k] = bload(rxd, xr0 < X.R ? (unsigned)(xr0 * W + k) * 8u : kOOB);
+            m1[k] = bload(rxm, xr1 < X.R ? (unsigned)(xr1 * W + k) * 8u : kOOB);
+            d1[k] = bload(rxd, xr1 < X.R ? (unsigned)(xr1 * W + k) * 8u : kOOB);
+        }
     }
     double sx0 = 1.0, sx1 = 1.0, fx0 = 1.0, fx1 = 1.0;
     if constexpr ((MODE & kScaleSrc) != 0) {
@@ -435,10 +450,19 @@ __device__ __forceinline__ void apply2d_chunk1(const ApplyArgs& g, int bx, int b
     const int c0 = x0 + lane;
     const auto rxm = buf(X.M, (size_t)X.R * W), rxd = buf(X.D, (size_t)X.R * W);
     double m0[W], d0[W];
+    if (x0 >= X.ilo && x0 + SW - 1 <= X.ihi) {   // interior strip: one row, uniform loads
+        const cdp um = (cdp)(X.M + (size_t)X.ilo * W), ud = (cdp)(X.D + (size_t)X.ilo * W);
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        m0[k] = bload(rxm, c0 < X.R ? (unsigned)(c0 * W + k) * 8u : kOOB);
-        d0[k] = bload(rxd, c0 < X.R ? (unsigned)(c0 * W + k) * 8u : kOOB);
+        for (int k = 0; k < W; ++k) {
+            m0[k] = um[k];
+            d0[k] = ud[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            m0[k] = bload(rxm, c0 < X.R ? (unsigned)(c0 * W + k) * 8u : kOOB);
+            d0[k] = bload(rxd, c0 < X.R ? (unsigned)(c0 * W + k) * 8u : kOOB);
+        }
     }
     double sx0 = 1.0, fx0 = 1.0;
     if constexpr ((MODE & kScaleSrc) != 0) {

@@ -105,16 +105,16 @@ __device__ __forceinline__ void lds_taps(double (&m)[W], double (&d)[W], const d
     }
 }
 
-// Loads through the constant address space: with a uniform address the compiler issues
-// scalar loads, and the taps then occupy scalar registers instead of vector ones.
-typedef const __attribute__((address_space(4))) double* cdptr;
+// Loads through the constant address space (cdp, apply.hpp): with a uniform address the
+// compiler issues scalar loads, and the taps then occupy scalar registers instead of
+// vector ones.
 
 template <int W>
 __device__ __forceinline__ void uniform_row(double (&m)[W], double (&d)[W], const double* M,
                                             const double* D, int row)
 {
-    const cdptr pm = (cdptr)(M + (size_t)row * W);
-    const cdptr pd = (cdptr)(D + (size_t)row * W);
+    const cdp pm = (cdp)(M + (size_t)row * W);
+    const cdp pd = (cdp)(D + (size_t)row * W);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         m[k] = pm[k];
@@ -456,7 +456,7 @@ __device__ __forceinline__ void apply3d_tile(const ApplyArgs& g, const Plan3D& p
             const bool live = k >= 2;
             const int oz = max(z0 + k - 2, 0);
             // uniform scalar loads of the plane's scale and source factors
-            const double sz = ((cdptr)Z.S)[oz], fz = ((cdptr)Z.F)[oz];
+            const double sz = ((cdp)Z.S)[oz], fz = ((cdp)Z.F)[oz];
             const size_t pb = live ? (size_t)oz * oplane : 0;
             const size_t pn = live ? oplane : 0;
             const auto ro = buf(g.out + pb, pn);
