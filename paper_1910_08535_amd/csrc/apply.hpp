@@ -220,8 +220,10 @@ struct Chunk2D {
 // One chunk: strip bx (output columns 128 bx ..) and rows TY by .. of one problem.
 // lds: Chunk2D<P, TY>::LDS doubles, 16-byte aligned, private to the calling wave.
 // DMA: even rows at even P load straight into LDS (below); the persistent batch kernel
-// keeps the register path, which measured faster there.
-template <int P, int TY, int MODE, bool VEC, bool DMA = false>
+// keeps the register path, which measured faster there.  YIN: every output row of the
+// chunk is interior, so the y taps are one row for all of them, read with uniform loads
+// (the chunk's band rows are then staged only when the step's S and F factors need them).
+template <int P, int TY, int MODE, bool VEC, bool DMA = false, bool YIN = false>
 __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by, double* lds)
 {
     using C = Chunk2D<P, TY>;
@@ -269,8 +271,9 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     // kDma (below): the band rows are stored after the input rows are issued, so that no
     // load waits for another
     constexpr bool kDma = DMA && VEC && (P % 2) == 0;
+    constexpr bool kCy = !YIN || (MODE & kScaleSrc) != 0;   // the chunk's band rows are read
     double cv[NCV];
-    {
+    if constexpr (kCy) {
         const auto rym = buf(Y.M, (size_t)Y.R * W), ryd = buf(Y.D, (size_t)Y.R * W);
         const auto rys = buf(Y.S, Y.R), ryf = buf(Y.F, Y.R);
 #pragma unroll
@@ -332,9 +335,20 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
     const auto rf = buf(g.farr, (MODE & kFarr) ? (size_t)X.R * Y.R : 0);
     const bool okc0 = xr0 < X.R, okc1 = xr1 < X.R;
     double ra0[W], rb0[W], ra1[W], rb1[W];
-    if constexpr (kDma) {
+    double ymu[W], ydu[W];   // YIN: every row of the chunk interior, one row of y taps
+    if constexpr (YIN) {
+        const cdp um = (cdp)(Y.M + (size_t)Y.ilo * W), ud = (cdp)(Y.D + (size_t)Y.ilo * W);
 #pragma unroll
-        for (int c = 0; c < NCV; ++c) cy[lane + 64 * c] = cv[c];
+        for (int k = 0; k < W; ++k) {
+            ymu[k] = um[k];
+            ydu[k] = ud[k];
+        }
+    }
+    if constexpr (kDma) {
+        if constexpr (kCy) {
+#pragma unroll
+            for (int c = 0; c < NCV; ++c) cy[lane + 64 * c] = cv[c];
+        }
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): every row is in LDS
     }
 #pragma unroll
@@ -371,7 +385,14 @@ __device__ __forceinline__ void apply2d_chunk(const ApplyArgs& g, int bx, int by
             double ms0 = 0.0, ly0 = 0.0, lx0 = 0.0, ms1 = 0.0, ly1 = 0.0, lx1 = 0.0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-                const double my = cr[k], dy = cr[W + k];
+                double my, dy;
+                if constexpr (YIN) {
+                    my = ymu[k];
+                    dy = ydu[k];
+                } else {
+                    my = cr[k];
+                    dy = cr[W + k];
+                }
                 const int sl = (j + k) % W;
                 ms0 = fma(my, ra0[sl], ms0);
                 ly0 = fma(dy, ra0[sl], ly0);
@@ -568,7 +589,10 @@ __global__ __launch_bounds__(64) void apply2d_kernel(ApplyArgs g, TileGrid tg)
     const int L = tg.TZ == 2 ? (int)blockIdx.x : xcd_logical_block(blockIdx.x, tg.nblk);
     const int bx = tg.TZ == 1 ? L / tg.ty : L % tg.tx;
     const int by = tg.TZ == 1 ? L % tg.ty : L / tg.tx;
-    apply2d_chunk<P, TY, MODE, VEC, true>(g, bx, by, lds);
+    if (by * TY >= g.ax[1].ilo && by * TY + TY - 1 <= g.ax[1].ihi)   // rows all interior
+        apply2d_chunk<P, TY, MODE, VEC, true, true>(g, bx, by, lds);
+    else
+        apply2d_chunk<P, TY, MODE, VEC, true, false>(g, bx, by, lds);
 }
 
 // Rows without a u-term: out_r = S(r) ( gsep prod_a F_a(r_a) + garr farr_r ).
