@@ -52,19 +52,19 @@ def copy_probe(mib: int) -> None:
 
 
 def measured_traffic(workload: str, kernel: str = None):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources (and on the named kernel); else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
-    try:
+    """HBM bytes per launch from a committed rocprofv3 counter summary of the workload
+    (profiles/traffic_<workload>*.json: one per tile that was profiled) taken on the
+    current kernel sources and on the named kernel; else None."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_{workload}*.json"))):
         with open(path) as fh:
             rec = json.load(fh)
-    except OSError:
-        return None
-    if rec.get("kernel_source_hash") != kernel_source_hash(rec.get("family", "apply2d")):
-        return None
-    if kernel is not None and kernel not in rec.get("kernel", ""):
-        return None
-    return rec.get("bytes_per_launch")
+        if rec.get("kernel_source_hash") != kernel_source_hash(rec.get("family", "apply2d")):
+            continue
+        if kernel is not None and kernel not in rec.get("kernel", ""):
+            continue
+        return rec.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(args) -> dict:
